@@ -1,0 +1,135 @@
+"""Pins of the Softmax oracle: the definition's special cases, the
+doubling identity, the Cauchy-Schwarz bound, the exact twins of the paper's
+loops, the packing, the precision theorem's bound under fixed-point noise,
+and the polynomial approximations' own optimality conditions."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import softmax as S
+from oracle import polyfit as P
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_softmax_special_cases():
+    n = 64
+    assert np.allclose(S.softmax(np.full((3, n), -7.0)), 1.0 / n, rtol=0, atol=1e-16)
+    M = 30.0
+    x = np.full(n, -M)
+    x[5] = 0.0
+    y = S.softmax(x[None])[0]
+    assert abs(y[5] - 1.0 / (1.0 + (n - 1) * math.exp(-M))) < 2e-15
+    a, b = -1.25, -4.0
+    y = S.softmax(np.array([[a, b]]))[0]
+    assert abs(y[0] - 1.0 / (1.0 + math.exp(b - a))) < 2e-15
+    # shift invariance (Eq. eq:normalized_sm)
+    x = np.random.default_rng(0).uniform(-9, 0, (4, 32))
+    assert np.allclose(S.softmax(x), S.softmax(x - 3.5), atol=1e-15)
+
+
+def test_doubling_identity_and_cauchy_schwarz():
+    x = np.random.default_rng(1).uniform(-128, 0, (20, 256))
+    for j in range(0, 8):
+        y = S.softmax(x / 2 ** j)
+        s2 = (y * y).sum(-1)
+        assert np.all(s2 >= 1 / 256 - 1e-15) and np.all(s2 <= 1 + 1e-15)
+        if j > 0:
+            assert np.allclose(S.softmax(x / 2 ** (j - 1)), y * y / s2[:, None], atol=1e-14)
+
+
+@pytest.mark.parametrize("n,M", [(16, 8.0), (256, 128.0), (128, 64.0), (1024, 256.0)])
+def test_exact_twins_equal_softmax(n, M):
+    x = np.random.default_rng(n).uniform(-M, 0, (8, n))
+    ref = S.softmax(x)
+    for k in (S.theorem_k(n, M), S.table_k(M)):
+        assert np.max(np.abs(S.main_loop(x, k) - ref)) < 1e-12
+        assert np.max(np.abs(S.softmax_b(x, k) - ref)) < 1e-12
+        assert np.allclose(S.main_loop(x, k).sum(-1), 1.0, atol=1e-12)
+
+
+def test_k_rules():
+    # Theorem: k = ceil(log M - log ln n); tables: range [-2^k, 0]
+    assert [S.theorem_k(n, M) for n, M in [(16, 8), (256, 128), (128, 64), (32768, 256)]] == [2, 5, 4, 5]
+    assert [S.table_k(M) for M in (8, 128, 64, 256)] == [3, 7, 6, 8]
+
+
+@pytest.mark.parametrize("m", [1, 4, 64])
+def test_packed_twin(m):
+    n, slots = 256, 1 << 12
+    L = m * slots // n
+    x = np.random.default_rng(m).uniform(-128, 0, (L, n))
+    packed = S.pack(x, m, slots)
+    assert np.array_equal(S.unpack(packed, n), x)
+    for variant in ("SM", "B"):
+        y = S.unpack(S.sm_packed(packed, n, 5, variant=variant), n)
+        assert np.max(np.abs(y - S.softmax(x))) < 1e-12
+    with pytest.raises(ValueError):
+        S.pack(x[:, :255], m, slots)
+
+
+def test_theorem_bound_under_fixed_point_noise():
+    n, M, p = 16, 8.0, 40
+    k = S.theorem_k(n, M)
+    bound, premise = S.theorem_bound(n, k, p)
+    assert premise
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-M, 0, (2000, n))
+    eps = 2.0 ** -p
+    exp_noisy = lambda t: np.exp(t) + rng.uniform(-eps, eps, t.shape)
+    inv_noisy = [lambda s: s ** -0.5 + rng.uniform(-eps, eps, s.shape)] * k
+    y = S.main_loop(x, k, exp_noisy, inv_noisy, rng=rng, eps=eps)
+    err = np.max(np.abs(y - S.softmax(x)))
+    assert err <= bound
+    # heuristic loss of about log M + 1.5 log n bits (Section 3.2)
+    assert -math.log2(err) >= p - (math.log2(M) + 1.5 * math.log2(n)) - 2
+
+
+def test_precision_metrics():
+    ref = np.zeros((4, 2))
+    y = np.array([[2 ** -10, 0], [0, 2 ** -12], [2 ** -20, 0], [2 ** -16, 0]])
+    r = S.precision_bits(ref, y)
+    assert r["worst"] == 10
+    assert abs(r["mean"] + math.log2(np.mean([2 ** -10, 2 ** -12, 2 ** -20, 2 ** -16]))) < 1e-12
+    assert abs(r["std"] - np.std([-10, -12, -20, -16])) < 1e-12
+
+
+def test_paper_depth_tables_are_self_consistent():
+    t = json.load(open(os.path.join(GOLD, "paper_tables.json")))
+    for row in t["tab_depth_aux_thread"]["rows"]:
+        first, mid, last = row["invsqrt_depths"]
+        a, b = row["total"].split("k")
+        a = int(a)
+        b = int(b) if b else 0
+        for k in range(2, 9):
+            assert 2 * k + first + mid * (k - 2) + last == a * k + b
+    assert t["tab_SMmany"]["SM_B"][-1] == 414
+
+
+def test_remez_equioscillates():
+    a, b, d = 0.81 / 256, 1.21, 31
+    coef, err = P.remez(lambda x: x ** -0.5, lambda x: x ** 0.5, a, b, d)
+    g = np.linspace(a, b, 200001)
+    E = P.cheb_eval(coef, g, a, b) * np.sqrt(g) - 1
+    assert abs(np.max(np.abs(E)) - err) < 1e-3 * err
+    # d + 2 alternating extrema of (nearly) equal size
+    s = np.sign(E)
+    runs = 1 + np.count_nonzero(s[1:] != s[:-1])
+    assert runs >= d + 2
+    # minimax beats interpolation
+    ci = P.cheb_interp(lambda x: x ** -0.5, a, b, d)
+    Ei = P.cheb_eval(ci, g, a, b) * np.sqrt(g) - 1
+    assert np.max(np.abs(Ei)) > err
+
+
+def test_cheb_interp_reproduces_polynomials():
+    c = np.array([0.5, -1.0, 0.25, 2.0])
+    f = lambda x: P.cheb_eval(c, x, -3.0, 1.0)
+    assert np.allclose(P.cheb_interp(f, -3.0, 1.0, 3), c, atol=1e-13)
+    # exponential: error below 2^-40 with degree 15 on [-128, 0] for k = 5
+    e = P.exp_table(128.0, 5, 15)
+    g = np.linspace(-128, 0, 10001)
+    assert np.max(np.abs(P.cheb_eval(e, g, -128.0, 0.0) - np.exp(g / 32))) < 2 ** -40
