@@ -1,0 +1,178 @@
+/*
+ * hs.h -- C ABI of the MI355X homomorphic Softmax library.
+ *
+ * The library evaluates Softmax on RNS-CKKS ciphertexts by the
+ * normalize-and-square method of Cho, Hanrot, Kim, Park and Stehle, "Fast and
+ * Accurate Homomorphic Softmax Evaluation" (CCS'24): Algorithm "SM"
+ * (Section 3.2), the auxiliary thread (Algorithm "alg:AuxThread", Section
+ * 3.3), the many-ciphertext packing (Section 4.2) and version B (Algorithm
+ * "alg:Softmax1B", Section 4.3), on top of the CKKS functionality the paper
+ * lists in Section 2.2 ("Functionalities": KeyGen, Enc, Dec, Add, Mult, Rot)
+ * plus bootstrapping (Section 2.2, "Levels").
+ *
+ * Conventions for every entry point
+ *  - Return value: HS_OK (0) or a negative hs_status; the message of the
+ *    last failure on the calling thread is returned by hs_last_error().
+ *    Nothing throws across this interface.  On failure, output handles are
+ *    set to NULL and caller buffers are left in an unspecified state.
+ *  - Handles (hs_ctx, hs_ct) are created by the library and released with
+ *    the matching destroy call.  Input handles are borrowed; every hs_ct**
+ *    output is a new handle owned by the caller.
+ *  - Host arrays are caller-allocated and only read or written during the
+ *    call.  Device memory is owned by the context (its own caching pool).
+ *  - A context is bound to one device and one HIP stream and is not
+ *    thread-safe: calls on one context must not overlap.
+ *  - Slots: a ciphertext holds N/2 complex slots; slot j is the evaluation
+ *    of the message at zeta^(5^j mod 2N), zeta = exp(i pi / N).  Rotation by
+ *    r maps slot j to slot j - r (left rotation, Galois element 5^r mod 2N).
+ *  - Levels: level l means the primes q_0..q_l; multiplication lowers the
+ *    level by one (Section 2.2, "Levels").  Ciphertext residues are stored
+ *    in the negacyclic NTT domain, limb-major: [component][l+1][N] uint64.
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hs_status;
+#define HS_OK 0
+#define HS_E_ARG (-1)      /* bad argument (null pointer, size, index)        */
+#define HS_E_PARAM (-2)    /* unsupported or inconsistent parameter set        */
+#define HS_E_LEVEL (-3)    /* level exhausted or operands at unusable levels   */
+#define HS_E_SCALE (-4)    /* operands with different scales                   */
+#define HS_E_KEY (-5)      /* required key (relinearisation / Galois) missing  */
+#define HS_E_OOM (-6)      /* device allocation failed                         */
+#define HS_E_DEVICE (-7)   /* HIP runtime error                                */
+#define HS_E_RANGE (-8)    /* input outside the documented range               */
+#define HS_E_STATE (-9)    /* call out of order (e.g. no keys yet)             */
+
+typedef struct hs_ctx hs_ctx;
+typedef struct hs_ct hs_ct;
+
+/* Parameter set.  Primes are found by the rule: for a bit size b the
+ * candidates are 2^b + 1 + j 2N for j = 1, -1, 2, -2, ...; the chain takes,
+ * in the order q_0..q_{n_q-1} then p_0..p_{n_p-1}, the next unused prime of
+ * its size.  Key-switching digits are consecutive blocks of `digit` Q primes;
+ * a parameter set whose digit product exceeds P = prod p_k is rejected with
+ * HS_E_PARAM.  The bootstrapping fields are ignored when boot_cts_levels is
+ * 0; otherwise the top boot_cts_levels + boot_evalmod_levels +
+ * boot_stc_levels Q primes are reserved for bootstrapping and user_top must
+ * equal n_q - 1 minus that count. */
+typedef struct hs_params {
+    int log_n;            /* ring degree N = 2^log_n, 3 <= log_n <= 17        */
+    int n_q;              /* number of Q primes                                */
+    const int* q_bits;    /* [n_q] target bit sizes (20..61)                   */
+    int n_p;              /* number of special primes                          */
+    const int* p_bits;    /* [n_p]                                             */
+    int digit;            /* primes per key-switching digit                    */
+    int hamming;          /* secret Hamming weight; 0 = uniform ternary        */
+    double sigma;         /* discrete Gaussian parameter of the errors         */
+    int log_scale;        /* default scale 2^log_scale                         */
+    int user_top;         /* highest level handed to users                     */
+    int boot_cts_levels;  /* bootstrapping: coefficient-to-slot levels         */
+    int boot_evalmod_levels;
+    int boot_stc_levels;
+    int boot_K;           /* bound on |I| in the modular reduction             */
+    int boot_double_angle;/* number of double-angle steps                      */
+    int boot_cos_degree;  /* degree of the cosine approximation                */
+    int boot_log_scale;   /* internal scale of the modular reduction           */
+} hs_params;
+
+typedef struct hs_ctx_info {
+    int log_n, n, slots, n_q, n_p, top_level, user_top, dnum, digit, has_boot;
+} hs_ctx_info;
+
+/* Library version string (static storage). */
+const char* hs_version(void);
+/* Message of the last failure on this thread (static thread-local storage). */
+const char* hs_last_error(void);
+
+/* Create a context on HIP device `device`, issuing all work on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  Builds the NTT tables,
+ * base-conversion constants and encoding twiddles. */
+hs_status hs_ctx_create(const hs_params* p, int device, void* hip_stream, hs_ctx** out);
+void hs_ctx_destroy(hs_ctx* ctx);
+hs_status hs_ctx_get_info(const hs_ctx* ctx, hs_ctx_info* info);
+/* The primes, Q then P: writes min(cap, n_q + n_p) values, *n = n_q + n_p. */
+hs_status hs_ctx_primes(const hs_ctx* ctx, uint64_t* out, size_t cap, size_t* n);
+/* Block until all work issued on the context's stream has finished. */
+hs_status hs_sync(hs_ctx* ctx);
+
+/* KeyGen (Section 2.2): secret, public and relinearisation keys from one
+ * 64-bit seed (Philox4x32-10 draws; see DESIGN notes in the source). */
+hs_status hs_keygen(hs_ctx* ctx, uint64_t seed);
+/* Rotation keys for the given left-rotation steps (any sign, modulo N/2),
+ * and the conjugation key when conj != 0. */
+hs_status hs_add_rotation_keys(hs_ctx* ctx, const int32_t* steps, size_t n_steps, int conj);
+/* Key material export for testing: key id 0 = relinearisation, otherwise a
+ * Galois element.  Layout [dnum][2 (b, a)][n_q + n_p][N]. */
+hs_status hs_key_export(hs_ctx* ctx, int key_id, uint64_t* out, size_t cap, size_t* used);
+/* Secret coefficients (int64, N values) and public key ([2][n_q][N]); for
+ * the client side and for tests. */
+hs_status hs_secret_export(hs_ctx* ctx, int64_t* out, size_t n);
+hs_status hs_pk_export(hs_ctx* ctx, uint64_t* out, size_t cap, size_t* used);
+
+/* Encode N/2 complex slots (im may be NULL) at `scale` into NTT-domain
+ * residues of q_0..q_level, written to out[(level+1) * N]. */
+hs_status hs_encode(hs_ctx* ctx, const double* re, const double* im, size_t n_slots, int level, double scale,
+                    uint64_t* out);
+/* Enc (Section 2.2) of the encoding of the slots, at `level` and `scale`;
+ * randomness from `seed`. */
+hs_status hs_encode_encrypt(hs_ctx* ctx, const double* re, const double* im, size_t n_slots, int level,
+                            double scale, uint64_t seed, hs_ct** out);
+/* Enc of given NTT-domain plaintext residues ((level+1) * N values). */
+hs_status hs_encrypt_rows(hs_ctx* ctx, const uint64_t* pt, int level, double scale, uint64_t seed, hs_ct** out);
+/* Dec (Section 2.2) followed by decoding to N/2 slots (im may be NULL). */
+hs_status hs_decrypt_decode(hs_ctx* ctx, const hs_ct* ct, double* re, double* im, size_t n_slots);
+
+/* Ciphertext transport: words = ncomp * (level+1) * N residues. */
+hs_status hs_ct_export(hs_ctx* ctx, const hs_ct* ct, uint64_t* words, size_t cap, size_t* used);
+hs_status hs_ct_import(hs_ctx* ctx, const uint64_t* words, int level, int ncomp, double scale, hs_ct** out);
+hs_status hs_ct_info(const hs_ct* ct, int* level, int* ncomp, double* scale);
+hs_status hs_ct_set_scale(hs_ct* ct, double scale);
+void hs_ct_destroy(hs_ct* ct);
+
+/* Add (Section 2.2): operands at the same level and scale. */
+hs_status hs_add(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, hs_ct** out);
+hs_status hs_sub(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, hs_ct** out);
+/* Tensor product (degree-2 result, no key switching). */
+hs_status hs_tensor(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, hs_ct** out);
+/* Relinearisation of a degree-2 ciphertext (hybrid key switching). */
+hs_status hs_relinearize(hs_ctx* ctx, const hs_ct* d, hs_ct** out);
+/* Rescale: divide by q_level with centred rounding; level - 1. */
+hs_status hs_rescale(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
+/* Mult (Section 2.2): tensor, relinearise and, if rescale != 0, rescale;
+ * operands at different levels are first brought to the lower one. */
+hs_status hs_mult_relin(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, int rescale, hs_ct** out);
+/* Rot (Section 2.2): left rotation of the slots by r (needs its key). */
+hs_status hs_rotate(hs_ctx* ctx, const hs_ct* a, int32_t r, hs_ct** out);
+/* Complex conjugation of every slot (needs the conjugation key). */
+hs_status hs_conjugate(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
+/* Multiply by NTT-domain plaintext residues pt[(a.level+1) * N] whose scale
+ * is pt_scale; rescale if rescale != 0. */
+hs_status hs_mul_plain_rows(hs_ctx* ctx, const hs_ct* a, const uint64_t* pt, double pt_scale, int rescale,
+                            hs_ct** out);
+/* Multiply by the signed integer k (no level consumed, scale unchanged). */
+hs_status hs_mul_int(hs_ctx* ctx, const hs_ct* a, int64_t k, hs_ct** out);
+/* Add the constant v to every slot (adds rint(v * scale) to the message). */
+hs_status hs_add_const(hs_ctx* ctx, const hs_ct* a, double v, hs_ct** out);
+/* Keep q_0..q_level (level <= the input's). */
+hs_status hs_mod_drop(hs_ctx* ctx, const hs_ct* a, int level, hs_ct** out);
+/* Lift a level-0 ciphertext to q_0..q_level with centred residues. */
+hs_status hs_mod_raise(hs_ctx* ctx, const hs_ct* a, int level, hs_ct** out);
+/* Multiply by the monomial X^k (k modulo 2N). */
+hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out);
+
+/* Raw negacyclic NTT (forward or inverse) of `nrows` rows of N residues
+ * modulo prime index `prime` (host buffer, in place); for parity tests. */
+hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HS_H */

@@ -1,0 +1,482 @@
+// extern "C" entry points: argument checks, error capture, handle wrapping.
+#include <hip/hip_runtime_api.h>
+
+#include <cstring>
+#include <string>
+
+#include "../../include/hs.h"
+#include "host.h"
+
+struct hs_ctx {
+    hs::Context* c;
+};
+struct hs_ct {
+    hs::Context* c;
+    hs::Ct ct;
+};
+
+static thread_local std::string g_err;
+
+template <class F>
+static hs_status guard(F&& f) {
+    try {
+        f();
+        return HS_OK;
+    } catch (const hs::Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return HS_E_DEVICE;
+    }
+}
+
+static hs_ct* wrap(hs::Context* c, const hs::Ct& ct) {
+    hs_ct* h = new hs_ct;
+    h->c = c;
+    h->ct = ct;
+    return h;
+}
+
+#define NEED(x) HS_REQUIRE((x), hs::E_ARG, "null argument: " #x)
+
+extern "C" {
+
+const char* hs_version(void) { return "hs 0.1 (gfx950)"; }
+const char* hs_last_error(void) { return g_err.c_str(); }
+
+hs_status hs_ctx_create(const hs_params* p, int device, void* stream, hs_ctx** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(p);
+        NEED(out);
+        NEED(p->q_bits);
+        NEED(p->p_bits);
+        hs::Params q;
+        q.logN = p->log_n;
+        q.q_bits.assign(p->q_bits, p->q_bits + p->n_q);
+        q.p_bits.assign(p->p_bits, p->p_bits + p->n_p);
+        q.digit = p->digit;
+        q.hamming = p->hamming;
+        q.sigma = p->sigma;
+        q.log_scale = p->log_scale;
+        q.user_top = p->user_top;
+        q.boot.cts_levels = p->boot_cts_levels;
+        q.boot.evalmod_levels = p->boot_evalmod_levels;
+        q.boot.stc_levels = p->boot_stc_levels;
+        q.boot.K = p->boot_K;
+        q.boot.double_angle = p->boot_double_angle;
+        q.boot.cos_degree = p->boot_cos_degree;
+        q.boot.log_boot_scale = p->boot_log_scale;
+        if (q.boot.cts_levels > 0) {
+            const int nb = q.boot.cts_levels + q.boot.evalmod_levels + q.boot.stc_levels;
+            HS_REQUIRE(q.user_top == p->n_q - 1 - nb, hs::E_PARAM, "user_top inconsistent with bootstrapping levels");
+        }
+        hs_ctx* h = new hs_ctx;
+        try {
+            h->c = new hs::Context(q, device, stream);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+void hs_ctx_destroy(hs_ctx* ctx) {
+    if (!ctx) return;
+    delete ctx->c;
+    delete ctx;
+}
+
+hs_status hs_ctx_get_info(const hs_ctx* ctx, hs_ctx_info* info) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(info);
+        const hs::Context& c = *ctx->c;
+        info->log_n = c.logN;
+        info->n = c.N;
+        info->slots = c.N / 2;
+        info->n_q = c.nq;
+        info->n_p = c.np;
+        info->top_level = c.L;
+        info->user_top = c.prm.user_top;
+        info->dnum = c.dnum;
+        info->digit = c.prm.digit;
+        info->has_boot = c.prm.boot.cts_levels > 0;
+    });
+}
+
+hs_status hs_ctx_primes(const hs_ctx* ctx, uint64_t* out, size_t cap, size_t* n) {
+    return guard([&] {
+        NEED(ctx);
+        const auto& pr = ctx->c->primes;
+        if (n) *n = pr.size();
+        for (size_t i = 0; i < pr.size() && i < cap && out; i++) out[i] = pr[i];
+    });
+}
+
+hs_status hs_sync(hs_ctx* ctx) {
+    return guard([&] {
+        NEED(ctx);
+        ctx->c->sync();
+    });
+}
+
+hs_status hs_keygen(hs_ctx* ctx, uint64_t seed) {
+    return guard([&] {
+        NEED(ctx);
+        hs::keygen(*ctx->c, seed);
+    });
+}
+
+hs_status hs_add_rotation_keys(hs_ctx* ctx, const int32_t* steps, size_t n, int conj) {
+    return guard([&] {
+        NEED(ctx);
+        HS_REQUIRE(n == 0 || steps, hs::E_ARG, "null steps");
+        hs::Context& c = *ctx->c;
+        for (size_t i = 0; i < n; i++) {
+            const int r = ((steps[i] % (c.N / 2)) + c.N / 2) % (c.N / 2);
+            if (r) hs::add_galois_key(c, hs::galois_rot(r, c.N));
+        }
+        if (conj) hs::add_galois_key(c, 2 * c.N - 1);
+    });
+}
+
+hs_status hs_key_export(hs_ctx* ctx, int key_id, uint64_t* out, size_t cap, size_t* used) {
+    return guard([&] {
+        NEED(ctx);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(hs::has_key(c, key_id), hs::E_KEY, "no such key");
+        const size_t w = (size_t)c.dnum * 2 * (c.nq + c.np) * c.N;
+        if (used) *used = w;
+        if (!out || cap == 0) return;
+        HS_REQUIRE(cap >= w, hs::E_ARG, "buffer too small");
+        c.download(out, c.keys.at(key_id), w * 8);
+    });
+}
+
+hs_status hs_secret_export(hs_ctx* ctx, int64_t* out, size_t n) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(c.have_keys, hs::E_STATE, "keygen first");
+        HS_REQUIRE(n >= (size_t)c.N, hs::E_ARG, "buffer too small");
+        std::memcpy(out, c.s_coeff.data(), sizeof(int64_t) * c.N);
+    });
+}
+
+hs_status hs_pk_export(hs_ctx* ctx, uint64_t* out, size_t cap, size_t* used) {
+    return guard([&] {
+        NEED(ctx);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(c.have_keys, hs::E_STATE, "keygen first");
+        const size_t w = 2 * (size_t)c.nq * c.N;
+        if (used) *used = w;
+        if (!out || cap == 0) return;
+        HS_REQUIRE(cap >= w, hs::E_ARG, "buffer too small");
+        c.download(out, c.pk, w * 8);
+    });
+}
+
+hs_status hs_encode(hs_ctx* ctx, const double* re, const double* im, size_t n_slots, int level, double scale,
+                    uint64_t* out) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(re);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(n_slots == (size_t)c.N / 2, hs::E_ARG, "n_slots must be N/2");
+        HS_REQUIRE(level >= 0 && level <= c.L, hs::E_LEVEL, "level out of range");
+        const size_t w = (size_t)(level + 1) * c.N;
+        u64* d = c.alloc_words(w);
+        hs::encode_to(c, d, re, im, level, scale);
+        c.download(out, d, w * 8);
+        c.free_words(d);
+    });
+}
+
+hs_status hs_encode_encrypt(hs_ctx* ctx, const double* re, const double* im, size_t n_slots, int level,
+                            double scale, uint64_t seed, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(re);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(n_slots == (size_t)c.N / 2, hs::E_ARG, "n_slots must be N/2");
+        HS_REQUIRE(level >= 0 && level <= c.L, hs::E_LEVEL, "level out of range");
+        const size_t w = (size_t)(level + 1) * c.N;
+        u64* d = c.alloc_words(w);
+        hs::encode_to(c, d, re, im, level, scale);
+        hs::Ct ct = hs::encrypt(c, d, level, scale, seed);
+        c.free_words(d);
+        *out = wrap(&c, ct);
+    });
+}
+
+hs_status hs_encrypt_rows(hs_ctx* ctx, const uint64_t* pt, int level, double scale, uint64_t seed, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(pt);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(level >= 0 && level <= c.L, hs::E_LEVEL, "level out of range");
+        const size_t w = (size_t)(level + 1) * c.N;
+        u64* d = c.alloc_words(w);
+        c.upload(d, pt, w * 8);
+        hs::Ct ct = hs::encrypt(c, d, level, scale, seed);
+        c.free_words(d);
+        *out = wrap(&c, ct);
+    });
+}
+
+hs_status hs_decrypt_decode(hs_ctx* ctx, const hs_ct* ct, double* re, double* im, size_t n_slots) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(ct);
+        NEED(re);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(n_slots == (size_t)c.N / 2, hs::E_ARG, "n_slots must be N/2");
+        hs::decrypt_decode(c, ct->ct, 0, re, im);
+    });
+}
+
+hs_status hs_ct_export(hs_ctx* ctx, const hs_ct* ct, uint64_t* words, size_t cap, size_t* used) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(ct);
+        hs::Context& c = *ctx->c;
+        const size_t w = ct->ct.ct_words(c.N);
+        if (used) *used = w;
+        if (!words || cap == 0) return;
+        HS_REQUIRE(cap >= w, hs::E_ARG, "buffer too small");
+        c.download(words, ct->ct.d, w * 8);
+    });
+}
+
+hs_status hs_ct_import(hs_ctx* ctx, const uint64_t* words, int level, int ncomp, double scale, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(words);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(ncomp == 2 || ncomp == 3, hs::E_ARG, "ncomp must be 2 or 3");
+        hs::Ct ct = hs::ct_alloc(c, 1, ncomp, level);
+        ct.scale = scale;
+        c.upload(ct.d, words, ct.ct_words(c.N) * 8);
+        *out = wrap(&c, ct);
+    });
+}
+
+hs_status hs_ct_info(const hs_ct* ct, int* level, int* ncomp, double* scale) {
+    return guard([&] {
+        NEED(ct);
+        if (level) *level = ct->ct.level;
+        if (ncomp) *ncomp = ct->ct.ncomp;
+        if (scale) *scale = ct->ct.scale;
+    });
+}
+
+hs_status hs_ct_set_scale(hs_ct* ct, double scale) {
+    return guard([&] {
+        NEED(ct);
+        HS_REQUIRE(scale > 0, hs::E_ARG, "scale must be positive");
+        ct->ct.scale = scale;
+    });
+}
+
+void hs_ct_destroy(hs_ct* ct) {
+    if (!ct) return;
+    if (ct->c && ct->ct.d) ct->c->free_words(ct->ct.d);
+    delete ct;
+}
+
+#define UNARY_OP(name, expr)                                     \
+    hs_status name(hs_ctx* ctx, const hs_ct* a, hs_ct** out) {   \
+        if (out) *out = nullptr;                                 \
+        return guard([&] {                                       \
+            NEED(ctx);                                           \
+            NEED(a);                                             \
+            NEED(out);                                           \
+            hs::Context& c = *ctx->c;                            \
+            hs::Ct r = (expr);                                   \
+            *out = wrap(&c, r);                                  \
+        });                                                      \
+    }
+
+hs_status hs_add(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(b);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_add(*ctx->c, a->ct, b->ct));
+    });
+}
+
+hs_status hs_sub(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(b);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_sub(*ctx->c, a->ct, b->ct));
+    });
+}
+
+hs_status hs_tensor(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(b);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_tensor(*ctx->c, a->ct, b->ct));
+    });
+}
+
+UNARY_OP(hs_relinearize, hs::op_relin(c, a->ct))
+
+hs_status hs_rescale(hs_ctx* ctx, const hs_ct* a, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_rescale(*ctx->c, a->ct));
+    });
+}
+
+hs_status hs_mult_relin(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, int rescale, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(b);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        if (rescale) {
+            *out = wrap(&c, hs::op_mult(c, a->ct, b->ct));
+        } else {
+            hs::Ct d = hs::op_tensor(c, a->ct, b->ct);
+            hs::Ct r = hs::op_relin(c, d);
+            hs::ct_free(c, d);
+            *out = wrap(&c, r);
+        }
+    });
+}
+
+hs_status hs_rotate(hs_ctx* ctx, const hs_ct* a, int32_t r, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_rotate(*ctx->c, a->ct, r));
+    });
+}
+
+UNARY_OP(hs_conjugate, hs::op_conjugate(c, a->ct))
+
+hs_status hs_mul_plain_rows(hs_ctx* ctx, const hs_ct* a, const uint64_t* pt, double pt_scale, int rescale,
+                            hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(pt);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        const size_t w = (size_t)(a->ct.level + 1) * c.N;
+        u64* d = c.alloc_words(w);
+        c.upload(d, pt, w * 8);
+        hs::Ct r = hs::op_mul_plain(c, a->ct, d, pt_scale, rescale != 0);
+        c.sync();
+        c.free_words(d);
+        *out = wrap(&c, r);
+    });
+}
+
+hs_status hs_mul_int(hs_ctx* ctx, const hs_ct* a, int64_t k, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        hs::Ct r = hs::ct_copy(c, a->ct);
+        hs::op_mul_int_inplace(c, r, (long long)k);
+        *out = wrap(&c, r);
+    });
+}
+
+hs_status hs_add_const(hs_ctx* ctx, const hs_ct* a, double v, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        hs::Ct r = hs::ct_copy(c, a->ct);
+        hs::op_add_const_inplace(c, r, v);
+        *out = wrap(&c, r);
+    });
+}
+
+hs_status hs_mod_drop(hs_ctx* ctx, const hs_ct* a, int level, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        *out = wrap(ctx->c, hs::ct_drop(*ctx->c, a->ct, level));
+    });
+}
+
+hs_status hs_mod_raise(hs_ctx* ctx, const hs_ct* a, int level, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_mod_raise(*ctx->c, a->ct, level));
+    });
+}
+
+hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        *out = wrap(ctx->c, hs::op_mul_monomial(*ctx->c, a->ct, k));
+    });
+}
+
+hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(rows);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(prime >= 0 && prime < c.nq + c.np, hs::E_ARG, "prime index out of range");
+        const size_t w = nrows * c.N;
+        u64* d = c.alloc_words(w);
+        c.upload(d, rows, w * 8);
+        hs::Rows r{d, (int)nrows, 1, (size_t)c.N, 1, prime, c.nq};
+        if (prime >= c.nq) {
+            r.nq = 0;
+            r.p_base = prime;
+        }
+        hs::k_ntt(c.T, r, inverse != 0, c.stream);
+        c.download(rows, d, w * 8);
+        c.free_words(d);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Interface between the host runtime (built with g++) and the HIP kernels
+// (built with hipcc for gfx950): plain structs and launch wrappers.
+#pragma once
+#include <cstdint>
+#include <cstddef>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+namespace hs {
+
+// Modulus data for one prime q < 2^61.  Barrett: b = bit length of q,
+// mu = floor(2^(2b) / q).
+struct PrimeInfo {
+    u64 q;
+    u64 mu;
+    int bits;
+    int pad;
+};
+
+// Device-resident tables of one context (negacyclic NTT twiddles in
+// bit-reversed order, with Shoup companions floor(w 2^64 / q)).
+struct DevTables {
+    const PrimeInfo* prime;   // [n_primes]
+    const u64* tw;            // [n_primes][N]   psi^brv(k)
+    const u64* tws;
+    const u64* itw;           // [n_primes][N]   psi^-brv(k)
+    const u64* itws;
+    const u64* ninv;          // [n_primes][2]   N^-1 mod q, Shoup companion
+    int logN;
+    int N;
+};
+
+// A set of rows: ngroups groups of rpg consecutive rows (N words each);
+// group g starts gstride words after group g-1.  Row r of a group uses prime
+// index q_off + r when r < nq, else p_base + (r - nq).
+struct Rows {
+    u64* base;
+    int ngroups;
+    int rpg;
+    size_t gstride;
+    int nq;
+    int q_off;
+    int p_base;
+};
+
+constexpr int kMaxRows = 64;
+// Per-row constants (indexed by the row within its group), passed by value.
+struct RowConsts {
+    u64 c[kMaxRows];
+    u64 cs[kMaxRows];
+};
+
+// Constants of one fast base conversion, k source rows -> m target rows of
+// the same group: y_t = sum_i [x_i inv_hat_i]_{d_i} * hat[i][t] mod q_t.
+struct ConvTables {
+    const u64* inv_hat;     // [k]
+    const u64* inv_hat_s;   // [k]
+    const u64* hat;         // [k * m]
+    const u64* hat_s;       // [k * m]
+    const int* src_prime;   // [k]
+    const int* dst_prime;   // [m]
+    const int* src_row;     // [k] row offsets (within the input group)
+    const int* dst_row;     // [m] row offsets (within the output group)
+    int k;
+    int m;
+};
+
+// ------------------------------------------------------------- launches
+// All launches are asynchronous on `stream` (a hipStream_t).
+void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream);
+void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
+void k_sub(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
+void k_neg(const DevTables& T, const Rows& out, const Rows& a, void* stream);
+void k_mul(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
+void k_mul_add(const DevTables& T, const Rows& acc, const Rows& a, const Rows& b, void* stream);
+void k_mul_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream);
+void k_add_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream);
+// out = (a - b) * c_row
+void k_sub_mul_const(const DevTables& T, const Rows& out, const Rows& a, const Rows& b,
+                     const RowConsts& c, void* stream);
+// out = d + (a - b) * c_row
+void k_add_sub_mul_const(const DevTables& T, const Rows& out, const Rows& d, const Rows& a,
+                         const Rows& b, const RowConsts& c, void* stream);
+// tensor product of ciphertext pairs: groups are ciphertexts; a, b have 2
+// components (component stride = rows * N inside the group), d has 3.
+void k_tensor(const DevTables& T, const Rows& d, const Rows& a, const Rows& b, size_t a_comp,
+              size_t b_comp, size_t d_comp, void* stream);
+// sum over the groups of a of a (x) a, written to one degree-2 ciphertext d
+void k_square_sum(const DevTables& T, u64* d, size_t d_comp, const Rows& a, size_t a_comp,
+                  void* stream);
+void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* perm, void* stream);
+void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride,
+                    const u64* in, size_t in_gstride, int ngroups, void* stream);
+// centred lift of one row (prime src_prime, coefficient domain) of each
+// group to the rows of `out` (coefficient domain)
+void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t in_gstride,
+                     int src_prime, void* stream);
+// hybrid key-switching inner product: for each ciphertext g and extended row
+// r: acc0 = sum_j ext[g][j][r] * key[j][0][kr(r)], acc1 likewise with key[j][1]
+void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta,
+                 int ext_rows, int nq_level, int key_rows, int key_nq, int alpha, void* stream);
+void k_sample_uniform(const DevTables& T, const Rows& out, u64 seed, u64 domain_base, void* stream);
+// kind: 0 uniform ternary, 2 gaussian (cdt table in device memory)
+void k_sample_small(int64_t* out, int N, u64 seed, u64 domain, int kind, const u64* cdt, int ncdt,
+                    void* stream);
+void k_small_to_rows(const DevTables& T, const Rows& out, const int64_t* small, void* stream);
+void k_copy_rows(const DevTables& T, const Rows& out, const Rows& in, void* stream);
+void k_zero_rows(const DevTables& T, const Rows& out, void* stream);
+// out = round(scale * w) mod q_row for each row (w: N doubles per group)
+void k_encode_real(const DevTables& T, const Rows& out, const double* w, size_t w_gstride,
+                   double scale, void* stream);
+
+}  // namespace hs

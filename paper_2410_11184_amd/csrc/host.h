@@ -1,0 +1,226 @@
+// Host runtime of the homomorphic Softmax library: parameter set, device
+// tables, key material, ciphertext buffers and the homomorphic operations
+// built from the kernels in kernels.hip.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dev.h"
+
+namespace hs {
+
+typedef unsigned __int128 u128;
+
+// Status codes (mirrors include/hs.h)
+enum Status {
+    OK = 0,
+    E_ARG = -1,
+    E_PARAM = -2,
+    E_LEVEL = -3,
+    E_SCALE = -4,
+    E_KEY = -5,
+    E_OOM = -6,
+    E_DEVICE = -7,
+    E_RANGE = -8,
+    E_STATE = -9,
+};
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HS_REQUIRE(cond, code, msg) \
+    do {                            \
+        if (!(cond)) throw ::hs::Error((code), (msg)); \
+    } while (0)
+
+// ------------------------------------------------------------ parameters
+struct BootParams {
+    int cts_levels = 0;      // coefficient-to-slot levels (0 = no bootstrapping)
+    int evalmod_levels = 0;
+    int stc_levels = 0;
+    int K = 32;              // |I| bound of the modular reduction
+    int double_angle = 3;
+    int cos_degree = 63;
+    int log_boot_scale = 50;
+};
+
+struct Params {
+    int logN = 12;
+    std::vector<int> q_bits;
+    std::vector<int> p_bits;
+    int digit = 2;
+    int hamming = 0;
+    double sigma = 3.2;
+    int log_scale = 40;
+    int user_top = 0;
+    BootParams boot;
+};
+
+// --------------------------------------------------------------- memory
+class Pool {
+public:
+    void* alloc(size_t bytes);
+    void free(void* p);
+    void release_all();
+    size_t bytes_in_use() const { return in_use_; }
+    ~Pool();
+
+private:
+    std::multimap<size_t, void*> free_;
+    std::map<void*, size_t> size_;
+    size_t in_use_ = 0;
+};
+
+struct DevBuf {
+    u64* p = nullptr;
+    size_t words = 0;
+};
+
+// A batch of m ciphertexts with the same level and component count, stored
+// densely as [m][ncomp][level+1][N] 64-bit residues (NTT domain).
+struct Ct {
+    u64* d = nullptr;
+    int m = 1;
+    int ncomp = 2;
+    int level = 0;
+    double scale = 1.0;
+    size_t comp_words(int N) const { return (size_t)(level + 1) * N; }
+    size_t ct_words(int N) const { return (size_t)ncomp * (level + 1) * N; }
+};
+
+struct ConvDev {
+    ConvTables t;
+    std::vector<void*> bufs;
+};
+
+struct Context;
+
+// Owned ciphertext handle (frees its buffer through the context's pool).
+struct CtHandle {
+    Context* ctx = nullptr;
+    Ct ct;
+    ~CtHandle();
+};
+
+struct Context {
+    Params prm;
+    int N = 0, logN = 0;
+    std::vector<u64> primes;     // Q primes then P primes
+    int nq = 0, np = 0;
+    int L = 0;                   // top level (nq - 1)
+    int dnum = 0;
+    std::vector<u64> psi;
+    DevTables T{};
+    void* stream = nullptr;
+    int device = 0;
+    Pool pool;
+    std::vector<PrimeInfo> pinfo;
+    u64 P_mod[kMaxRows];         // P mod q_i for Q primes
+    // key material
+    bool have_keys = false;
+    u64 key_seed = 0;
+    std::vector<int64_t> s_coeff;
+    u64* s_ntt = nullptr;        // [nq + np][N]
+    u64* pk = nullptr;           // [2][nq][N]
+    std::map<int, u64*> keys;    // key id -> [dnum][2][nq + np][N]
+    u64* cdt = nullptr;
+    int ncdt = 0;
+    std::vector<u64> cdt_host;
+    std::map<std::pair<int, int>, ConvDev> modup;   // (level, digit)
+    std::map<int, ConvDev> moddown;                 // level
+    std::map<int, int*> perms;                      // galois element -> device perm
+    std::map<int, u64*> monomials;                  // k -> NTT of X^k over all Q primes
+    std::vector<void*> owned;                       // device tables
+    std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
+
+    Context(const Params& p, int device, void* stream);
+    ~Context();
+
+    // helpers
+    u64 q(int i) const { return primes[i]; }
+    Rows rows(u64* base, int ngroups, int rpg, size_t gstride, int q_off = 0) const {
+        return Rows{base, ngroups, rpg, gstride, rpg, q_off, nq};
+    }
+    Rows ext_rows(u64* base, int ngroups, int nql, size_t gstride) const {
+        return Rows{base, ngroups, nql + np, gstride, nql, 0, nq};
+    }
+    Rows p_rows(u64* base, int ngroups, size_t gstride) const {
+        return Rows{base, ngroups, np, gstride, 0, 0, nq};
+    }
+    Rows ct_rows(const Ct& c) const {  // all rows of all components of all cts
+        return Rows{c.d, c.m * c.ncomp, c.level + 1, (size_t)(c.level + 1) * N, c.level + 1, 0, nq};
+    }
+    Rows comp_rows(const Ct& c, int comp) const {
+        return Rows{c.d + (size_t)comp * c.comp_words(N), c.m, c.level + 1, c.ct_words(N), c.level + 1, 0, nq};
+    }
+    u64* alloc_words(size_t w) { return (u64*)pool.alloc(w * sizeof(u64)); }
+    void free_words(u64* p) { pool.free(p); }
+    void sync();
+    void upload(void* dst, const void* src, size_t bytes);
+    void download(void* dst, const void* src, size_t bytes);
+    void* dev_table(const void* host, size_t bytes);   // permanent device copy
+
+    const ConvDev& modup_tables(int level, int j);
+    const ConvDev& moddown_tables(int level);
+    const int* perm(int g);
+    RowConsts shoup_consts(const std::vector<u64>& vals, int q_off, bool p_part = false) const;
+};
+
+// ----------------------------------------------------------- arithmetic
+u64 mulmod_h(u64 a, u64 b, u64 q);
+u64 powmod_h(u64 a, u64 e, u64 q);
+u64 invmod_h(u64 a, u64 q);
+u64 shoup_h(u64 w, u64 q);
+int galois_rot(int r, int N);
+
+// --------------------------------------------------------- ciphertexts
+Ct ct_alloc(Context& c, int m, int ncomp, int level);
+void ct_free(Context& c, Ct& ct);
+Ct ct_copy(Context& c, const Ct& a);
+Ct ct_drop(Context& c, const Ct& a, int level);          // copy to a lower level
+Ct ct_slice(Context& c, const Ct& a, int first, int count);
+Ct ct_gather(Context& c, const std::vector<const Ct*>& parts);
+
+// ---------------------------------------------------- keys / encoding
+void keygen(Context& c, u64 seed);
+void add_galois_key(Context& c, int g);
+bool has_key(const Context& c, int id);
+void special_fft_inverse(const Context& c, std::vector<double>& re, std::vector<double>& im);
+void special_fft(const Context& c, std::vector<double>& re, std::vector<double>& im);
+// encode a slot vector (n = N/2 complex values) into NTT-domain rows 0..level
+void encode_to(Context& c, u64* out_rows, const double* re, const double* im, int level, double scale);
+Ct encrypt(Context& c, const u64* pt_rows, int level, double scale, u64 seed);
+void decrypt_decode(Context& c, const Ct& a, int index, double* re, double* im);
+std::vector<double> decrypt_coeffs_double(Context& c, const Ct& a, int index);
+
+// --------------------------------------------------------------- ops
+void op_add_inplace(Context& c, Ct& a, const Ct& b);         // a += b (b may have m = 1)
+void op_sub_inplace(Context& c, Ct& a, const Ct& b);
+Ct op_add(Context& c, const Ct& a, const Ct& b);
+Ct op_sub(Context& c, const Ct& a, const Ct& b);
+void op_neg_inplace(Context& c, Ct& a);
+void op_mul_int_inplace(Context& c, Ct& a, long long k);     // scale unchanged
+void op_mul_residues_inplace(Context& c, Ct& a, const std::vector<u64>& res);
+void op_add_const_inplace(Context& c, Ct& a, double v);       // adds rint(v * scale)
+Ct op_mul_const(Context& c, const Ct& a, double v, double target_scale); // const mult + rescale
+Ct op_mul_plain(Context& c, const Ct& a, const u64* pt, double pt_scale, bool rescale);
+Ct op_tensor(Context& c, const Ct& a, const Ct& b);
+Ct op_square_sum(Context& c, const Ct& a);                   // sum_g a_g (x) a_g
+Ct op_relin(Context& c, const Ct& d);
+Ct op_rescale(Context& c, const Ct& a);
+Ct op_mult(Context& c, const Ct& a, const Ct& b);            // tensor, relin, rescale
+Ct op_apply_galois(Context& c, const Ct& a, int g);
+Ct op_rotate(Context& c, const Ct& a, int r);
+Ct op_conjugate(Context& c, const Ct& a);
+Ct op_mod_raise(Context& c, const Ct& a, int level);
+Ct op_mul_monomial(Context& c, const Ct& a, int k);
+void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1,
+                size_t out_gstride, const Rows* add0, const Rows* add1);
+
+}  // namespace hs

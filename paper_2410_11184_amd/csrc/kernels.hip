@@ -1,0 +1,643 @@
+// HIP kernels for RNS-CKKS ring arithmetic on CDNA4 (gfx950).
+//
+// Every polynomial is a set of rows ("limbs") of N 64-bit residues, one row
+// per prime, in the negacyclic NTT domain unless a kernel says otherwise.
+// Arithmetic is on the VALU: 64-bit products from 32-bit multiplies, Shoup
+// multiplication by precomputed constants (twiddles, conversion constants)
+// and Barrett reduction for products of two variables.  All kernels keep
+// values fully reduced in [0, q) at their boundaries.
+#include <hip/hip_runtime.h>
+#include "dev.h"
+
+namespace hs {
+
+// ------------------------------------------------------------- arithmetic
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// a * w mod q for any a < 2^64, w < q, ws = floor(w 2^64 / q)
+__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 ws, u64 q) {
+    u64 hi = __umul64hi(a, ws);
+    u64 r = a * w - hi * q;
+    return r >= q ? r - q : r;
+}
+
+// Barrett reduction of the 128-bit x = (hi, lo) < 2^(2b) (HAC 14.42, base 2)
+__device__ __forceinline__ u64 barrett128(u64 hi, u64 lo, const PrimeInfo& P) {
+    const int b = P.bits;
+    u64 x1 = (hi << (65 - b)) | (lo >> (b - 1));
+    u64 plo = x1 * P.mu;
+    u64 phi = __umul64hi(x1, P.mu);
+    u64 qh = (phi << (63 - b)) | (plo >> (b + 1));
+    u64 r = lo - qh * P.q;
+    if (r >= P.q) r -= P.q;
+    if (r >= P.q) r -= P.q;
+    return r;
+}
+
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const PrimeInfo& P) {
+    return barrett128(__umul64hi(a, b), a * b, P);
+}
+
+// x mod q for any 64-bit x (valid since 2^64 <= 2^(2b) for b >= 32)
+__device__ __forceinline__ u64 reduce64(u64 x, const PrimeInfo& P) { return barrett128(0, x, P); }
+
+__device__ __forceinline__ int prime_of(const Rows& x, int r) {
+    return r < x.nq ? x.q_off + r : x.p_base + (r - x.nq);
+}
+
+__device__ __forceinline__ u64* row_ptr(const Rows& x, int row, int N) {
+    int g = row / x.rpg;
+    int r = row - g * x.rpg;
+    return x.base + (size_t)g * x.gstride + (size_t)r * N;
+}
+
+// ------------------------------------------------------------ Philox4x32-10
+__device__ __forceinline__ void philox(u64 seed, u64 domain, u64 index, u32 out[4]) {
+    u32 c0 = (u32)index, c1 = (u32)(index >> 32), c2 = (u32)domain, c3 = (u32)(domain >> 32);
+    u32 k0 = (u32)seed, k1 = (u32)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        u64 p0 = (u64)0xD2511F53u * c0;
+        u64 p1 = (u64)0xCD9E8D57u * c2;
+        u32 n0 = (u32)(p1 >> 32) ^ c1 ^ k0;
+        u32 n1 = (u32)p1;
+        u32 n2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+        u32 n3 = (u32)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// ------------------------------------------------------------------ NTT
+// Forward: Cooley-Tukey with psi^brv twiddles, natural order in, bit-reversed
+// evaluation order out.  Inverse: Gentleman-Sande with psi^-brv, then N^-1.
+// N <= 4096: one workgroup holds a whole row in LDS.  Larger N: N = R * C;
+// pass 1 runs the first log R stages on LDS tiles of R rows x TC columns
+// (stride-C elements), pass 2 the last log C stages on TR contiguous chunks
+// of C elements.
+
+__global__ void __launch_bounds__(256) ntt_small_kernel(DevTables T, Rows x, int inverse) {
+    extern __shared__ u64 sm[];
+    const int N = T.N, logN = T.logN;
+    const int row = blockIdx.x;
+    u64* p = row_ptr(x, row, N);
+    const int pi = prime_of(x, row % x.rpg);
+    const u64 q = T.prime[pi].q;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) sm[e] = p[e];
+    __syncthreads();
+    const int half = N >> 1;
+    if (!inverse) {
+        const u64* w = T.tw + (size_t)pi * N;
+        const u64* ws = T.tws + (size_t)pi * N;
+        for (int s = 0; s < logN; s++) {
+            const int m = 1 << s;
+            const int lt = logN - 1 - s;  // log t
+            for (int k = threadIdx.x; k < half; k += blockDim.x) {
+                const int i = k >> lt;
+                const int j = k & ((1 << lt) - 1);
+                const int j1 = (i << (lt + 1)) + j;
+                const u64 W = w[m + i], Ws = ws[m + i];
+                const u64 u = sm[j1];
+                const u64 v = mul_shoup(sm[j1 + (1 << lt)], W, Ws, q);
+                sm[j1] = add_mod(u, v, q);
+                sm[j1 + (1 << lt)] = sub_mod(u, v, q);
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < N; e += blockDim.x) p[e] = sm[e];
+    } else {
+        const u64* w = T.itw + (size_t)pi * N;
+        const u64* ws = T.itws + (size_t)pi * N;
+        for (int s = logN - 1; s >= 0; s--) {
+            const int m = 1 << s;
+            const int lt = logN - 1 - s;
+            for (int k = threadIdx.x; k < half; k += blockDim.x) {
+                const int i = k >> lt;
+                const int j = k & ((1 << lt) - 1);
+                const int j1 = (i << (lt + 1)) + j;
+                const u64 W = w[m + i], Ws = ws[m + i];
+                const u64 u = sm[j1];
+                const u64 v = sm[j1 + (1 << lt)];
+                sm[j1] = add_mod(u, v, q);
+                sm[j1 + (1 << lt)] = mul_shoup(sub_mod(u, v, q), W, Ws, q);
+            }
+            __syncthreads();
+        }
+        const u64 ni = T.ninv[2 * pi], nis = T.ninv[2 * pi + 1];
+        for (int e = threadIdx.x; e < N; e += blockDim.x) p[e] = mul_shoup(sm[e], ni, nis, q);
+    }
+}
+
+// pass 1: stages m = 1 .. R/2 (forward) or R/2 .. 1 (inverse, then * N^-1)
+__global__ void __launch_bounds__(256) ntt_pass1_kernel(DevTables T, Rows x, int logR, int logC,
+                                                        int logTC, int inverse) {
+    extern __shared__ u64 sm[];
+    const int N = T.N;
+    const int R = 1 << logR, C = 1 << logC, TC = 1 << logTC;
+    const int row = blockIdx.y;
+    const int c0 = blockIdx.x * TC;
+    u64* p = row_ptr(x, row, N);
+    const int pi = prime_of(x, row % x.rpg);
+    const u64 q = T.prime[pi].q;
+    for (int e = threadIdx.x; e < R * TC; e += blockDim.x) {
+        const int rr = e >> logTC, cc = e & (TC - 1);
+        sm[e] = p[(size_t)rr * C + c0 + cc];
+    }
+    __syncthreads();
+    const int nb = (R >> 1) * TC;
+    if (!inverse) {
+        const u64* w = T.tw + (size_t)pi * N;
+        const u64* ws = T.tws + (size_t)pi * N;
+        for (int s = 0; s < logR; s++) {
+            const int m = 1 << s;
+            const int ltr = logR - 1 - s;
+            for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+                const int cc = k & (TC - 1);
+                const int kk = k >> logTC;
+                const int i = kk >> ltr;
+                const int jr = kk & ((1 << ltr) - 1);
+                const int r0 = (i << (ltr + 1)) + jr;
+                const int a0 = (r0 << logTC) + cc, a1 = ((r0 + (1 << ltr)) << logTC) + cc;
+                const u64 u = sm[a0];
+                const u64 v = mul_shoup(sm[a1], w[m + i], ws[m + i], q);
+                sm[a0] = add_mod(u, v, q);
+                sm[a1] = sub_mod(u, v, q);
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < R * TC; e += blockDim.x) {
+            const int rr = e >> logTC, cc = e & (TC - 1);
+            p[(size_t)rr * C + c0 + cc] = sm[e];
+        }
+    } else {
+        const u64* w = T.itw + (size_t)pi * N;
+        const u64* ws = T.itws + (size_t)pi * N;
+        for (int s = logR - 1; s >= 0; s--) {
+            const int m = 1 << s;
+            const int ltr = logR - 1 - s;
+            for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+                const int cc = k & (TC - 1);
+                const int kk = k >> logTC;
+                const int i = kk >> ltr;
+                const int jr = kk & ((1 << ltr) - 1);
+                const int r0 = (i << (ltr + 1)) + jr;
+                const int a0 = (r0 << logTC) + cc, a1 = ((r0 + (1 << ltr)) << logTC) + cc;
+                const u64 u = sm[a0];
+                const u64 v = sm[a1];
+                sm[a0] = add_mod(u, v, q);
+                sm[a1] = mul_shoup(sub_mod(u, v, q), w[m + i], ws[m + i], q);
+            }
+            __syncthreads();
+        }
+        const u64 ni = T.ninv[2 * pi], nis = T.ninv[2 * pi + 1];
+        for (int e = threadIdx.x; e < R * TC; e += blockDim.x) {
+            const int rr = e >> logTC, cc = e & (TC - 1);
+            p[(size_t)rr * C + c0 + cc] = mul_shoup(sm[e], ni, nis, q);
+        }
+    }
+}
+
+// pass 2: stages m = R .. N/2 (forward) or N/2 .. R (inverse)
+__global__ void __launch_bounds__(256) ntt_pass2_kernel(DevTables T, Rows x, int logR, int logC,
+                                                        int logTR, int inverse) {
+    extern __shared__ u64 sm[];
+    const int N = T.N;
+    const int R = 1 << logR, C = 1 << logC, TR = 1 << logTR;
+    const int row = blockIdx.y;
+    const int rc0 = blockIdx.x * TR;
+    u64* p = row_ptr(x, row, N) + (size_t)rc0 * C;
+    const int pi = prime_of(x, row % x.rpg);
+    const u64 q = T.prime[pi].q;
+    for (int e = threadIdx.x; e < TR * C; e += blockDim.x) sm[e] = p[e];
+    __syncthreads();
+    const int nb = TR * (C >> 1);
+    const u64* w = (inverse ? T.itw : T.tw) + (size_t)pi * N;
+    const u64* ws = (inverse ? T.itws : T.tws) + (size_t)pi * N;
+    for (int step = 0; step < logC; step++) {
+        const int s = inverse ? (logC - 1 - step) : step;
+        const int m = R << s;
+        const int lt = logC - 1 - s;  // log t
+        for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+            const int rr = k >> (logC - 1);
+            const int kk = k & ((C >> 1) - 1);
+            const int gi = kk >> lt;
+            const int j = kk & ((1 << lt) - 1);
+            const int e0 = (rr << logC) + (gi << (lt + 1)) + j;
+            const int e1 = e0 + (1 << lt);
+            const int i = ((rc0 + rr) << (logC - 1 - lt)) + gi;
+            const u64 W = w[m + i], Ws = ws[m + i];
+            const u64 u = sm[e0];
+            if (!inverse) {
+                const u64 v = mul_shoup(sm[e1], W, Ws, q);
+                sm[e0] = add_mod(u, v, q);
+                sm[e1] = sub_mod(u, v, q);
+            } else {
+                const u64 v = sm[e1];
+                sm[e0] = add_mod(u, v, q);
+                sm[e1] = mul_shoup(sub_mod(u, v, q), W, Ws, q);
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < TR * C; e += blockDim.x) p[e] = sm[e];
+}
+
+void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) {
+    const int nrows = x.ngroups * x.rpg;
+    if (nrows == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    if (T.N <= 4096) {
+        hipLaunchKernelGGL(ntt_small_kernel, dim3(nrows), dim3(256), T.N * sizeof(u64), st, T, x,
+                           inverse ? 1 : 0);
+        return;
+    }
+    const int logC = (T.logN + 1) / 2, logR = T.logN - logC;
+    const int logTC = 4, logTR = logR >= 4 ? 4 : logR;
+    const dim3 g1((1 << logC) >> logTC, nrows), g2((1 << logR) >> logTR, nrows);
+    const size_t lds1 = ((size_t)1 << (logR + logTC)) * sizeof(u64);
+    const size_t lds2 = ((size_t)1 << (logC + logTR)) * sizeof(u64);
+    if (!inverse) {
+        hipLaunchKernelGGL(ntt_pass1_kernel, g1, dim3(256), lds1, st, T, x, logR, logC, logTC, 0);
+        hipLaunchKernelGGL(ntt_pass2_kernel, g2, dim3(256), lds2, st, T, x, logR, logC, logTR, 0);
+    } else {
+        hipLaunchKernelGGL(ntt_pass2_kernel, g2, dim3(256), lds2, st, T, x, logR, logC, logTR, 1);
+        hipLaunchKernelGGL(ntt_pass1_kernel, g1, dim3(256), lds1, st, T, x, logR, logC, logTC, 1);
+    }
+}
+
+// ----------------------------------------------------------- elementwise
+// grid: (N / 256, rows); one coefficient per thread
+#define EW_INDEX                                  \
+    const int row = blockIdx.y;                   \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x; \
+    const int N = T.N;                            \
+    if (i >= N) return;                           \
+    const int r = row % out.rpg;                  \
+    const PrimeInfo P = T.prime[prime_of(out, r)];
+
+__global__ void add_kernel(DevTables T, Rows out, Rows a, Rows b) {
+    EW_INDEX
+    row_ptr(out, row, N)[i] = add_mod(row_ptr(a, row, N)[i], row_ptr(b, row, N)[i], P.q);
+}
+__global__ void sub_kernel(DevTables T, Rows out, Rows a, Rows b) {
+    EW_INDEX
+    row_ptr(out, row, N)[i] = sub_mod(row_ptr(a, row, N)[i], row_ptr(b, row, N)[i], P.q);
+}
+__global__ void neg_kernel(DevTables T, Rows out, Rows a) {
+    EW_INDEX
+    const u64 v = row_ptr(a, row, N)[i];
+    row_ptr(out, row, N)[i] = v ? P.q - v : 0;
+}
+__global__ void mul_kernel(DevTables T, Rows out, Rows a, Rows b) {
+    EW_INDEX
+    row_ptr(out, row, N)[i] = mul_mod(row_ptr(a, row, N)[i], row_ptr(b, row, N)[i], P);
+}
+__global__ void mul_add_kernel(DevTables T, Rows out, Rows a, Rows b) {
+    EW_INDEX
+    u64* o = row_ptr(out, row, N) + i;
+    *o = add_mod(*o, mul_mod(row_ptr(a, row, N)[i], row_ptr(b, row, N)[i], P), P.q);
+}
+__global__ void mul_row_const_kernel(DevTables T, Rows out, Rows a, RowConsts c) {
+    EW_INDEX
+    row_ptr(out, row, N)[i] = mul_shoup(row_ptr(a, row, N)[i], c.c[r], c.cs[r], P.q);
+}
+__global__ void add_row_const_kernel(DevTables T, Rows out, Rows a, RowConsts c) {
+    EW_INDEX
+    row_ptr(out, row, N)[i] = add_mod(row_ptr(a, row, N)[i], c.c[r], P.q);
+}
+__global__ void sub_mul_const_kernel(DevTables T, Rows out, Rows a, Rows b, RowConsts c) {
+    EW_INDEX
+    const u64 d = sub_mod(row_ptr(a, row, N)[i], row_ptr(b, row, N)[i], P.q);
+    row_ptr(out, row, N)[i] = mul_shoup(d, c.c[r], c.cs[r], P.q);
+}
+__global__ void add_sub_mul_const_kernel(DevTables T, Rows out, Rows d, Rows a, Rows b, RowConsts c) {
+    EW_INDEX
+    const u64 t = sub_mod(row_ptr(a, row, N)[i], row_ptr(b, row, N)[i], P.q);
+    row_ptr(out, row, N)[i] = add_mod(row_ptr(d, row, N)[i], mul_shoup(t, c.c[r], c.cs[r], P.q), P.q);
+}
+
+static inline dim3 ew_grid(const DevTables& T, const Rows& x) {
+    return dim3((T.N + 255) / 256, x.ngroups * x.rpg);
+}
+
+#define EW_LAUNCH(kern, out, ...)                                                        \
+    do {                                                                                 \
+        if ((out).ngroups * (out).rpg == 0) return;                                      \
+        hipLaunchKernelGGL(kern, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, T, out, \
+                           __VA_ARGS__);                                                 \
+    } while (0)
+
+void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream) {
+    EW_LAUNCH(add_kernel, out, a, b);
+}
+void k_sub(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream) {
+    EW_LAUNCH(sub_kernel, out, a, b);
+}
+void k_neg(const DevTables& T, const Rows& out, const Rows& a, void* stream) { EW_LAUNCH(neg_kernel, out, a); }
+void k_mul(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream) {
+    EW_LAUNCH(mul_kernel, out, a, b);
+}
+void k_mul_add(const DevTables& T, const Rows& acc, const Rows& a, const Rows& b, void* stream) {
+    EW_LAUNCH(mul_add_kernel, acc, a, b);
+}
+void k_mul_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream) {
+    EW_LAUNCH(mul_row_const_kernel, out, a, c);
+}
+void k_add_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream) {
+    EW_LAUNCH(add_row_const_kernel, out, a, c);
+}
+void k_sub_mul_const(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, const RowConsts& c,
+                     void* stream) {
+    EW_LAUNCH(sub_mul_const_kernel, out, a, b, c);
+}
+void k_add_sub_mul_const(const DevTables& T, const Rows& out, const Rows& d, const Rows& a, const Rows& b,
+                         const RowConsts& c, void* stream) {
+    EW_LAUNCH(add_sub_mul_const_kernel, out, d, a, b, c);
+}
+
+// ------------------------------------------------------------- tensor
+__global__ void tensor_kernel(DevTables T, Rows d, Rows a, Rows b, size_t ac, size_t bc, size_t dc) {
+    const int row = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    const int r = row % d.rpg;
+    const PrimeInfo P = T.prime[prime_of(d, r)];
+    const u64* pa = row_ptr(a, row, N) + i;
+    const u64* pb = row_ptr(b, row, N) + i;
+    u64* pd = row_ptr(d, row, N) + i;
+    const u64 a0 = pa[0], a1 = pa[ac], b0 = pb[0], b1 = pb[bc];
+    pd[0] = mul_mod(a0, b0, P);
+    pd[dc] = add_mod(mul_mod(a0, b1, P), mul_mod(a1, b0, P), P.q);
+    pd[2 * dc] = mul_mod(a1, b1, P);
+}
+
+void k_tensor(const DevTables& T, const Rows& d, const Rows& a, const Rows& b, size_t a_comp, size_t b_comp,
+              size_t d_comp, void* stream) {
+    if (d.ngroups * d.rpg == 0) return;
+    hipLaunchKernelGGL(tensor_kernel, ew_grid(T, d), dim3(256), 0, (hipStream_t)stream, T, d, a, b, a_comp,
+                       b_comp, d_comp);
+}
+
+// d = sum over groups g of (a0^2, 2 a0 a1, a1^2)
+__global__ void square_sum_kernel(DevTables T, u64* d, size_t dc, Rows a, size_t ac) {
+    const int r = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    const PrimeInfo P = T.prime[prime_of(a, r)];
+    u64 s0 = 0, s1 = 0, s2 = 0;
+    for (int g = 0; g < a.ngroups; g++) {
+        const u64* pa = a.base + (size_t)g * a.gstride + (size_t)r * N + i;
+        const u64 a0 = pa[0], a1 = pa[ac];
+        s0 = add_mod(s0, mul_mod(a0, a0, P), P.q);
+        const u64 x = mul_mod(a0, a1, P);
+        s1 = add_mod(s1, add_mod(x, x, P.q), P.q);
+        s2 = add_mod(s2, mul_mod(a1, a1, P), P.q);
+    }
+    u64* pd = d + (size_t)r * N + i;
+    pd[0] = s0;
+    pd[dc] = s1;
+    pd[2 * dc] = s2;
+}
+
+void k_square_sum(const DevTables& T, u64* d, size_t d_comp, const Rows& a, size_t a_comp, void* stream) {
+    hipLaunchKernelGGL(square_sum_kernel, dim3((T.N + 255) / 256, a.rpg), dim3(256), 0, (hipStream_t)stream, T,
+                       d, d_comp, a, a_comp);
+}
+
+// ---------------------------------------------------------- permutation
+__global__ void permute_kernel(Rows out, Rows in, const int* perm, int N) {
+    const int row = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    row_ptr(out, row, N)[i] = row_ptr(in, row, N)[perm[i]];
+}
+
+void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* perm, void* stream) {
+    if (out.ngroups * out.rpg == 0) return;
+    hipLaunchKernelGGL(permute_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, in, perm, T.N);
+}
+
+// --------------------------------------------------------- base conversion
+constexpr int kMaxConvSrc = 16;
+
+__global__ void base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t og, const u64* in, size_t ig) {
+    const int g = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    u64 xh[kMaxConvSrc];
+    for (int s = 0; s < C.k; s++) {
+        const u64 x = in[(size_t)g * ig + (size_t)C.src_row[s] * N + i];
+        const u64 d = T.prime[C.src_prime[s]].q;
+        xh[s] = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
+    }
+    for (int t = 0; t < C.m; t++) {
+        const u64 q = T.prime[C.dst_prime[t]].q;
+        u64 acc = 0;
+        for (int s = 0; s < C.k; s++)
+            acc = add_mod(acc, mul_shoup(xh[s], C.hat[s * C.m + t], C.hat_s[s * C.m + t], q), q);
+        out[(size_t)g * og + (size_t)C.dst_row[t] * N + i] = acc;
+    }
+}
+
+void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride, const u64* in,
+                    size_t in_gstride, int ngroups, void* stream) {
+    if (ngroups == 0 || C.m == 0) return;
+    hipLaunchKernelGGL(base_convert_kernel, dim3((T.N + 255) / 256, ngroups), dim3(256), 0, (hipStream_t)stream,
+                       T, C, out, out_gstride, in, in_gstride);
+}
+
+// centred lift: v = x if x <= (q_s - 1)/2 else x - q_s, reduced mod each row's prime
+__global__ void lift_centered_kernel(DevTables T, Rows out, const u64* in, size_t ig, int src_prime) {
+    const int row = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    const int g = row / out.rpg;
+    const int r = row - g * out.rpg;
+    const PrimeInfo P = T.prime[prime_of(out, r)];
+    const u64 qs = T.prime[src_prime].q;
+    const u64 x = in[(size_t)g * ig + i];
+    u64 v;
+    if (x <= (qs - 1) / 2) {
+        v = reduce64(x, P);
+    } else {
+        const u64 mag = reduce64(qs - x, P);
+        v = mag ? P.q - mag : 0;
+    }
+    row_ptr(out, row, N)[i] = v;
+}
+
+void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t in_gstride, int src_prime,
+                     void* stream) {
+    if (out.ngroups * out.rpg == 0) return;
+    hipLaunchKernelGGL(lift_centered_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, T, out, in,
+                       in_gstride, src_prime);
+}
+
+// ------------------------------------------------------ key inner product
+// ext:  [ncts][beta][E][N]   (E = nq_level + alpha extended rows)
+// key:  [beta][2][key_rows][N]  (rows = all Q primes then all P primes)
+// acc:  [ncts][2][E][N]
+constexpr int kMaxDigits = 16;
+
+__global__ void key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u64* key, int ncts, int beta,
+                                 int E, int nql, int key_rows, int key_nq) {
+    const int r = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    const int kr = r < nql ? r : key_nq + (r - nql);
+    const PrimeInfo P = T.prime[kr];
+    u64 kb[kMaxDigits], ka[kMaxDigits];
+    for (int j = 0; j < beta; j++) {
+        kb[j] = key[((size_t)(2 * j) * key_rows + kr) * N + i];
+        ka[j] = key[((size_t)(2 * j + 1) * key_rows + kr) * N + i];
+    }
+    for (int g = 0; g < ncts; g++) {
+        u64 s0 = 0, s1 = 0;
+        for (int j = 0; j < beta; j++) {
+            const u64 x = ext[(((size_t)g * beta + j) * E + r) * N + i];
+            s0 = add_mod(s0, mul_mod(x, kb[j], P), P.q);
+            s1 = add_mod(s1, mul_mod(x, ka[j], P), P.q);
+        }
+        acc[(((size_t)g * 2 + 0) * E + r) * N + i] = s0;
+        acc[(((size_t)g * 2 + 1) * E + r) * N + i] = s1;
+    }
+}
+
+void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta, int ext_rows,
+                 int nq_level, int key_rows, int key_nq, int alpha, void* stream) {
+    (void)alpha;
+    hipLaunchKernelGGL(key_inner_kernel, dim3((T.N + 255) / 256, ext_rows), dim3(256), 0, (hipStream_t)stream, T,
+                       acc, ext, key, ncts, beta, ext_rows, nq_level, key_rows, key_nq);
+}
+
+// ------------------------------------------------------------- sampling
+// uniform residues: row with prime index t uses domain (domain_base | t),
+// coefficient i the Philox block at counter i; value = 128-bit block mod q
+__global__ void sample_uniform_kernel(DevTables T, Rows out, u64 seed, u64 dbase) {
+    EW_INDEX
+    const int t = prime_of(out, r);
+    u32 w[4];
+    philox(seed, dbase | (u64)t, (u64)i, w);
+    const u64 lo = ((u64)w[1] << 32) | w[0];
+    const u64 hi = ((u64)w[3] << 32) | w[2];
+    const u64 r64 = reduce64(0 - P.q, P);  // 2^64 mod q
+    const u64 v = add_mod(mul_mod(reduce64(hi, P), r64, P), reduce64(lo, P), P.q);
+    row_ptr(out, row, N)[i] = v;
+}
+
+void k_sample_uniform(const DevTables& T, const Rows& out, u64 seed, u64 domain_base, void* stream) {
+    EW_LAUNCH(sample_uniform_kernel, out, seed, domain_base);
+}
+
+__global__ void sample_small_kernel(int64_t* out, int N, u64 seed, u64 domain, int kind, const u64* cdt, int ncdt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    u32 w[4];
+    philox(seed, domain, (u64)i, w);
+    int64_t v;
+    if (kind == 0) {
+        const u32 r = w[0] % 3u;
+        v = r == 0 ? 0 : (r == 1 ? 1 : -1);
+    } else {
+        const u64 u = ((u64)w[1] << 32) | w[0];
+        int k = 0;
+        while (k < ncdt - 1 && u >= cdt[k]) k++;
+        v = (w[2] & 1u) ? -(int64_t)k : (int64_t)k;
+    }
+    out[i] = v;
+}
+
+void k_sample_small(int64_t* out, int N, u64 seed, u64 domain, int kind, const u64* cdt, int ncdt, void* stream) {
+    hipLaunchKernelGGL(sample_small_kernel, dim3((N + 255) / 256), dim3(256), 0, (hipStream_t)stream, out, N, seed,
+                       domain, kind, cdt, ncdt);
+}
+
+__global__ void small_to_rows_kernel(DevTables T, Rows out, const int64_t* small) {
+    EW_INDEX
+    const int64_t v = small[i];
+    u64 x;
+    if (v >= 0) {
+        x = reduce64((u64)v, P);
+    } else {
+        const u64 m = reduce64((u64)(-v), P);
+        x = m ? P.q - m : 0;
+    }
+    row_ptr(out, row, N)[i] = x;
+}
+
+void k_small_to_rows(const DevTables& T, const Rows& out, const int64_t* small, void* stream) {
+    EW_LAUNCH(small_to_rows_kernel, out, small);
+}
+
+// ------------------------------------------------------------ copy / zero
+__global__ void copy_rows_kernel(Rows out, Rows in, int N) {
+    const int row = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    row_ptr(out, row, N)[i] = row_ptr(in, row, N)[i];
+}
+__global__ void zero_rows_kernel(Rows out, int N) {
+    const int row = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    row_ptr(out, row, N)[i] = 0;
+}
+
+void k_copy_rows(const DevTables& T, const Rows& out, const Rows& in, void* stream) {
+    if (out.ngroups * out.rpg == 0) return;
+    hipLaunchKernelGGL(copy_rows_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, in, T.N);
+}
+
+void k_zero_rows(const DevTables& T, const Rows& out, void* stream) {
+    if (out.ngroups * out.rpg == 0) return;
+    hipLaunchKernelGGL(zero_rows_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, T.N);
+}
+
+// ------------------------------------------------------------- encoding
+// value = rint(scale * w) as an exact integer, reduced mod the row's prime
+__device__ u64 double_to_residue(double v, const PrimeInfo& P) {
+    const bool neg = v < 0;
+    const double a = neg ? -v : v;
+    u64 mag;
+    if (a < 9.2e18) {
+        mag = reduce64((u64)a, P);
+    } else {
+        int e;
+        const double m = frexp(a, &e);                 // a = m 2^e, m in [0.5, 1)
+        const u64 mant = (u64)ldexp(m, 53);            // exact 53-bit integer
+        int sh = e - 53;                               // a = mant * 2^sh, sh > 0
+        u64 p2 = 1, base = 2 % P.q;
+        while (sh > 0) {
+            if (sh & 1) p2 = mul_mod(p2, base, P);
+            base = mul_mod(base, base, P);
+            sh >>= 1;
+        }
+        mag = mul_mod(reduce64(mant, P), p2, P);
+    }
+    return (neg && mag) ? P.q - mag : mag;
+}
+
+__global__ void encode_real_kernel(DevTables T, Rows out, const double* w, size_t wg, double scale) {
+    EW_INDEX
+    const int g = row / out.rpg;
+    const double v = rint(scale * w[(size_t)g * wg + i]);
+    row_ptr(out, row, N)[i] = double_to_residue(v, P);
+}
+
+void k_encode_real(const DevTables& T, const Rows& out, const double* w, size_t w_gstride, double scale,
+                   void* stream) {
+    EW_LAUNCH(encode_real_kernel, out, w, w_gstride, scale);
+}
+
+}  // namespace hs

@@ -1,0 +1,349 @@
+// Homomorphic operations on batches of ciphertexts (Section 2.2,
+// "Functionalities" and "Levels": Add, Mult with level min(l1, l2) - 1, Rot).
+// Every operation runs over all m ciphertexts of a batch in one launch per
+// kernel; a batch with m = 1 may be broadcast against a larger one.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+
+namespace hs {
+
+static void check_scales(double a, double b) {
+    HS_REQUIRE(std::fabs(a / b - 1.0) < 1e-9, E_SCALE, "operands have different scales");
+}
+
+static Rows comp_rows_bcast(const Context& c, const Ct& a, int comp, int m_target) {
+    Rows r = c.comp_rows(a, comp);
+    if (a.m == 1 && m_target > 1) {
+        r.gstride = 0;
+        r.ngroups = m_target;
+    }
+    return r;
+}
+
+void op_add_inplace(Context& c, Ct& a, const Ct& b) {
+    HS_REQUIRE(a.level == b.level, E_LEVEL, "add: levels differ");
+    HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "add: batch sizes differ");
+    HS_REQUIRE(b.ncomp <= a.ncomp, E_ARG, "add: component count");
+    check_scales(a.scale, b.scale);
+    for (int k = 0; k < b.ncomp; k++) {
+        Rows o = c.comp_rows(a, k);
+        k_add(c.T, o, o, comp_rows_bcast(c, b, k, a.m), c.stream);
+    }
+}
+
+void op_sub_inplace(Context& c, Ct& a, const Ct& b) {
+    HS_REQUIRE(a.level == b.level, E_LEVEL, "sub: levels differ");
+    HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "sub: batch sizes differ");
+    HS_REQUIRE(b.ncomp <= a.ncomp, E_ARG, "sub: component count");
+    check_scales(a.scale, b.scale);
+    for (int k = 0; k < b.ncomp; k++) {
+        Rows o = c.comp_rows(a, k);
+        k_sub(c.T, o, o, comp_rows_bcast(c, b, k, a.m), c.stream);
+    }
+}
+
+Ct op_add(Context& c, const Ct& a, const Ct& b) {
+    Ct o = ct_copy(c, a);
+    op_add_inplace(c, o, b);
+    return o;
+}
+
+Ct op_sub(Context& c, const Ct& a, const Ct& b) {
+    Ct o = ct_copy(c, a);
+    op_sub_inplace(c, o, b);
+    return o;
+}
+
+void op_neg_inplace(Context& c, Ct& a) {
+    Rows r = c.ct_rows(a);
+    k_neg(c.T, r, r, c.stream);
+}
+
+void op_mul_residues_inplace(Context& c, Ct& a, const std::vector<u64>& res) {
+    RowConsts rc = c.shoup_consts(std::vector<u64>(res.begin(), res.begin() + a.level + 1), 0);
+    Rows r = c.ct_rows(a);
+    k_mul_row_const(c.T, r, r, rc, c.stream);
+}
+
+static std::vector<u64> int_residues(const Context& c, long long k, int level) {
+    std::vector<u64> r(level + 1);
+    for (int i = 0; i <= level; i++) {
+        const u64 q = c.primes[i];
+        const u64 m = (u64)(k < 0 ? -(k + 1) : k) % q;  // |k| - 1 for negatives avoids overflow
+        if (k >= 0) r[i] = m;
+        else r[i] = (q - (m + 1) % q) % q;
+    }
+    return r;
+}
+
+void op_mul_int_inplace(Context& c, Ct& a, long long k) { op_mul_residues_inplace(c, a, int_residues(c, k, a.level)); }
+
+// residues of the integer value of the (integral) double v
+static std::vector<u64> double_residues(const Context& c, double v, int level) {
+    std::vector<u64> r(level + 1);
+    const bool neg = v < 0;
+    const double a = std::fabs(v);
+    int e = 0;
+    double mant = 0;
+    u64 mi = 0;
+    bool small = a < 9.2e18;
+    if (!small) {
+        mant = std::frexp(a, &e);
+        mi = (u64)std::ldexp(mant, 53);
+        e -= 53;
+    }
+    for (int i = 0; i <= level; i++) {
+        const u64 q = c.primes[i];
+        u64 mag = small ? (u64)a % q : mulmod_h(mi % q, powmod_h(2, (u64)e, q), q);
+        r[i] = (neg && mag) ? q - mag : mag;
+    }
+    return r;
+}
+
+void op_add_const_inplace(Context& c, Ct& a, double v) {
+    const double K = std::rint(v * a.scale);
+    std::vector<u64> res = double_residues(c, K, a.level);
+    RowConsts rc = c.shoup_consts(res, 0);
+    Rows r = c.comp_rows(a, 0);
+    k_add_row_const(c.T, r, r, rc, c.stream);
+}
+
+Ct op_rescale(Context& c, const Ct& a) {
+    HS_REQUIRE(a.level >= 1, E_LEVEL, "rescale: no level left");
+    const int l = a.level;
+    const int np_ = a.m * a.ncomp;
+    const size_t N = c.N;
+    u64* last = c.alloc_words((size_t)np_ * N);
+    u64* lifted = c.alloc_words((size_t)np_ * l * N);
+    Rows in_last{a.d + (size_t)l * N, np_, 1, (size_t)(l + 1) * N, 1, l, c.nq};
+    Rows r_last{last, np_, 1, N, 1, l, c.nq};
+    k_copy_rows(c.T, r_last, in_last, c.stream);
+    k_ntt(c.T, r_last, true, c.stream);
+    Rows r_lift{lifted, np_, l, (size_t)l * N, l, 0, c.nq};
+    k_lift_centered(c.T, r_lift, last, N, l, c.stream);
+    k_ntt(c.T, r_lift, false, c.stream);
+    Ct o = ct_alloc(c, a.m, a.ncomp, l - 1);
+    std::vector<u64> inv(l);
+    for (int i = 0; i < l; i++) inv[i] = invmod_h(c.primes[l] % c.primes[i], c.primes[i]);
+    RowConsts rc = c.shoup_consts(inv, 0);
+    Rows out{o.d, np_, l, (size_t)l * N, l, 0, c.nq};
+    Rows ain{a.d, np_, l, (size_t)(l + 1) * N, l, 0, c.nq};
+    k_sub_mul_const(c.T, out, ain, r_lift, rc, c.stream);
+    o.scale = a.scale / (double)c.primes[l];
+    c.free_words(last);
+    c.free_words(lifted);
+    return o;
+}
+
+Ct op_mul_const(Context& c, const Ct& a, double v, double target_scale) {
+    const double S = target_scale * (double)c.primes[a.level] / a.scale;
+    const double K = std::rint(v * S);
+    Ct t = ct_copy(c, a);
+    op_mul_residues_inplace(c, t, double_residues(c, K, a.level));
+    Ct o = op_rescale(c, t);
+    ct_free(c, t);
+    o.scale = target_scale;
+    return o;
+}
+
+Ct op_mul_plain(Context& c, const Ct& a, const u64* pt, double pt_scale, bool rescale) {
+    Ct o = ct_alloc(c, a.m, a.ncomp, a.level);
+    Rows rp{const_cast<u64*>(pt), a.m * a.ncomp, a.level + 1, 0, a.level + 1, 0, c.nq};
+    k_mul(c.T, c.ct_rows(o), c.ct_rows(a), rp, c.stream);
+    o.scale = a.scale * pt_scale;
+    if (!rescale) return o;
+    Ct r = op_rescale(c, o);
+    ct_free(c, o);
+    return r;
+}
+
+Ct op_tensor(Context& c, const Ct& a, const Ct& b) {
+    HS_REQUIRE(a.ncomp == 2 && b.ncomp == 2, E_ARG, "tensor: degree-1 inputs expected");
+    HS_REQUIRE(a.level == b.level, E_LEVEL, "tensor: levels differ");
+    HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "tensor: batch sizes differ");
+    Ct d = ct_alloc(c, a.m, 3, a.level);
+    d.scale = a.scale * b.scale;
+    const size_t cw = a.comp_words(c.N);
+    Rows rd{d.d, a.m, a.level + 1, d.ct_words(c.N), a.level + 1, 0, c.nq};
+    Rows ra{a.d, a.m, a.level + 1, a.ct_words(c.N), a.level + 1, 0, c.nq};
+    Rows rb{b.d, a.m, a.level + 1, b.m == 1 ? 0 : b.ct_words(c.N), a.level + 1, 0, c.nq};
+    k_tensor(c.T, rd, ra, rb, cw, cw, cw, c.stream);
+    return d;
+}
+
+Ct op_square_sum(Context& c, const Ct& a) {
+    HS_REQUIRE(a.ncomp == 2, E_ARG, "square_sum: degree-1 inputs expected");
+    Ct d = ct_alloc(c, 1, 3, a.level);
+    d.scale = a.scale * a.scale;
+    Rows ra{a.d, a.m, a.level + 1, a.ct_words(c.N), a.level + 1, 0, c.nq};
+    k_square_sum(c.T, d.d, d.comp_words(c.N), ra, a.comp_words(c.N), c.stream);
+    return d;
+}
+
+// Hybrid key switching of the m polynomials d (level l, NTT domain):
+// ModUp per digit, inner product with the key, ModDown.  Writes
+// out_k[g] = (add_k[g] +) ModDown(acc_k[g]) for k = 0, 1.
+void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1, size_t out_gstride,
+                const Rows* add0, const Rows* add1) {
+    const int m = d.ngroups;
+    const int l = level;
+    const int nql = l + 1;
+    const int E = nql + c.np;
+    const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
+    const size_t N = c.N;
+    // coefficient-domain copy of d
+    u64* dc = c.alloc_words((size_t)m * nql * N);
+    Rows rdc{dc, m, nql, (size_t)nql * N, nql, 0, c.nq};
+    k_copy_rows(c.T, rdc, d, c.stream);
+    k_ntt(c.T, rdc, true, c.stream);
+    // ModUp: digit j -> extended rows (coefficient domain), then NTT
+    u64* ext = c.alloc_words((size_t)m * beta * E * N);
+    for (int j = 0; j < beta; j++) {
+        const int lo = j * c.prm.digit, hi = std::min((j + 1) * c.prm.digit, nql);
+        const ConvDev& cv = c.modup_tables(l, j);
+        k_base_convert(c.T, cv.t, ext + (size_t)j * E * N, (size_t)beta * E * N, dc, (size_t)nql * N, m, c.stream);
+        Rows own_out{ext + (size_t)j * E * N + (size_t)lo * N, m, hi - lo, (size_t)beta * E * N, hi - lo, lo, c.nq};
+        Rows own_in{dc + (size_t)lo * N, m, hi - lo, (size_t)nql * N, hi - lo, lo, c.nq};
+        k_copy_rows(c.T, own_out, own_in, c.stream);
+    }
+    c.free_words(dc);
+    Rows rext{ext, m * beta, E, (size_t)E * N, nql, 0, c.nq};
+    k_ntt(c.T, rext, false, c.stream);
+    // inner product with the key: acc [m][2][E][N]
+    u64* acc = c.alloc_words((size_t)m * 2 * E * N);
+    k_key_inner(c.T, acc, ext, key, m, beta, E, nql, c.nq + c.np, c.nq, c.np, c.stream);
+    c.free_words(ext);
+    // ModDown
+    Rows accp{acc + (size_t)nql * N, 2 * m, c.np, (size_t)E * N, 0, 0, c.nq};
+    k_ntt(c.T, accp, true, c.stream);
+    u64* conv = c.alloc_words((size_t)2 * m * nql * N);
+    const ConvDev& md = c.moddown_tables(l);
+    k_base_convert(c.T, md.t, conv, (size_t)nql * N, acc, (size_t)E * N, 2 * m, c.stream);
+    Rows rconv{conv, 2 * m, nql, (size_t)nql * N, nql, 0, c.nq};
+    k_ntt(c.T, rconv, false, c.stream);
+    std::vector<u64> pinv(nql);
+    for (int i = 0; i < nql; i++) pinv[i] = invmod_h(c.P_mod[i], c.primes[i]);
+    RowConsts rc = c.shoup_consts(pinv, 0);
+    for (int k = 0; k < 2; k++) {
+        u64* outk = k == 0 ? out0 : out1;
+        Rows ro{outk, m, nql, out_gstride, nql, 0, c.nq};
+        Rows ra{acc + (size_t)k * E * N, m, nql, (size_t)2 * E * N, nql, 0, c.nq};
+        Rows rb{conv + (size_t)k * nql * N, m, nql, (size_t)2 * nql * N, nql, 0, c.nq};
+        const Rows* add = k == 0 ? add0 : add1;
+        if (add) k_add_sub_mul_const(c.T, ro, *add, ra, rb, rc, c.stream);
+        else k_sub_mul_const(c.T, ro, ra, rb, rc, c.stream);
+    }
+    c.free_words(acc);
+    c.free_words(conv);
+}
+
+Ct op_relin(Context& c, const Ct& d) {
+    HS_REQUIRE(d.ncomp == 3, E_ARG, "relin: degree-2 input expected");
+    HS_REQUIRE(has_key(c, 0), E_KEY, "relinearisation key missing");
+    Ct o = ct_alloc(c, d.m, 2, d.level);
+    o.scale = d.scale;
+    Rows d2 = c.comp_rows(d, 2);
+    Rows a0 = c.comp_rows(d, 0), a1 = c.comp_rows(d, 1);
+    key_switch(c, d2, d.level, c.keys.at(0), o.d, o.d + o.comp_words(c.N), o.ct_words(c.N), &a0, &a1);
+    return o;
+}
+
+Ct op_mult(Context& c, const Ct& a, const Ct& b) {
+    const Ct* pa = &a;
+    const Ct* pb = &b;
+    Ct ta, tb;
+    if (a.level > b.level) {
+        ta = ct_drop(c, a, b.level);
+        pa = &ta;
+    } else if (b.level > a.level) {
+        tb = ct_drop(c, b, a.level);
+        pb = &tb;
+    }
+    Ct d = op_tensor(c, *pa, *pb);
+    if (ta.d) ct_free(c, ta);
+    if (tb.d) ct_free(c, tb);
+    Ct r = op_relin(c, d);
+    ct_free(c, d);
+    Ct o = op_rescale(c, r);
+    ct_free(c, r);
+    return o;
+}
+
+Ct op_apply_galois(Context& c, const Ct& a, int g) {
+    HS_REQUIRE(a.ncomp == 2, E_ARG, "automorphism: degree-1 input expected");
+    g = ((g % (2 * c.N)) + 2 * c.N) % (2 * c.N);
+    HS_REQUIRE(has_key(c, g), E_KEY, "Galois key missing");
+    Ct b = ct_alloc(c, a.m, 2, a.level);
+    k_permute(c.T, c.ct_rows(b), c.ct_rows(a), c.perm(g), c.stream);
+    Ct o = ct_alloc(c, a.m, 2, a.level);
+    o.scale = a.scale;
+    Rows b0 = c.comp_rows(b, 0);
+    Rows b1 = c.comp_rows(b, 1);
+    key_switch(c, b1, a.level, c.keys.at(g), o.d, o.d + o.comp_words(c.N), o.ct_words(c.N), &b0, nullptr);
+    ct_free(c, b);
+    return o;
+}
+
+Ct op_rotate(Context& c, const Ct& a, int r) {
+    if (((r % (c.N / 2)) + c.N / 2) % (c.N / 2) == 0) return ct_copy(c, a);
+    return op_apply_galois(c, a, galois_rot(r, c.N));
+}
+
+Ct op_conjugate(Context& c, const Ct& a) { return op_apply_galois(c, a, 2 * c.N - 1); }
+
+Ct op_mod_raise(Context& c, const Ct& a, int level) {
+    HS_REQUIRE(a.level == 0, E_LEVEL, "ModRaise expects a level-0 ciphertext");
+    HS_REQUIRE(level >= 1 && level <= c.L, E_LEVEL, "ModRaise target level");
+    const size_t N = c.N;
+    const int np_ = a.m * a.ncomp;
+    Ct o = ct_alloc(c, a.m, a.ncomp, level);
+    o.scale = a.scale;
+    Rows r0{o.d, np_, 1, (size_t)(level + 1) * N, 1, 0, c.nq};
+    k_copy_rows(c.T, r0, c.ct_rows(a), c.stream);
+    u64* coef = c.alloc_words((size_t)np_ * N);
+    Rows rc{coef, np_, 1, N, 1, 0, c.nq};
+    k_copy_rows(c.T, rc, c.ct_rows(a), c.stream);
+    k_ntt(c.T, rc, true, c.stream);
+    Rows up{o.d + N, np_, level, (size_t)(level + 1) * N, level, 1, c.nq};
+    k_lift_centered(c.T, up, coef, N, 0, c.stream);
+    k_ntt(c.T, up, false, c.stream);
+    c.free_words(coef);
+    return o;
+}
+
+Ct op_mul_monomial(Context& c, const Ct& a, int k) {
+    k = ((k % (2 * c.N)) + 2 * c.N) % (2 * c.N);
+    auto& cache = c.monomials;
+    const int key = k;
+    u64* mono;
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        const size_t w = (size_t)(c.L + 1) * c.N;
+        std::vector<u64> h(w, 0);
+        for (int i = 0; i <= c.L; i++) {
+            if (k < c.N) h[(size_t)i * c.N + k] = 1;
+            else h[(size_t)i * c.N + (k - c.N)] = c.primes[i] - 1;
+        }
+        void* p = nullptr;
+        hipMalloc(&p, w * 8);
+        c.owned.push_back(p);
+        mono = (u64*)p;
+        c.upload(mono, h.data(), w * 8);
+        k_ntt(c.T, c.rows(mono, 1, c.L + 1, w), false, c.stream);
+        cache[key] = mono;
+    } else {
+        mono = it->second;
+    }
+    Ct o = ct_alloc(c, a.m, a.ncomp, a.level);
+    o.scale = a.scale;
+    Rows rp{mono, a.m * a.ncomp, a.level + 1, 0, a.level + 1, 0, c.nq};
+    k_mul(c.T, c.ct_rows(o), c.ct_rows(a), rp, c.stream);
+    return o;
+}
+
+}  // namespace hs

@@ -1,0 +1,339 @@
+"""Python binding of the C ABI in ``include/hs.h`` (argument marshalling only).
+
+Every computation runs inside ``libhs.so`` (HIP kernels for gfx950 plus the
+C++ host runtime).  If the library is missing the import fails loudly: there
+is no CPU fallback.  PyTorch is used only to hand the library the current
+HIP stream.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhs.so")
+
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_vp = ctypes.c_void_p
+
+ERRORS = {
+    -1: "HS_E_ARG", -2: "HS_E_PARAM", -3: "HS_E_LEVEL", -4: "HS_E_SCALE", -5: "HS_E_KEY",
+    -6: "HS_E_OOM", -7: "HS_E_DEVICE", -8: "HS_E_RANGE", -9: "HS_E_STATE",
+}
+
+
+class HSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class hs_params(ctypes.Structure):
+    _fields_ = [
+        ("log_n", ctypes.c_int), ("n_q", ctypes.c_int), ("q_bits", ctypes.POINTER(ctypes.c_int)),
+        ("n_p", ctypes.c_int), ("p_bits", ctypes.POINTER(ctypes.c_int)), ("digit", ctypes.c_int),
+        ("hamming", ctypes.c_int), ("sigma", ctypes.c_double), ("log_scale", ctypes.c_int),
+        ("user_top", ctypes.c_int), ("boot_cts_levels", ctypes.c_int), ("boot_evalmod_levels", ctypes.c_int),
+        ("boot_stc_levels", ctypes.c_int), ("boot_K", ctypes.c_int), ("boot_double_angle", ctypes.c_int),
+        ("boot_cos_degree", ctypes.c_int), ("boot_log_scale", ctypes.c_int),
+    ]
+
+
+class hs_ctx_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in
+                ("log_n", "n", "slots", "n_q", "n_p", "top_level", "user_top", "dnum", "digit", "has_boot")]
+
+
+class hs_softmax_opts(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int), ("k", ctypes.c_int), ("exp_degree", ctypes.c_int),
+        ("inv_degree_first", ctypes.c_int), ("inv_degree_mid", ctypes.c_int),
+        ("inv_degree_last", ctypes.c_int), ("alpha", ctypes.c_double),
+        ("plain_per_ct", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhs.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    L = ctypes.CDLL(LIB_PATH)
+    S = ctypes.c_int
+    L.hs_version.restype = ctypes.c_char_p
+    L.hs_last_error.restype = ctypes.c_char_p
+    sig = {
+        "hs_ctx_create": [ctypes.POINTER(hs_params), S, _vp, ctypes.POINTER(_vp)],
+        "hs_ctx_get_info": [_vp, ctypes.POINTER(hs_ctx_info)],
+        "hs_ctx_primes": [_vp, _u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "hs_sync": [_vp],
+        "hs_keygen": [_vp, ctypes.c_uint64],
+        "hs_add_rotation_keys": [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, S],
+        "hs_key_export": [_vp, S, _u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "hs_secret_export": [_vp, _i64p, ctypes.c_size_t],
+        "hs_pk_export": [_vp, _u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "hs_encode": [_vp, _f64p, _vp, ctypes.c_size_t, S, ctypes.c_double, _u64p],
+        "hs_encode_encrypt": [_vp, _f64p, _vp, ctypes.c_size_t, S, ctypes.c_double, ctypes.c_uint64,
+                              ctypes.POINTER(_vp)],
+        "hs_encrypt_rows": [_vp, _u64p, S, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(_vp)],
+        "hs_decrypt_decode": [_vp, _vp, _f64p, _vp, ctypes.c_size_t],
+        "hs_ct_export": [_vp, _vp, _u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "hs_ct_import": [_vp, _u64p, S, S, ctypes.c_double, ctypes.POINTER(_vp)],
+        "hs_ct_info": [_vp, ctypes.POINTER(S), ctypes.POINTER(S), ctypes.POINTER(ctypes.c_double)],
+        "hs_ct_set_scale": [_vp, ctypes.c_double],
+        "hs_add": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
+        "hs_sub": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
+        "hs_tensor": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
+        "hs_relinearize": [_vp, _vp, ctypes.POINTER(_vp)],
+        "hs_rescale": [_vp, _vp, ctypes.POINTER(_vp)],
+        "hs_mult_relin": [_vp, _vp, _vp, S, ctypes.POINTER(_vp)],
+        "hs_rotate": [_vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
+        "hs_conjugate": [_vp, _vp, ctypes.POINTER(_vp)],
+        "hs_mul_plain_rows": [_vp, _vp, _u64p, ctypes.c_double, S, ctypes.POINTER(_vp)],
+        "hs_mul_int": [_vp, _vp, ctypes.c_int64, ctypes.POINTER(_vp)],
+        "hs_add_const": [_vp, _vp, ctypes.c_double, ctypes.POINTER(_vp)],
+        "hs_mod_drop": [_vp, _vp, S, ctypes.POINTER(_vp)],
+        "hs_mod_raise": [_vp, _vp, S, ctypes.POINTER(_vp)],
+        "hs_mul_monomial": [_vp, _vp, S, ctypes.POINTER(_vp)],
+        "hs_dbg_ntt": [_vp, S, _u64p, ctypes.c_size_t, S],
+    }
+    optional = {
+        "hs_bootstrap": [_vp, _vp, ctypes.POINTER(_vp)],
+        "hs_softmax": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_uint32, ctypes.c_double,
+                       ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
+        "hs_softmax_stats": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+    }
+    for name, args in list(sig.items()) + list(optional.items()):
+        if not hasattr(L, name):
+            if name in sig:
+                raise ImportError("libhs.so lacks %s" % name)
+            continue
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = S
+    L.hs_ct_destroy.argtypes = [_vp]
+    L.hs_ct_destroy.restype = None
+    L.hs_ctx_destroy.argtypes = [_vp]
+    L.hs_ctx_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise HSError(st, lib().hs_last_error().decode())
+
+
+def current_stream():
+    """HIP stream handle of torch's current stream on the current device."""
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Ciphertext:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.h = handle
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hs_ct_destroy(self.h)
+            self.h = None
+
+    @property
+    def info(self):
+        lv, nc, sc = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().hs_ct_info(self.h, ctypes.byref(lv), ctypes.byref(nc), ctypes.byref(sc)))
+        return lv.value, nc.value, sc.value
+
+    @property
+    def level(self):
+        return self.info[0]
+
+    @property
+    def scale(self):
+        return self.info[2]
+
+    def export(self):
+        used = ctypes.c_size_t()
+        _check(lib().hs_ct_export(self.ctx.h, self.h, np.zeros(1, np.uint64), 0, ctypes.byref(used)))
+        out = np.zeros(used.value, dtype=np.uint64)
+        _check(lib().hs_ct_export(self.ctx.h, self.h, out, out.size, ctypes.byref(used)))
+        lv, nc, _ = self.info
+        return out.reshape(nc, lv + 1, -1)
+
+
+class Context:
+    """One parameter set on one device.  ``params`` is a dict like the
+    presets in ``synthetic.PRESETS``."""
+
+    def __init__(self, params, device=0, stream=None):
+        L = lib()
+        self._keep = []
+        qb = (ctypes.c_int * len(params["q_bits"]))(*params["q_bits"])
+        pb = (ctypes.c_int * len(params["p_bits"]))(*params["p_bits"])
+        self._keep += [qb, pb]
+        boot = params.get("boot") or {}
+        p = hs_params(
+            log_n=params["logN"], n_q=len(params["q_bits"]), q_bits=qb, n_p=len(params["p_bits"]),
+            p_bits=pb, digit=params["digit"], hamming=params["hamming"], sigma=params.get("sigma", 3.2),
+            log_scale=params["log_scale"], user_top=params["user_top"],
+            boot_cts_levels=boot.get("cts_levels", 0), boot_evalmod_levels=boot.get("evalmod_levels", 0),
+            boot_stc_levels=boot.get("stc_levels", 0), boot_K=boot.get("K", 0),
+            boot_double_angle=boot.get("double_angle", 0), boot_cos_degree=boot.get("cos_degree", 0),
+            boot_log_scale=boot.get("log_boot_scale", 0))
+        h = _vp()
+        st = stream if stream is not None else None
+        _check(L.hs_ctx_create(ctypes.byref(p), device, st, ctypes.byref(h)))
+        self.h = h
+        info = hs_ctx_info()
+        _check(L.hs_ctx_get_info(h, ctypes.byref(info)))
+        self.N = info.n
+        self.slots = info.slots
+        self.nq = info.n_q
+        self.np = info.n_p
+        self.L = info.top_level
+        self.user_top = info.user_top
+        self.dnum = info.dnum
+        self.delta = float(2 ** params["log_scale"])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hs_ctx_destroy(self.h)
+            self.h = None
+
+    def primes(self):
+        out = np.zeros(self.nq + self.np, dtype=np.uint64)
+        n = ctypes.c_size_t()
+        _check(lib().hs_ctx_primes(self.h, out, out.size, ctypes.byref(n)))
+        return [int(v) for v in out]
+
+    def sync(self):
+        _check(lib().hs_sync(self.h))
+
+    def keygen(self, seed, rotations=(), conj=False):
+        _check(lib().hs_keygen(self.h, seed))
+        self.add_rotation_keys(rotations, conj)
+
+    def add_rotation_keys(self, rotations=(), conj=False):
+        arr = (ctypes.c_int32 * max(1, len(rotations)))(*rotations)
+        _check(lib().hs_add_rotation_keys(self.h, arr, len(rotations), 1 if conj else 0))
+
+    def key_export(self, key_id):
+        used = ctypes.c_size_t()
+        _check(lib().hs_key_export(self.h, key_id, np.zeros(1, np.uint64), 0, ctypes.byref(used)))
+        out = np.zeros(used.value, dtype=np.uint64)
+        _check(lib().hs_key_export(self.h, key_id, out, out.size, ctypes.byref(used)))
+        return out.reshape(self.dnum, 2, self.nq + self.np, self.N)
+
+    def secret(self):
+        out = np.zeros(self.N, dtype=np.int64)
+        _check(lib().hs_secret_export(self.h, out, out.size))
+        return out
+
+    def pk_export(self):
+        used = ctypes.c_size_t()
+        out = np.zeros(2 * self.nq * self.N, dtype=np.uint64)
+        _check(lib().hs_pk_export(self.h, out, out.size, ctypes.byref(used)))
+        return out.reshape(2, self.nq, self.N)
+
+    @staticmethod
+    def _slots(z):
+        z = np.asarray(z)
+        re = np.ascontiguousarray(z.real, dtype=np.float64)
+        im = np.ascontiguousarray(z.imag, dtype=np.float64) if np.iscomplexobj(z) else None
+        return re, im
+
+    def encode(self, z, level, scale):
+        re, im = self._slots(z)
+        out = np.zeros((level + 1) * self.N, dtype=np.uint64)
+        _check(lib().hs_encode(self.h, re, im.ctypes.data if im is not None else None, re.size, level, scale, out))
+        return out.reshape(level + 1, self.N)
+
+    def encrypt(self, z, level, scale, seed):
+        re, im = self._slots(z)
+        h = _vp()
+        _check(lib().hs_encode_encrypt(self.h, re, im.ctypes.data if im is not None else None, re.size, level,
+                                       scale, seed, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def encrypt_rows(self, pt, level, scale, seed):
+        h = _vp()
+        _check(lib().hs_encrypt_rows(self.h, np.ascontiguousarray(pt, dtype=np.uint64).reshape(-1), level, scale,
+                                     seed, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def decrypt(self, ct):
+        re = np.zeros(self.slots)
+        im = np.zeros(self.slots)
+        _check(lib().hs_decrypt_decode(self.h, ct.h, re, im.ctypes.data, self.slots))
+        return re + 1j * im
+
+    def import_ct(self, words, level, ncomp, scale):
+        h = _vp()
+        _check(lib().hs_ct_import(self.h, np.ascontiguousarray(words, dtype=np.uint64).reshape(-1), level, ncomp,
+                                  scale, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def _op(self, name, *args):
+        h = _vp()
+        _check(getattr(lib(), name)(self.h, *args, ctypes.byref(h)))
+        return Ciphertext(self, h)
+
+    def add(self, a, b):
+        return self._op("hs_add", a.h, b.h)
+
+    def sub(self, a, b):
+        return self._op("hs_sub", a.h, b.h)
+
+    def tensor(self, a, b):
+        return self._op("hs_tensor", a.h, b.h)
+
+    def relinearize(self, d):
+        return self._op("hs_relinearize", d.h)
+
+    def rescale(self, a):
+        return self._op("hs_rescale", a.h)
+
+    def mult(self, a, b, rescale=True):
+        return self._op("hs_mult_relin", a.h, b.h, 1 if rescale else 0)
+
+    def rotate(self, a, r):
+        return self._op("hs_rotate", a.h, r)
+
+    def conjugate(self, a):
+        return self._op("hs_conjugate", a.h)
+
+    def mul_plain_rows(self, a, pt, pt_scale, rescale=False):
+        return self._op("hs_mul_plain_rows", a.h, np.ascontiguousarray(pt, dtype=np.uint64).reshape(-1),
+                        pt_scale, 1 if rescale else 0)
+
+    def mul_int(self, a, k):
+        return self._op("hs_mul_int", a.h, int(k))
+
+    def add_const(self, a, v):
+        return self._op("hs_add_const", a.h, float(v))
+
+    def mod_drop(self, a, level):
+        return self._op("hs_mod_drop", a.h, level)
+
+    def mod_raise(self, a, level):
+        return self._op("hs_mod_raise", a.h, level)
+
+    def mul_monomial(self, a, k):
+        return self._op("hs_mul_monomial", a.h, k)
+
+    def bootstrap(self, a):
+        return self._op("hs_bootstrap", a.h)
+
+    def ntt(self, rows, prime, inverse=False):
+        x = np.ascontiguousarray(rows, dtype=np.uint64).copy()
+        _check(lib().hs_dbg_ntt(self.h, prime, x.reshape(-1), x.size // self.N, 1 if inverse else 0))
+        return x
