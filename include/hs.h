@@ -168,6 +168,52 @@ hs_status hs_mod_raise(hs_ctx* ctx, const hs_ct* a, int level, hs_ct** out);
 /* Multiply by the monomial X^k (k modulo 2N). */
 hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out);
 
+/* ---------------------------------------------------------------- Softmax
+ * Options of hs_softmax.  variant 0 = Algorithm SM (Section 3.2, with the
+ * auxiliary thread of Section 3.3 and the packing of Section 4); variant 1 =
+ * SM version B (Algorithm "alg:Softmax1B", Section 4.3).  k = 0 selects
+ * k = ceil(log2 M - log2 ln n) (Theorem "th:prec_softmax"). */
+typedef struct hs_softmax_opts {
+    int variant;
+    int k;
+    int exp_degree;       /* degree of the exp approximation (2^t - 1)        */
+    int inv_degree_first; /* degree of the first normalisation polynomial     */
+    int inv_degree_mid;   /* intermediate iterations                          */
+    int inv_degree_last;  /* last iteration                                   */
+    double alpha;         /* reserved (0)                                     */
+    int plain_per_ct;     /* reserved (0)                                     */
+} hs_softmax_opts;
+
+/* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n
+ * packed in the m ciphertexts in[0..m) (layout of hs_pack_softmax), all at
+ * the same level and scale, inputs in [-M, 0] (the paper's assumption of
+ * Section 3.1; values outside give unspecified results).  For the first step
+ * to cost no level, encrypt the inputs at scale 2^(log_scale + 1) / M.
+ * Writes m new handles to out[0..m).  Needs n a power of two, m | n,
+ * n <= N/2 (HS_E_PARAM / HS_E_ARG otherwise), enough levels or bootstrapping
+ * parameters (HS_E_LEVEL).  Rotation keys for strides +-L 2^t are generated
+ * on first use. */
+hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double M, const hs_softmax_opts* opts,
+                     hs_ct** out);
+/* Statistics of the last hs_softmax call: [k, bootstraps, levels_left,
+ * milliseconds]; writes min(n, 4) values. */
+hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n);
+
+/* Packing of Section 4 (host only).  logits: [L][n] row-major, L n =
+ * m (N/2); out: [m][slots] with ciphertext j holding coordinate
+ * j (n/m) + c of Softmax l in slot c L + l.  Checks every logit is in
+ * [-M, 0] (HS_E_RANGE otherwise). */
+hs_status hs_pack_softmax(const double* logits, size_t L, uint32_t n, size_t slots, double M, double* out,
+                          size_t* m_out);
+/* Inverse of hs_pack_softmax: slots [m][slots] -> out [L][n]. */
+hs_status hs_unpack_softmax(const double* slots_in, size_t m, uint32_t n, size_t slots, double* out);
+
+/* Bootstrapping: refresh a ciphertext (any level) to the top user level
+ * (CoeffToSlot, EvalMod, SlotToCoeff).  HS_E_PARAM without bootstrapping
+ * parameters; needs the conjugation and linear-transform rotation keys,
+ * generated on first use. */
+hs_status hs_bootstrap(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
+
 /* Raw negacyclic NTT (forward or inverse) of `nrows` rows of N residues
  * modulo prime index `prime` (host buffer, in place); for parity tests. */
 hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse);

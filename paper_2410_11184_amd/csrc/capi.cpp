@@ -6,9 +6,13 @@
 
 #include "../../include/hs.h"
 #include "host.h"
+#include "softmax.h"
+#include <chrono>
+#include <vector>
 
 struct hs_ctx {
     hs::Context* c;
+    double last_stats[4] = {0, 0, 0, 0};
 };
 struct hs_ct {
     hs::Context* c;
@@ -476,6 +480,105 @@ hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int i
         hs::k_ntt(c.T, r, inverse != 0, c.stream);
         c.download(rows, d, w * 8);
         c.free_words(d);
+    });
+}
+
+hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double M, const hs_softmax_opts* opts,
+                     hs_ct** out) {
+    if (out)
+        for (size_t i = 0; i < m; i++) out[i] = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(in);
+        NEED(out);
+        HS_REQUIRE(m >= 1, hs::E_ARG, "m must be >= 1");
+        hs::Context& c = *ctx->c;
+        std::vector<const hs::Ct*> parts;
+        for (size_t i = 0; i < m; i++) {
+            HS_REQUIRE(in[i] != nullptr, hs::E_ARG, "null input ciphertext");
+            HS_REQUIRE(in[i]->ct.scale == in[0]->ct.scale, hs::E_SCALE, "inputs must share one scale");
+            parts.push_back(&in[i]->ct);
+        }
+        hs::SoftmaxOpts o;
+        if (opts) {
+            o.variant = opts->variant;
+            o.k = opts->k;
+            if (opts->exp_degree > 0) o.exp_degree = opts->exp_degree;
+            if (opts->inv_degree_first > 0) o.inv_degree_first = opts->inv_degree_first;
+            if (opts->inv_degree_mid > 0) o.inv_degree_mid = opts->inv_degree_mid;
+            if (opts->inv_degree_last > 0) o.inv_degree_last = opts->inv_degree_last;
+        }
+        auto t0 = std::chrono::steady_clock::now();
+        hs::Ct batch = hs::ct_gather(c, parts);
+        hs::SoftmaxStats st;
+        hs::Ct y;
+        try {
+            y = hs::softmax(c, batch, (int)n, M, o, &st);
+        } catch (...) {
+            hs::ct_free(c, batch);
+            throw;
+        }
+        hs::ct_free(c, batch);
+        for (size_t i = 0; i < m; i++) out[i] = wrap(&c, hs::ct_slice(c, y, (int)i, 1));
+        hs::ct_free(c, y);
+        c.sync();
+        auto t1 = std::chrono::steady_clock::now();
+        ctx->last_stats[0] = st.k;
+        ctx->last_stats[1] = st.bootstraps;
+        ctx->last_stats[2] = st.levels_left;
+        ctx->last_stats[3] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    });
+}
+
+hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(out);
+        for (size_t i = 0; i < n && i < 4; i++) out[i] = ctx->last_stats[i];
+    });
+}
+
+hs_status hs_pack_softmax(const double* logits, size_t L, uint32_t n, size_t slots, double M, double* out,
+                          size_t* m_out) {
+    return guard([&] {
+        NEED(logits);
+        NEED(m_out);
+        HS_REQUIRE(n >= 1 && (n & (n - 1)) == 0 && n <= slots, hs::E_PARAM, "n must be a power of two <= slots");
+        HS_REQUIRE((L * n) % slots == 0 && L * n >= slots, hs::E_ARG, "L n must be a multiple of the slot count");
+        const size_t m = L * n / slots;
+        HS_REQUIRE(n % m == 0, hs::E_ARG, "m must divide n");
+        *m_out = m;
+        for (size_t i = 0; i < L * n; i++)
+            HS_REQUIRE(logits[i] >= -M && logits[i] <= 0.0, hs::E_RANGE, "logit outside [-M, 0]");
+        if (!out) return;
+        const size_t per = n / m;
+        for (size_t j = 0; j < m; j++)
+            for (size_t c = 0; c < per; c++)
+                for (size_t l = 0; l < L; l++) out[j * slots + c * L + l] = logits[l * n + j * per + c];
+    });
+}
+
+hs_status hs_unpack_softmax(const double* slots_in, size_t m, uint32_t n, size_t slots, double* out) {
+    return guard([&] {
+        NEED(slots_in);
+        NEED(out);
+        HS_REQUIRE(m >= 1 && n % m == 0 && (m * slots) % n == 0, hs::E_ARG, "bad shape");
+        const size_t L = m * slots / n, per = n / m;
+        for (size_t j = 0; j < m; j++)
+            for (size_t c = 0; c < per; c++)
+                for (size_t l = 0; l < L; l++) out[l * n + j * per + c] = slots_in[j * slots + c * L + l];
+    });
+}
+
+hs_status hs_bootstrap(hs_ctx* ctx, const hs_ct* a, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(hs::can_bootstrap(c), hs::E_PARAM, "no bootstrapping parameters");
+        *out = wrap(&c, hs::bootstrap(c, a->ct, 1.0));
     });
 }
 

@@ -136,6 +136,7 @@ struct Context {
     std::map<int, ConvDev> moddown;                 // level
     std::map<int, int*> perms;                      // galois element -> device perm
     std::map<int, u64*> monomials;                  // k -> NTT of X^k over all Q primes
+    std::map<int, double*> mask_coeffs;             // L -> coefficients of the slot mask [0, L)
     std::vector<void*> owned;                       // device tables
     std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
 

@@ -1,0 +1,301 @@
+// Polynomial approximation and homomorphic polynomial evaluation.
+//
+// The paper evaluates exp and x^(-1/2^j) by polynomial approximations of
+// degree 2^t - 1 (Section 5.1, "Designing auxiliary functions"), in
+// ceil(log(d+1)) levels and O(sqrt d) products (Section 2.2, "Functions as
+// polynomials", Paterson-Stockmeyer).  Here:
+//  * coefficients: Chebyshev interpolation at the d+1 first-kind nodes,
+//    computed in long double;
+//  * evaluation: baby-step giant-step in the Chebyshev basis.  Baby steps
+//    T_1..T_{B-1} by T_2k = 2 T_k^2 - 1 and T_2k+1 = 2 T_k T_k+1 - T_1; giant
+//    steps T_B, T_2B, ...; the polynomial splits as q_lo + q_hi T_n
+//    (T_n+i = 2 T_n T_i - T_n-i).  Every addition is scale-exact: each leaf
+//    sum_j c_j T_j multiplies T_j by the integer rint(c_j S q / s_j) so that
+//    all terms share the scale S q before the single rescale of the leaf.
+//    Depth: ceil(log2(d+1)) + 1 (the +1 is the leaf's constant products).
+#include <cmath>
+#include <functional>
+#include <map>
+
+#include "host.h"
+#include "poly.h"
+
+namespace hs {
+
+ChebPoly cheb_fit(const std::function<long double(long double)>& f, double a, double b, int d) {
+    ChebPoly p;
+    p.a = a;
+    p.b = b;
+    p.c.assign(d + 1, 0.0);
+    std::vector<long double> fx(d + 1);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k <= d; k++) {
+        const long double u = cosl(pi * (k + 0.5L) / (d + 1));
+        const long double x = (u * ((long double)b - a) + (long double)a + b) / 2;
+        fx[k] = f(x);
+    }
+    for (int j = 0; j <= d; j++) {
+        long double s = 0;
+        for (int k = 0; k <= d; k++) s += fx[k] * cosl(pi * j * (k + 0.5L) / (d + 1));
+        long double cj = 2.0L / (d + 1) * s;
+        if (j == 0) cj /= 2;
+        p.c[j] = (double)cj;
+    }
+    return p;
+}
+
+double cheb_eval_plain(const ChebPoly& p, double x) {
+    const double u = (2 * x - p.a - p.b) / (p.b - p.a);
+    double b1 = 0, b2 = 0;
+    for (int j = (int)p.c.size() - 1; j >= 1; j--) {
+        const double t = 2 * u * b1 - b2 + p.c[j];
+        b2 = b1;
+        b1 = t;
+    }
+    return u * b1 - b2 + p.c[0];
+}
+
+static int ceil_log2(int x) {
+    int l = 0;
+    while ((1 << l) < x) l++;
+    return l;
+}
+
+int cheb_depth(int degree) { return ceil_log2(degree + 1) + 1; }
+
+// ---------------------------------------------------------------- evaluator
+namespace {
+
+struct Val {
+    bool is_const = false;
+    double cval = 0;
+    Ct ct;
+};
+
+struct Evaluator {
+    Context& c;
+    std::map<int, Ct> T;          // Chebyshev basis polynomials of u
+    std::map<std::pair<int, long long>, Ct> t1_at;  // T_1 adjusted to (level, scale key)
+    int B = 2;
+    // When set: every leaf constant c is replaced by the plaintext c * mask
+    // (mask = device coefficients of a 0/1 slot vector), which multiplies the
+    // whole polynomial by the mask since mask^2 = mask.
+    const double* mask = nullptr;
+
+    // NTT-domain rows 0..lv of rint(scale * mask), in a pool buffer
+    u64* mask_pt(double scale, int lv) {
+        u64* pt = c.alloc_words((size_t)(lv + 1) * c.N);
+        Rows r = c.rows(pt, 1, lv + 1, (size_t)(lv + 1) * c.N);
+        k_encode_real(c.T, r, mask, 0, scale, c.stream);
+        k_ntt(c.T, r, false, c.stream);
+        return pt;
+    }
+
+    // a (level lv) * (value * mask) with the product at scale a.scale * pscale
+    Ct mul_mask(const Ct& a, double value, double pscale) {
+        u64* pt = mask_pt(value * pscale, a.level);
+        Ct o = op_mul_plain(c, a, pt, pscale, false);
+        c.free_words(pt);
+        return o;
+    }
+
+    void add_mask_const(Ct& a, double value) {
+        u64* pt = mask_pt(value * a.scale, a.level);
+        Rows r0 = c.comp_rows(a, 0);
+        Rows rp{pt, a.m, a.level + 1, 0, a.level + 1, 0, c.nq};
+        k_add(c.T, r0, r0, rp, c.stream);
+        c.free_words(pt);
+    }
+
+    explicit Evaluator(Context& cc) : c(cc) {}
+    ~Evaluator() {
+        for (auto& kv : T) ct_free(c, kv.second);
+        for (auto& kv : t1_at) ct_free(c, kv.second);
+    }
+
+    // T_1 brought to (level, scale) by a scale-exact constant product
+    const Ct& t1_adjusted(int level, double scale) {
+        long long key = (long long)std::llround(std::log2(scale) * 1e6);
+        auto k = std::make_pair(level, key);
+        auto it = t1_at.find(k);
+        if (it != t1_at.end()) return it->second;
+        const Ct& t1 = T.at(1);
+        HS_REQUIRE(t1.level > level, E_LEVEL, "polynomial evaluation: level budget exhausted");
+        Ct d = ct_drop(c, t1, level + 1);
+        Ct r = op_mul_const(c, d, 1.0, scale);
+        ct_free(c, d);
+        return t1_at.emplace(k, r).first->second;
+    }
+
+    Ct mult_aligned(const Ct& a, const Ct& b) { return op_mult(c, a, b); }
+
+    void build_T(int j) {
+        if (T.count(j)) return;
+        if (j % 2 == 0) {
+            build_T(j / 2);
+            Ct s = mult_aligned(T.at(j / 2), T.at(j / 2));
+            op_mul_int_inplace(c, s, 2);
+            op_add_const_inplace(c, s, -1.0);
+            T[j] = s;
+        } else {
+            build_T((j + 1) / 2);
+            build_T((j - 1) / 2);
+            Ct s = mult_aligned(T.at((j + 1) / 2), T.at((j - 1) / 2));
+            op_mul_int_inplace(c, s, 2);
+            const Ct& t1 = t1_adjusted(s.level, s.scale);
+            op_sub_inplace(c, s, t1);
+            T[j] = s;
+        }
+    }
+
+    // sum_j coef[j] T_j at (scale S, level lv); one rescale
+    Val leaf(const std::vector<double>& coef, double S, int lv) {
+        int deg = (int)coef.size() - 1;
+        while (deg > 0 && coef[deg] == 0.0) deg--;
+        Val v;
+        if (deg == 0) {
+            v.is_const = true;
+            v.cval = coef.empty() ? 0.0 : coef[0];
+            return v;
+        }
+        const double ql = (double)c.primes[lv + 1];
+        Ct acc;
+        bool have = false;
+        for (int j = 1; j <= deg; j++) {
+            if (coef[j] == 0.0) continue;
+            build_T(j);
+            const Ct& tj = T.at(j);
+            HS_REQUIRE(tj.level >= lv + 1, E_LEVEL, "polynomial evaluation: level budget exhausted");
+            Ct d = ct_drop(c, tj, lv + 1);
+            if (mask) {
+                Ct md = mul_mask(d, coef[j], S * ql / tj.scale);
+                ct_free(c, d);
+                md.scale = S * ql;
+                if (!have) {
+                    acc = md;
+                    have = true;
+                } else {
+                    op_add_inplace(c, acc, md);
+                    ct_free(c, md);
+                }
+                continue;
+            }
+            const double K = std::rint(coef[j] * S * ql / tj.scale);
+            std::vector<u64> res(lv + 2);
+            {
+                const bool neg = K < 0;
+                const double a = std::fabs(K);
+                for (int i = 0; i <= lv + 1; i++) {
+                    const u64 q = c.primes[i];
+                    u64 m;
+                    if (a < 9.2e18) {
+                        m = (u64)a % q;
+                    } else {
+                        int e;
+                        const double mant = std::frexp(a, &e);
+                        const u64 mi = (u64)std::ldexp(mant, 53);
+                        m = mulmod_h(mi % q, powmod_h(2, (u64)(e - 53), q), q);
+                    }
+                    res[i] = (neg && m) ? q - m : m;
+                }
+            }
+            op_mul_residues_inplace(c, d, res);
+            d.scale = S * ql;
+            if (!have) {
+                acc = d;
+                have = true;
+            } else {
+                op_add_inplace(c, acc, d);
+                ct_free(c, d);
+            }
+        }
+        if (mask) add_mask_const(acc, coef[0]);
+        else op_add_const_inplace(c, acc, coef[0]);
+        v.ct = op_rescale(c, acc);
+        ct_free(c, acc);
+        v.ct.scale = S;
+        return v;
+    }
+
+    Val eval(const std::vector<double>& coef, double S, int lv) {
+        int deg = (int)coef.size() - 1;
+        while (deg > 0 && coef[deg] == 0.0) deg--;
+        if (deg < B) return leaf(std::vector<double>(coef.begin(), coef.begin() + deg + 1), S, lv);
+        int n = B;
+        while (2 * n <= deg) n *= 2;
+        // p = q_lo + q_hi T_n
+        std::vector<double> hi(deg - n + 1), lo(n);
+        hi[0] = coef[n];
+        for (int k = 1; k <= deg - n; k++) hi[k] = 2 * coef[n + k];
+        for (int j = 0; j < n; j++) lo[j] = coef[j];
+        for (int k = 1; k <= deg - n; k++) lo[n - k] -= coef[n + k];
+        build_T(n);
+        const Ct& G = T.at(n);
+        HS_REQUIRE(G.level >= lv + 1, E_LEVEL, "polynomial evaluation: level budget exhausted");
+        const double ql = (double)c.primes[lv + 1];
+        Val vh = eval(hi, S * ql / G.scale, lv + 1);
+        Val out;
+        Ct g = ct_drop(c, G, lv + 1);
+        if (vh.is_const && mask) {
+            Ct t = mul_mask(g, vh.cval, S * ql / g.scale);
+            out.ct = op_rescale(c, t);
+            ct_free(c, t);
+            out.ct.scale = S;
+        } else if (vh.is_const) {
+            out.ct = op_mul_const(c, g, vh.cval, S);
+        } else {
+            Ct d = op_tensor(c, vh.ct, g);
+            Ct r = op_relin(c, d);
+            ct_free(c, d);
+            out.ct = op_rescale(c, r);
+            ct_free(c, r);
+            ct_free(c, vh.ct);
+            out.ct.scale = S;
+        }
+        ct_free(c, g);
+        Val vl = eval(lo, S, lv);
+        if (vl.is_const && mask) {
+            add_mask_const(out.ct, vl.cval);
+        } else if (vl.is_const) {
+            op_add_const_inplace(c, out.ct, vl.cval);
+        } else {
+            op_add_inplace(c, out.ct, vl.ct);
+            ct_free(c, vl.ct);
+        }
+        return out;
+    }
+};
+
+}  // namespace
+
+Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, const double* mask) {
+    const int d = (int)p.c.size() - 1;
+    HS_REQUIRE(d >= 1, E_ARG, "polynomial degree must be >= 1");
+    // affine map to u in [-1, 1]: u = alpha x + beta
+    const double alpha = 2.0 / (p.b - p.a);
+    const double beta = -(p.a + p.b) / (p.b - p.a);
+    Ct u;
+    int ea = 0;
+    const double fa = std::frexp(alpha, &ea);  // alpha = fa 2^ea, fa in [0.5, 1)
+    if (fa == 0.5 && ea >= 1) {
+        // alpha = 2^(ea-1) >= 1: integer product, no level used
+        u = ct_copy(c, x);
+        op_mul_int_inplace(c, u, 1LL << (ea - 1));
+    } else {
+        HS_REQUIRE(x.level >= 1, E_LEVEL, "polynomial evaluation: level budget exhausted");
+        u = op_mul_const(c, x, alpha, std::ldexp(1.0, c.prm.log_scale));
+    }
+    op_add_const_inplace(c, u, beta);
+    const int t = ceil_log2(d + 1);
+    const int out_level = u.level - (t + 1);
+    HS_REQUIRE(out_level >= 0, E_LEVEL, "polynomial evaluation: level budget exhausted");
+    Evaluator ev(c);
+    ev.mask = mask;
+    ev.B = 1 << std::max(1, (t + 1) / 2);
+    ev.T[1] = u;
+    Val v = ev.eval(p.c, target_scale, out_level);
+    HS_REQUIRE(!v.is_const, E_ARG, "constant polynomial");
+    return v.ct;
+}
+
+}  // namespace hs

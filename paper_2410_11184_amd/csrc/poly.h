@@ -1,0 +1,25 @@
+// Chebyshev approximations and their homomorphic evaluation.
+#pragma once
+#include <functional>
+#include <vector>
+
+#include "host.h"
+
+namespace hs {
+
+// p(x) = sum_j c[j] T_j((2x - a - b) / (b - a)) on [a, b]
+struct ChebPoly {
+    double a = -1, b = 1;
+    std::vector<double> c;
+};
+
+ChebPoly cheb_fit(const std::function<long double(long double)>& f, double a, double b, int degree);
+double cheb_eval_plain(const ChebPoly& p, double x);
+int cheb_depth(int degree);   // levels used by eval_cheb (plus 1 if the affine map needs one)
+// Evaluate p on every slot of the batch x; result at scale target_scale.
+// With `mask` (device array of the N real coefficients of a 0/1 slot vector,
+// laid out as encode_to lays out w), the result is p(x) * mask at no extra
+// level: every leaf constant becomes a masked plaintext.
+Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, const double* mask = nullptr);
+
+}  // namespace hs

@@ -1,0 +1,259 @@
+// Homomorphic Softmax by normalize-and-square.
+//
+//  * Algorithm SM (Section 3.2): y0 = exp(x / 2^k); for j = 1..k:
+//    lambda_j = (sum_i y_i^2)^(-1/2), z = lambda_j y, y = z^2.
+//  * The auxiliary thread (Algorithm "alg:AuxThread", Section 3.3): square,
+//    rotate-and-add with strides -L 2^t, the normalisation polynomial, mask
+//    to slots [0, L), rotate-and-add with strides +L 2^t.
+//  * Many ciphertexts (Section 4.2): m ciphertexts hold L = m N0 / n Softmax;
+//    the squares of all m are summed into one auxiliary ciphertext before the
+//    log2(n/m) rotations, and one auxiliary thread serves all of them.
+//  * Version B (Algorithm "alg:Softmax1B", Section 4.3): lambda_j =
+//    (sum y^(j-1)^2)^(-2^-j), Lambda *= lambda_j, z = Lambda y0,
+//    y^(j) = z^(2^j), so the main thread spends one level per iteration plus
+//    the squarings.  Its last iteration is evaluated as one normalize-and-
+//    square step on y^(k-1), y^(k) = (S_k^(-1/2) y^(k-1))^2, which is the same
+//    value (Lambda_k^(2^k) y0^(2^k) = y^(k-1)^2 / S_k) with two main-thread
+//    levels and an error that is not amplified by 2^k.
+//  * Bootstraps follow the rules of Section 5.1 ("Bootstrapping strategy in
+//    the many ciphertexts case"): bootstrap the auxiliary ciphertext before
+//    the normalisation polynomial when its budget is short, again afterwards
+//    if its level is below what the main thread needs, and the main thread
+//    only when its own budget runs out.
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+#include "poly.h"
+#include "softmax.h"
+
+namespace hs {
+
+// device coefficients of the 0/1 slot vector with ones on slots [0, L)
+static const double* mask_coeffs(Context& c, int L) {
+    auto it = c.mask_coeffs.find(L);
+    if (it != c.mask_coeffs.end()) return it->second;
+    const int n = c.N / 2;
+    std::vector<double> re(n, 0.0), im(n, 0.0);
+    for (int j = 0; j < L; j++) re[j] = 1.0;
+    special_fft_inverse(c, re, im);
+    std::vector<double> w(c.N);
+    for (int k = 0; k < n; k++) {
+        w[k] = re[k];
+        w[k + n] = im[k];
+    }
+    double* d = (double*)c.dev_table(w.data(), sizeof(double) * c.N);
+    c.mask_coeffs[L] = d;
+    return d;
+}
+
+int theorem_k(int n, double M) {
+    const double v = std::ceil(std::log2(M) - std::log2(std::log((double)n)));
+    return std::max(1, (int)v);
+}
+
+static int ilog2(int x) {
+    int l = 0;
+    while ((1 << l) < x) l++;
+    return l;
+}
+
+// max over a dense grid of |p(s) s^e - 1| on [lo, hi]
+static double rel_error(const ChebPoly& p, double lo, double hi, double e) {
+    double worst = 0;
+    const int G = 4000;
+    for (int i = 0; i <= G; i++) {
+        // geometric grid (the error is largest near the lower end)
+        const double s = lo * std::pow(hi / lo, (double)i / G);
+        worst = std::max(worst, std::fabs(cheb_eval_plain(p, s) * std::pow(s, e) - 1.0));
+    }
+    return worst;
+}
+
+static double max_abs(const ChebPoly& p, double lo, double hi) {
+    double m = 0;
+    for (int i = 0; i <= 2000; i++) m = std::max(m, std::fabs(cheb_eval_plain(p, lo + (hi - lo) * i / 2000.0)));
+    return m;
+}
+
+// Chebyshev interval [a, a + 2^e] covering [lo, hi] with 2^e <= 2 (so the
+// affine map to [-1, 1] is an integer product and a constant addition)
+static void free_interval(double lo, double hi, double& a, double& b) {
+    a = lo;
+    double w = 1.0;
+    while (w < hi - lo) w *= 2;
+    while (w / 2 >= hi - lo && w > 1.0 / 64) w /= 2;
+    b = a + w;
+}
+
+// bound on |Lambda| used to scale it into the bootstrapping range
+static double lam_bound_big(Context&, const Ct&, double lam_bound) { return std::max(64.0, lam_bound); }
+
+static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxStats& st, bool& replaced) {
+    replaced = false;
+    if (x.level >= need) return x;
+    HS_REQUIRE(can_bootstrap(c), E_LEVEL, "Softmax: level budget exhausted and no bootstrapping configured");
+    Ct b = bootstrap(c, x, bound);
+    st.bootstraps += x.m;
+    replaced = true;
+    HS_REQUIRE(b.level >= need, E_LEVEL, "Softmax: bootstrapping does not restore enough levels");
+    return b;
+}
+
+Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats) {
+    SoftmaxStats st;
+    const int N0 = c.N / 2;
+    const int m = x.m;
+    HS_REQUIRE(n >= 2 && (n & (n - 1)) == 0, E_PARAM, "Softmax dimension must be a power of two >= 2");
+    HS_REQUIRE(n <= N0 && m >= 1 && n % m == 0, E_ARG, "need m | n <= N/2");
+    HS_REQUIRE(M > 0, E_ARG, "range M must be positive");
+    HS_REQUIRE(x.ncomp == 2, E_ARG, "degree-1 ciphertexts expected");
+    const int L = (int)((long long)m * N0 / n);
+    const int k = o.k > 0 ? o.k : theorem_k(n, M);
+    const int per = n / m;
+    const int nrot = ilog2(per);
+    const bool smb = o.variant == 1;
+    const double Delta = std::ldexp(1.0, c.prm.log_scale);
+    // rotation keys for the rotate-and-add loops (strides +-L 2^t)
+    for (int t = 0; t < nrot; t++) {
+        add_galois_key(c, galois_rot(-(L << t), c.N));
+        add_galois_key(c, galois_rot(L << t, c.N));
+    }
+    // v = 2x / M in [-2, 0]: a change of the declared scale when the input
+    // was encrypted at scale ~ 2 Delta / M, otherwise one constant product.
+    Ct v;
+    const double vs = x.scale * M / 2.0;
+    if (std::fabs(std::log2(vs) - c.prm.log_scale) <= 2.0) {
+        v = ct_copy(c, x);
+        v.scale = vs;
+    } else {
+        v = op_mul_const(c, x, 2.0 / M, Delta);
+    }
+    // y0 = exp(x / 2^k) / sqrt(n)  (the 1/sqrt(n) keeps sum y0^2 in [e^(-2M/2^k), 1])
+    const double isn = 1.0 / std::sqrt((double)n);
+    const long double Ml = M;
+    const int kk = k;
+    ChebPoly pexp = cheb_fit([&](long double t) { return expl(Ml * t / ldexpl(1.0L, kk + 1)) * (long double)isn; },
+                             -2.0, 0.0, o.exp_degree);
+    Ct y0 = eval_cheb(c, v, pexp, Delta);
+    ct_free(c, v);
+    const double* mask = mask_coeffs(c, L);
+
+    Ct y = ct_copy(c, y0);      // y^(j-1)
+    Ct big;                     // Lambda (version B)
+    bool have_big = false;
+    double lo = std::exp(-2.0 * M / std::ldexp(1.0, k)) * 0.98, hi = 1.0;
+    for (int j = 1; j <= k; j++) {
+        const bool last = j == k;
+        const bool smb_step = smb && !last;
+        // exponent of the normalisation: 1/2 (SM, and the last step of B) or 2^-j
+        const double e = smb_step ? std::ldexp(1.0, -j) : 0.5;
+        const int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
+        double a, b;
+        free_interval(lo, hi, a, b);
+        const double ee = e;
+        ChebPoly pinv = cheb_fit([&](long double s) { return powl(s, -(long double)ee); }, a, b, deg);
+        const double delta = rel_error(pinv, lo, hi, e);
+        const double lam_bound = max_abs(pinv, lo, hi) * 1.05;
+        // main thread must keep one level for the square feeding S
+        if (!smb) {
+            bool rep;
+            Ct y2 = ensure_level(c, y, last ? 2 : 3, 1.0, st, rep);
+            if (rep) {
+                ct_free(c, y);
+                y = y2;
+            }
+        }
+        // AUX step 1: S = sum over the m ciphertexts of y^2 (one relinearisation)
+        Ct d = op_square_sum(c, y);
+        Ct r = op_relin(c, d);
+        ct_free(c, d);
+        Ct S = op_rescale(c, r);
+        ct_free(c, r);
+        // AUX steps 2-4: rotate-and-add with strides -L 2^t
+        for (int t = 0; t < nrot; t++) {
+            Ct rr = op_rotate(c, S, -(L << t));
+            op_add_inplace(c, S, rr);
+            ct_free(c, rr);
+        }
+        // AUX step 5 budget: the polynomial (mask folded into its leaves)
+        {
+            bool rep;
+            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 1, hi * 1.1, st, rep);
+            if (rep) {
+                ct_free(c, S);
+                S = S2;
+            }
+        }
+        // AUX steps 5-6: lambda = P(S) * mask
+        Ct lam = eval_cheb(c, S, pinv, Delta, mask);
+        ct_free(c, S);
+        // AUX steps 7-9: broadcast slots [0, L) to all n/m positions
+        for (int t = 0; t < nrot; t++) {
+            Ct rr = op_rotate(c, lam, L << t);
+            op_add_inplace(c, lam, rr);
+            ct_free(c, rr);
+        }
+        if (!smb_step) {
+            // SM step (and the last step of version B): z = lambda y, y = z^2
+            if (!last && can_bootstrap(c) && lam.level < y.level) {
+                bool rep;
+                Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep);
+                if (rep) {
+                    ct_free(c, lam);
+                    lam = l2;
+                }
+            }
+            Ct z = op_mult(c, y, lam);
+            ct_free(c, lam);
+            ct_free(c, y);
+            y = op_mult(c, z, z);
+            ct_free(c, z);
+            lo = std::pow(1.0 - delta, 4.0) / n * 0.98;
+            hi = std::pow(1.0 + delta, 4.0) * 1.0001;
+        } else {
+            // version B: Lambda = Lambda * lambda_j; z = Lambda y0; y = z^(2^j)
+            if (!have_big) {
+                big = lam;
+                have_big = true;
+            } else {
+                Ct nb = op_mult(c, big, lam);
+                ct_free(c, big);
+                ct_free(c, lam);
+                big = nb;
+            }
+            // y^(j) = (Lambda y0)^(2^j) must keep r levels: 1 for the next
+            // S, 2 before the final normalize-and-square step
+            const int r = (j == k - 1) ? 2 : 1;
+            const int want = j + 1 + r;
+            HS_REQUIRE(y0.level >= want, E_LEVEL, "Softmax version B: main-thread level budget exhausted");
+            if (big.level < want) {
+                bool rep;
+                Ct b2 = ensure_level(c, big, want, lam_bound_big(c, big, lam_bound), st, rep);
+                if (rep) {
+                    ct_free(c, big);
+                    big = b2;
+                }
+            }
+            Ct z = op_mult(c, y0, big);
+            ct_free(c, y);
+            y = z;
+            for (int s = 0; s < j; s++) {
+                Ct y2 = op_mult(c, y, y);
+                ct_free(c, y);
+                y = y2;
+            }
+            const double ej = std::ldexp(1.0, j + 1);
+            lo = std::pow(1.0 - delta, ej) / n * 0.98;
+            hi = std::pow(1.0 + delta, ej) * 1.0001;
+        }
+        st.levels_left = y.level;
+    }
+    ct_free(c, y0);
+    if (have_big) ct_free(c, big);
+    st.k = k;
+    if (stats) *stats = st;
+    return y;
+}
+
+}  // namespace hs

@@ -109,6 +109,9 @@ def lib():
         "hs_softmax": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_uint32, ctypes.c_double,
                        ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_stats": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+        "hs_pack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double, _vp,
+                            ctypes.POINTER(ctypes.c_size_t)],
+        "hs_unpack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, _f64p],
     }
     for name, args in list(sig.items()) + list(optional.items()):
         if not hasattr(L, name):
@@ -333,7 +336,42 @@ class Context:
     def bootstrap(self, a):
         return self._op("hs_bootstrap", a.h)
 
+    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0)):
+        """hs_softmax over the packed ciphertexts `cts`; returns new handles."""
+        m = len(cts)
+        arr = (_vp * m)(*[c.h for c in cts])
+        out = (_vp * m)()
+        o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
+                            inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
+                            plain_per_ct=0)
+        _check(lib().hs_softmax(self.h, arr, m, n, M, ctypes.byref(o), out))
+        return [Ciphertext(self, _vp(out[i])) for i in range(m)]
+
+    def softmax_stats(self):
+        buf = (ctypes.c_double * 4)()
+        _check(lib().hs_softmax_stats(self.h, buf, 4))
+        return dict(k=int(buf[0]), bootstraps=int(buf[1]), levels_left=int(buf[2]), ms=float(buf[3]))
+
     def ntt(self, rows, prime, inverse=False):
         x = np.ascontiguousarray(rows, dtype=np.uint64).copy()
         _check(lib().hs_dbg_ntt(self.h, prime, x.reshape(-1), x.size // self.N, 1 if inverse else 0))
         return x
+
+
+def pack_softmax(logits, slots, M):
+    """hs_pack_softmax: (L, n) logits -> (m, slots) slot vectors."""
+    logits = np.ascontiguousarray(logits, dtype=np.float64)
+    L, n = logits.shape
+    m = ctypes.c_size_t()
+    _check(lib().hs_pack_softmax(logits.reshape(-1), L, n, slots, M, None, ctypes.byref(m)))
+    out = np.zeros((m.value, slots))
+    _check(lib().hs_pack_softmax(logits.reshape(-1), L, n, slots, M, out.ctypes.data, ctypes.byref(m)))
+    return out
+
+
+def unpack_softmax(slot_vecs, n):
+    slot_vecs = np.ascontiguousarray(slot_vecs, dtype=np.float64)
+    m, slots = slot_vecs.shape
+    out = np.zeros((m * slots // n, n))
+    _check(lib().hs_unpack_softmax(slot_vecs.reshape(-1), m, n, slots, out))
+    return out

@@ -1,0 +1,59 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/hs.h, and its host-only entry points (packing of
+Section 4, parameter validation messages) behave; no GPU call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_11184_amd import hs
+    L = hs.lib()
+    names = _declared()
+    assert len(names) > 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert L.hs_version().decode().startswith("hs")
+
+
+@pytest.mark.parametrize("m", [1, 4])
+def test_pack_matches_oracle_layout(m):
+    from paper_2410_11184_amd import hs
+    from oracle import softmax as S
+    slots, n = 1024, 64
+    L = m * slots // n
+    x = np.random.default_rng(m).uniform(-10, 0, (L, n))
+    p = hs.pack_softmax(x, slots, 10.0)
+    assert p.shape == (m, slots)
+    assert np.array_equal(p, S.pack(x, m, slots))
+    assert np.array_equal(hs.unpack_softmax(p, n), x)
+
+
+def test_pack_range_check():
+    from paper_2410_11184_amd import hs
+    x = np.zeros((16, 64))
+    x[2, 2] = -10.5
+    with pytest.raises(hs.HSError) as e:
+        hs.pack_softmax(x, 1024, 10.0)
+    assert e.value.name == "HS_E_RANGE"
+    with pytest.raises(hs.HSError):
+        hs.pack_softmax(np.zeros((16, 48)), 1024, 10.0)    # n not a power of two
+
+
+def test_last_error_is_thread_local_string():
+    from paper_2410_11184_amd import hs
+    L = hs.lib()
+    st = L.hs_pack_softmax(np.zeros(4), 1, 3, 8, 1.0, None, ctypes.byref(ctypes.c_size_t()))
+    assert st == -2
+    assert b"power of two" in L.hs_last_error()

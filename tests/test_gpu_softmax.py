@@ -1,0 +1,79 @@
+"""Encrypted Softmax on the GPU against the FP64 definition.
+
+The method approximates Softmax (polynomial exp and normalisation factors),
+so the check is the spec precision bar, >= 16 bits worst case against
+the FP64 Softmax, plus the paper's invariants: rows sum to 1, special cases.
+Toy parameters (N = 2^12, 23 levels, no bootstrapping)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import softmax as S
+
+pytestmark = pytest.mark.gpu
+
+TOY = dict(exp_degree=7, inv_degrees=(15, 15, 31))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_11184_amd import hs
+    c = hs.Context(synthetic.preset("toy12"))
+    c.keygen(99)
+    return c
+
+
+def _run(ctx, x, M, variant="SM", **kw):
+    from paper_2410_11184_amd.softmax import softmax_encrypted
+    args = dict(TOY)
+    args.update(kw)
+    return softmax_encrypted(ctx, x, M, variant=variant, seed=5, **args)
+
+
+@pytest.mark.parametrize("variant", ["SM", "B"])
+def test_toy_workload_precision(ctx, variant):
+    x = synthetic.workload_logits("toy12_sm")          # 128 x 16, U[-8, 0]
+    y = _run(ctx, x, 8.0, variant)
+    ref = S.softmax(x)
+    bits = S.precision_bits(ref, y)
+    print(variant, bits, ctx.softmax_stats())
+    assert bits["worst"] >= 16.0, bits
+    assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -14
+
+
+def test_many_ciphertexts(ctx):
+    # m = 2 ciphertexts, L = m N0 / n = 256 Softmax of dimension 16
+    x = synthetic.logits_paper(256, 16, 8.0, seed=3)
+    y = _run(ctx, x, 8.0, "SM")
+    bits = S.precision_bits(S.softmax(x), y)
+    assert bits["worst"] >= 16.0, bits
+
+
+def test_special_cases(ctx):
+    n, L = 16, 128
+    x = np.full((L, n), -3.0)                            # all equal -> 1/n
+    x[1::2, 5] = 0.0                                     # one-hot-ish rows
+    x[1::2, :5] = -8.0
+    x[1::2, 6:] = -8.0
+    y = _run(ctx, x, 8.0, "SM")
+    assert np.max(np.abs(y[0::2] - 1.0 / n)) < 2 ** -16
+    want = 1.0 / (1.0 + (n - 1) * np.exp(-8.0))
+    assert np.max(np.abs(y[1::2, 5] - want)) < 2 ** -16
+
+
+def test_out_of_range_rejected_at_pack_time(ctx):
+    from paper_2410_11184_amd import hs
+    x = np.full((128, 16), -1.0)
+    x[3, 3] = 0.5
+    with pytest.raises(hs.HSError) as e:
+        hs.pack_softmax(x, ctx.slots, 8.0)
+    assert e.value.name == "HS_E_RANGE"
+
+
+def test_bad_dimension(ctx):
+    from paper_2410_11184_amd import hs
+    x = np.zeros((1, ctx.slots))
+    cts = [ctx.encrypt(x[0], ctx.user_top, ctx.delta, 1)]
+    with pytest.raises(hs.HSError) as e:
+        ctx.softmax(cts, 12, 8.0)
+    assert e.value.name == "HS_E_PARAM"
