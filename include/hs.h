@@ -104,7 +104,8 @@ hs_status hs_ctx_primes(const hs_ctx* ctx, uint64_t* out, size_t cap, size_t* n)
 hs_status hs_sync(hs_ctx* ctx);
 
 /* KeyGen (Section 2.2): secret, public and relinearisation keys from one
- * 64-bit seed (Philox4x32-10 draws; see DESIGN notes in the source). */
+ * 64-bit seed.  Every draw is Philox4x32-10 (Salmon et al., SC11) with
+ * key = seed and counter = (coefficient index, 64-bit domain tag). */
 hs_status hs_keygen(hs_ctx* ctx, uint64_t seed);
 /* Rotation keys for the given left-rotation steps (any sign, modulo N/2),
  * and the conjugation key when conj != 0. */
@@ -213,6 +214,22 @@ hs_status hs_unpack_softmax(const double* slots_in, size_t m, uint32_t n, size_t
  * parameters; needs the conjugation and linear-transform rotation keys,
  * generated on first use. */
 hs_status hs_bootstrap(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
+
+/* Launch profiling with HIP events on the context's stream.  When enabled,
+ * every launch of the NTT, key-switching inner product, base conversion,
+ * tensor, elementwise, permutation and lift kernels records an event pair and
+ * its algorithmic bytes (compulsory reads and writes).  hs_prof_collect
+ * waits for the recorded events and writes, for kinds 0..7 (NTT, KEYIP,
+ * CONV, TENSOR, EW, PERM, LIFT, OTHER), [launches, milliseconds, bytes]
+ * (n >= 24), then clears the record. */
+hs_status hs_prof_enable(hs_ctx* ctx, int on);
+hs_status hs_prof_collect(hs_ctx* ctx, double* out, size_t n);
+
+/* Intermediate ciphertexts of hs_bootstrap, for tests: stage 1 = after
+ * ModRaise (declared scale 2 q0 (K+1) N/2), 2 = after CoeffToSlot, 3 = real
+ * part after the conjugation split, 4 = real part after the cosine
+ * polynomial, 5 = real part after the double-angle steps. */
+hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct** out);
 
 /* Raw negacyclic NTT (forward or inverse) of `nrows` rows of N residues
  * modulo prime index `prime` (host buffer, in place); for parity tests. */

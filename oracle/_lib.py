@@ -53,6 +53,7 @@ def lib():
             getattr(L, name).argtypes = [_u64p, _u64p, _u64p, _u64, _u64]
         L.or_vec_scalar_mul.argtypes = [_u64p, _u64, _u64p, _u64, _u64]
         L.or_base_convert.argtypes = [_u64p, _u64p, ctypes.c_int, _u64p, _u64p, ctypes.c_int, _u64]
+        L.or_base_convert_centered.argtypes = [_u64p, _u64p, ctypes.c_int, _u64p, _u64p, ctypes.c_int, _u64]
         L.or_automorph_perm.argtypes = [_u64, _u64, _u64p]
         L.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.or_draw_block.argtypes = [_u64, _u64, _u64, _u32p]

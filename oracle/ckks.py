@@ -14,7 +14,9 @@ below follows the textbook RNS-CKKS definitions:
   * level l means limbs q[0..l]; rescale divides by q[l] with centred
     rounding; the scale of a ciphertext is tracked as an FP64 number;
   * key switching is the hybrid (digit-decomposed, special-modulus) method:
-    digits are consecutive blocks of `digit` primes, P = prod p[*];
+    digits are consecutive blocks of `digit` primes, P = prod p[*]; ModUp
+    uses the plain fast base conversion (its error is cancelled by the key),
+    ModDown the centred one (its error becomes zero-mean noise);
     swk_j = (-a_j s + e_j + [t in D_j] (P mod t) s', a_j) on every prime t;
   * rotation by r applies X -> X^(5^r mod 2N) then switches from s(X^g) back
     to s; conjugation uses g = 2N - 1.
@@ -158,15 +160,17 @@ class Context:
         t = np.int64(self.primes[idx])
         return (np.asarray(v, dtype=np.int64) % t).astype(np.uint64)
 
-    def base_convert(self, limbs, src_idx, dst_idx):
-        """Fast base conversion (coefficient domain) from primes src to dst."""
+    def base_convert(self, limbs, src_idx, dst_idx, centered=False):
+        """Fast base conversion (coefficient domain) from primes src to dst;
+        centered=True takes each [x_i (D/d_i)^-1]_{d_i} in (-d_i/2, d_i/2]."""
         k = len(src_idx)
         m = len(dst_idx)
         inp = np.ascontiguousarray(np.stack(limbs).reshape(-1), dtype=np.uint64)
         src = np.array([self.primes[i] for i in src_idx], dtype=np.uint64)
         dst = np.array([self.primes[i] for i in dst_idx], dtype=np.uint64)
         out = np.empty(m * self.N, dtype=np.uint64)
-        self._L.or_base_convert(inp, src, k, out, dst, m, self.N)
+        f = self._L.or_base_convert_centered if centered else self._L.or_base_convert
+        f(inp, src, k, out, dst, m, self.N)
         return [out[i * self.N:(i + 1) * self.N].copy() for i in range(m)]
 
     def automorph_perm(self, g):
@@ -400,7 +404,7 @@ class Context:
         nq_l = level + 1
         p_idx = list(range(len(self.q), len(self.primes)))
         cp = [self.intt(limbs[nq_l + k], t) for k, t in enumerate(p_idx)]
-        conv = self.base_convert(cp, p_idx, list(range(nq_l)))
+        conv = self.base_convert(cp, p_idx, list(range(nq_l)), centered=True)
         out = []
         for i in range(nq_l):
             cn = self.ntt(conv[i], i)

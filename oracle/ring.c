@@ -178,6 +178,48 @@ void or_base_convert(const u64* in, const u64* src, int k, u64* out, const u64* 
     free(hat_mod);
 }
 
+/*
+ * Centred fast base conversion: as or_base_convert but each
+ * [x_i (D/d_i)^-1]_{d_i} is taken in (-d_i/2, d_i/2], so the result is
+ * x + u D with |u| <= k/2 and u of mean zero.  Used by ModDown, where the
+ * conversion error becomes noise and must not carry a bias.
+ */
+void or_base_convert_centered(const u64* in, const u64* src, int k, u64* out, const u64* dst, int m, u64 N) {
+    u64* inv_hat = (u64*)malloc(sizeof(u64) * k);
+    u64* hat_mod = (u64*)malloc(sizeof(u64) * k * m);
+    u64* D_mod = (u64*)malloc(sizeof(u64) * m);
+    for (int i = 0; i < k; i++) {
+        u64 h = 1;
+        for (int j = 0; j < k; j++) if (j != i) h = mulmod(h, src[j] % src[i], src[i]);
+        inv_hat[i] = or_invmod(h, src[i]);
+        for (int t = 0; t < m; t++) {
+            u64 g = 1;
+            for (int j = 0; j < k; j++) if (j != i) g = mulmod(g, src[j] % dst[t], dst[t]);
+            hat_mod[i * m + t] = g;
+        }
+    }
+    for (int t = 0; t < m; t++) {
+        u64 g = 1;
+        for (int j = 0; j < k; j++) g = mulmod(g, src[j] % dst[t], dst[t]);
+        D_mod[t] = g;
+    }
+    for (int t = 0; t < m; t++) {
+        u64 qt = dst[t];
+        for (u64 c = 0; c < N; c++) {
+            u64 acc = 0;
+            for (int i = 0; i < k; i++) {
+                u64 xh = mulmod(in[(u64)i * N + c], inv_hat[i], src[i]);
+                acc = addmod(acc, mulmod(xh % qt, hat_mod[i * m + t], qt), qt);
+                if (xh > (src[i] - 1) / 2) acc = submod(acc, D_mod[t], qt);   /* xh - d_i */
+            }
+            out[(u64)t * N + c] = acc;
+        }
+    }
+    free(inv_hat);
+    free(hat_mod);
+    free(D_mod);
+}
+
 /* Index map of X -> X^g in the NTT (bit-reversed evaluation) domain:
  * out[i] = in[perm[i]] with 2 brv(perm[i]) + 1 = (2 brv(i) + 1) g mod 2N. */
 void or_automorph_perm(u64 N, u64 g, u64* perm) {

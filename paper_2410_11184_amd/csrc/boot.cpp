@@ -1,17 +1,486 @@
-// Bootstrapping: placeholder until the CoeffToSlot / EvalMod / SlotToCoeff
-// pipeline is configured for the context.
+// CKKS bootstrapping, coefficient-to-slot first (Section 2.2, "Levels": a
+// ciphertext at its bottom level is refreshed to a full budget).  The paper
+// uses an external library's bootstrapping and gives only its cost and
+// precision (Section 5.1, Table "tab:fgb_data"); this pipeline is the
+// standard one for full-slot CKKS and is this library's own design:
+//
+//  1. scale the message so that |m| ~ q0 / 2^14 at the stated bound, keep
+//     the q0 limb and lift it to every Q prime (ModRaise): the result
+//     decrypts to t = m + q0 I with |I| <= K;
+//  2. CoeffToSlot: the inverse special FFT (without its bit reversal) as a
+//     product of butterfly stages, grouped into `cts_levels` sparse
+//     matrices with at most 2^(r+1) - 1 diagonals, each applied by
+//     baby-step giant-step rotations and plaintext products; the slots then
+//     hold (t_lo + i t_hi) / (2 q0 (K+1));
+//  3. split real and imaginary parts with one conjugation;
+//  4. EvalMod on both halves at once: a Chebyshev approximation of
+//     cos(2 pi ((K+1) u - 1/4) / 2^r) followed by r double-angle steps
+//     c -> 2 c^2 - 1, which gives sin(2 pi t / q0) ~ 2 pi m / q0;
+//  5. recombine and SlotToCoeff (the forward butterfly stages), with the
+//     factor q0 / (2 pi Delta) folded into its first matrix.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <set>
+
 #include "host.h"
+#include "poly.h"
 #include "softmax.h"
 
 namespace hs {
 
-bool can_bootstrap(const Context& c) { return false && c.prm.boot.cts_levels > 0; }
+typedef std::complex<double> cd;
+typedef std::map<int, std::vector<cd>> Mat;   // offset (mod n) -> diagonal
 
-Ct bootstrap(Context& c, const Ct& x, double bound) {
-    (void)x;
-    (void)bound;
-    HS_REQUIRE(can_bootstrap(c), E_LEVEL, "bootstrapping is not configured for this context");
-    return Ct();
+static void stage_exps(int N, int length, std::vector<int>& e) {
+    const int h = length / 2;
+    const long long lq = 4LL * length;
+    e.resize(h);
+    long long p = 1;
+    for (int j = 0; j < h; j++) {
+        e[j] = (int)(p * (2LL * N / lq));
+        p = p * 5 % lq;
+    }
+}
+
+// one inverse butterfly stage (a, b) -> (a + b, (a - b) conj(W_j)) on blocks of `len`
+static Mat stage_inverse(const Context& c, int n, int len) {
+    std::vector<int> e;
+    stage_exps(c.N, len, e);
+    const int h = len / 2;
+    std::vector<cd> d0(n), dp(n), dm(n);
+    for (int i = 0; i < n; i++) {
+        const int r = i % len;
+        if (r < h) {
+            d0[i] = 1.0;
+            dp[i] = 1.0;
+        } else {
+            const int j = r - h;
+            const cd cw(c.tw_cos[e[j]], -c.tw_sin[e[j]]);
+            d0[i] = -cw;
+            dm[i] = cw;
+        }
+    }
+    // +h and -h coincide when h = n/2: the two diagonals add
+    Mat m;
+    m[0] = d0;
+    m[h % n] = dp;
+    auto& dmr = m[(n - h) % n];
+    if (dmr.empty()) dmr = dm;
+    else
+        for (int i = 0; i < n; i++) dmr[i] += dm[i];
+    return m;
+}
+
+// one forward butterfly stage (a, b) -> (a + W_j b, a - W_j b)
+static Mat stage_forward(const Context& c, int n, int len) {
+    std::vector<int> e;
+    stage_exps(c.N, len, e);
+    const int h = len / 2;
+    std::vector<cd> d0(n), dp(n), dm(n);
+    for (int i = 0; i < n; i++) {
+        const int r = i % len;
+        if (r < h) {
+            const cd w(c.tw_cos[e[r]], c.tw_sin[e[r]]);
+            d0[i] = 1.0;
+            dp[i] = w;
+        } else {
+            const cd w(c.tw_cos[e[r - h]], c.tw_sin[e[r - h]]);
+            dm[i] = 1.0;
+            d0[i] = -w;
+        }
+    }
+    // +h and -h coincide when h = n/2: the two diagonals add
+    Mat m;
+    m[0] = d0;
+    m[h % n] = dp;
+    auto& dmr = m[(n - h) % n];
+    if (dmr.empty()) dmr = dm;
+    else
+        for (int i = 0; i < n; i++) dmr[i] += dm[i];
+    return m;
+}
+
+// (A B)_{da+db}[i] = sum A_da[i] B_db[i + da]  (B applied first)
+static Mat mat_mul(const Mat& A, const Mat& B, int n) {
+    Mat C;
+    for (auto& a : A)
+        for (auto& b : B) {
+            const int d = (a.first + b.first) % n;
+            auto& out = C[d];
+            if (out.empty()) out.assign(n, 0.0);
+            for (int i = 0; i < n; i++) out[i] += a.second[i] * b.second[(i + a.first) % n];
+        }
+    return C;
+}
+
+struct LinLevel {
+    int level = 0;        // level of the input ciphertext
+    int unit = 1, n1 = 1;
+    double in_scale = 1, pt_scale = 1;
+    std::map<int, std::vector<int>> by_giant;      // g -> babies b
+    std::map<std::pair<int, int>, u64*> pt;        // (g, b) -> rows [level+1][N]
+    std::vector<int> rotations() const {
+        std::vector<int> r;
+        std::set<int> babies;
+        for (auto& kv : by_giant) {
+            for (int b : kv.second) babies.insert(b);
+            if (kv.first != 0) r.push_back(kv.first * n1 * unit);
+        }
+        for (int b : babies)
+            if (b) r.push_back(b * unit);
+        return r;
+    }
+};
+
+struct BootCtx {
+    std::vector<LinLevel> cts, stc;
+    std::vector<Mat> stc_mats;     // unencoded (scales known at first use)
+    std::vector<int> stc_units;
+    double stc_in_scale = 0;       // scale the StC plaintexts were made for
+    ChebPoly pcos;
+    double s0 = 1;                 // declared scale after ModRaise
+    bool keys_done = false;
+};
+
+static std::map<const Context*, BootCtx*>& boot_registry() {
+    static std::map<const Context*, BootCtx*> r;
+    return r;
+}
+
+bool can_bootstrap(const Context& c) { return c.prm.boot.cts_levels > 0; }
+
+// split `nst` stages into `g` groups, larger groups first
+static std::vector<int> group_sizes(int nst, int g) {
+    std::vector<int> s(g, nst / g);
+    for (int i = 0; i < nst % g; i++) s[i]++;
+    return s;
+}
+
+static void encode_level(Context& c, LinLevel& lv, const Mat& M, double constant) {
+    const int n = c.N / 2;
+    // split offsets t u = g n1 u + b u, pre-rotate by -g n1 u
+    std::map<std::pair<int, int>, std::vector<cd>> pre;
+    for (auto& kv : M) {
+        double mx = 0;
+        for (auto& v : kv.second) mx = std::max(mx, std::abs(v));
+        if (mx < 1e-300) continue;
+        const int sgn = kv.first <= n / 2 ? kv.first : kv.first - n;
+        HS_REQUIRE(sgn % lv.unit == 0, E_PARAM, "linear transform: offset not a multiple of the unit");
+        const int t = sgn / lv.unit;
+        const int b = ((t % lv.n1) + lv.n1) % lv.n1;
+        const int g = (t - b) / lv.n1;
+        const int shift = ((g * lv.n1 * lv.unit) % n + n) % n;
+        std::vector<cd> d(n);
+        for (int i = 0; i < n; i++) d[i] = kv.second[(i - shift + n) % n] * constant;
+        pre[{g, b}] = d;
+        lv.by_giant[g].push_back(b);
+    }
+    const int rows = lv.level + 1;
+    std::vector<double> re(n), im(n), w(c.N);
+    double* dw = (double*)c.pool.alloc(sizeof(double) * c.N);
+    for (auto& kv : pre) {
+        for (int i = 0; i < n; i++) {
+            re[i] = kv.second[i].real();
+            im[i] = kv.second[i].imag();
+        }
+        special_fft_inverse(c, re, im);
+        for (int k = 0; k < n; k++) {
+            w[k] = re[k];
+            w[k + n] = im[k];
+        }
+        c.upload(dw, w.data(), sizeof(double) * c.N);
+        u64* pt = nullptr;
+        if (hipMalloc((void**)&pt, sizeof(u64) * rows * c.N) != hipSuccess) throw Error(E_OOM, "bootstrap plaintexts");
+        c.owned.push_back(pt);
+        Rows r = c.rows(pt, 1, rows, (size_t)rows * c.N);
+        k_encode_real(c.T, r, dw, 0, lv.pt_scale, c.stream);
+        k_ntt(c.T, r, false, c.stream);
+        lv.pt[kv.first] = pt;
+    }
+    c.sync();
+    c.pool.free(dw);
+}
+
+static BootCtx& boot_ctx(Context& c) {
+    auto& reg = boot_registry();
+    auto it = reg.find(&c);
+    if (it != reg.end()) return *it->second;
+    HS_REQUIRE(can_bootstrap(c), E_PARAM, "no bootstrapping parameters");
+    const BootParams& bp = c.prm.boot;
+    HS_REQUIRE(c.prm.user_top + bp.cts_levels + bp.evalmod_levels + bp.stc_levels == c.L, E_PARAM,
+               "bootstrapping levels do not match the modulus chain");
+    BootCtx* B = new BootCtx();
+    const int n = c.N / 2;
+    int nst = 0;
+    while ((1 << nst) < n) nst++;
+    const double q0 = (double)c.primes[0];
+    const double Db = std::ldexp(1.0, bp.log_boot_scale);
+    // ---- CoeffToSlot: stages of length n, n/2, ..., 2 (in application order)
+    {
+        std::vector<int> gs = group_sizes(nst, bp.cts_levels);
+        B->s0 = 2.0 * q0 * (bp.K + 1) * n;
+        int len = n;
+        double s_prev = B->s0;
+        for (int gi = 0; gi < bp.cts_levels; gi++) {
+            Mat M;
+            bool first = true;
+            int unit = len;
+            for (int s = 0; s < gs[gi]; s++) {
+                Mat S = stage_inverse(c, n, len);
+                M = first ? S : mat_mul(S, M, n);
+                first = false;
+                unit = len / 2;
+                len /= 2;
+            }
+            LinLevel lv;
+            lv.level = c.L - gi;
+            lv.unit = unit;
+            lv.n1 = 1 << ((gs[gi] + 1) / 2);
+            const double frac = (double)(gi + 1) / bp.cts_levels;
+            const double s_next = std::exp2(std::log2(B->s0) * (1 - frac) + std::log2(Db) * frac);
+            lv.in_scale = s_prev;
+            lv.pt_scale = s_next * (double)c.primes[lv.level] / s_prev;
+            encode_level(c, lv, M, 1.0);
+            s_prev = s_prev * lv.pt_scale / (double)c.primes[lv.level];
+            B->cts.push_back(lv);
+        }
+    }
+    // ---- SlotToCoeff: stages of length 2, 4, ..., n; encoded at first use
+    {
+        std::vector<int> gs = group_sizes(nst, bp.stc_levels);
+        std::reverse(gs.begin(), gs.end());
+        int len = 2;
+        for (int gi = 0; gi < bp.stc_levels; gi++) {
+            Mat M;
+            bool first = true;
+            int unit = len / 2;
+            for (int s = 0; s < gs[gi]; s++) {
+                Mat S = stage_forward(c, n, len);
+                M = first ? S : mat_mul(S, M, n);
+                first = false;
+                len *= 2;
+            }
+            B->stc_mats.push_back(M);
+            B->stc_units.push_back(unit);
+            LinLevel lv;
+            lv.level = c.prm.user_top + bp.stc_levels - gi;
+            lv.unit = unit;
+            lv.n1 = 1 << ((gs[gi] + 1) / 2);
+            // register the rotation layout now (plaintexts later)
+            const int nn = n;
+            for (auto& kv : M) {
+                const int sgn = kv.first <= nn / 2 ? kv.first : kv.first - nn;
+                const int t = sgn / unit;
+                const int b = ((t % lv.n1) + lv.n1) % lv.n1;
+                lv.by_giant[(t - b) / lv.n1].push_back(b);
+            }
+            B->stc.push_back(lv);
+        }
+    }
+    // ---- EvalMod polynomial
+    {
+        const long double two_pi = 6.283185307179586476925286766559005768L;
+        const long double K1 = bp.K + 1;
+        const long double sc = ldexpl(1.0L, -bp.double_angle);
+        B->pcos = cheb_fit([&](long double u) { return cosl(two_pi * (K1 * u - 0.25L) * sc); }, -1.0, 1.0,
+                           bp.cos_degree);
+    }
+    reg[&c] = B;
+    return *B;
+}
+
+static void ensure_keys(Context& c, BootCtx& B) {
+    if (B.keys_done) return;
+    add_galois_key(c, 2 * c.N - 1);
+    for (auto* levels : {&B.cts, &B.stc})
+        for (auto& lv : *levels)
+            for (int r : lv.rotations()) add_galois_key(c, galois_rot(r, c.N));
+    B.keys_done = true;
+}
+
+// baby-step giant-step application of one encoded level; one rescale
+static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x) {
+    HS_REQUIRE(x.level == lv.level, E_LEVEL, "linear transform: unexpected input level");
+    std::map<int, Ct> baby;
+    std::set<int> need;
+    for (auto& kv : lv.by_giant)
+        for (int b : kv.second) need.insert(b);
+    for (int b : need) baby[b] = b == 0 ? ct_copy(c, x) : op_rotate(c, x, b * lv.unit);
+    Ct acc;
+    bool have = false;
+    for (auto& kv : lv.by_giant) {
+        const int g = kv.first;
+        Ct inner;
+        bool hi = false;
+        for (int b : kv.second) {
+            Ct p = op_mul_plain(c, baby.at(b), lv.pt.at({g, b}), lv.pt_scale, false);
+            if (!hi) {
+                inner = p;
+                hi = true;
+            } else {
+                op_add_inplace(c, inner, p);
+                ct_free(c, p);
+            }
+        }
+        if (g != 0) {
+            Ct r = op_rotate(c, inner, g * lv.n1 * lv.unit);
+            ct_free(c, inner);
+            inner = r;
+        }
+        if (!have) {
+            acc = inner;
+            have = true;
+        } else {
+            op_add_inplace(c, acc, inner);
+            ct_free(c, inner);
+        }
+    }
+    for (auto& kv : baby) ct_free(c, kv.second);
+    Ct out = op_rescale(c, acc);
+    ct_free(c, acc);
+    return out;
+}
+
+static void encode_stc(Context& c, BootCtx& B, double in_scale) {
+    if (B.stc_in_scale == in_scale) return;
+    HS_REQUIRE(B.stc_in_scale == 0, E_STATE, "bootstrapping: EvalMod output scale changed");
+    const BootParams& bp = c.prm.boot;
+    const double q0 = (double)c.primes[0];
+    const double Dout = std::ldexp(1.0, c.prm.log_scale);
+    const double two_pi = 6.283185307179586;
+    const double cst = q0 / (two_pi * Dout);
+    double s_prev = in_scale;
+    for (int gi = 0; gi < bp.stc_levels; gi++) {
+        LinLevel& lv = B.stc[gi];
+        lv.by_giant.clear();
+        const double frac = (double)(gi + 1) / bp.stc_levels;
+        const double s_next = std::exp2(std::log2(in_scale) * (1 - frac) + std::log2(Dout) * frac);
+        lv.in_scale = s_prev;
+        lv.pt_scale = s_next * (double)c.primes[lv.level] / s_prev;
+        encode_level(c, lv, B.stc_mats[gi], gi == 0 ? cst : 1.0);
+        s_prev = s_prev * lv.pt_scale / (double)c.primes[lv.level];
+    }
+    B.stc_in_scale = in_scale;
+}
+
+Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop);
+
+Ct bootstrap(Context& c, const Ct& x, double bound) { return bootstrap_stage(c, x, bound, 0); }
+
+// stop: 0 = full; 1 = after ModRaise; 2 = after CoeffToSlot; 3 = real part
+// after the split; 4 = real part after the cosine polynomial; 5 = real part
+// after the double angles (intermediate results for tests)
+Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
+    HS_REQUIRE(can_bootstrap(c), E_PARAM, "no bootstrapping parameters");
+    HS_REQUIRE(x.ncomp == 2, E_ARG, "bootstrap: degree-1 ciphertext expected");
+    BootCtx& B = boot_ctx(c);
+    ensure_keys(c, B);
+    const BootParams& bp = c.prm.boot;
+    const double q0 = (double)c.primes[0];
+    const double Db = std::ldexp(1.0, bp.log_boot_scale);
+    const double Bd = std::max(bound, std::ldexp(1.0, -20));
+    // 1. message size |m| ~ q0 / 2^14 at the bound
+    const double target = q0 / 16384.0;
+    Ct xx;
+    int e = 0;
+    if (Bd * x.scale > 2.0 * target && x.level >= 1) {
+        e = (int)std::ceil(std::log2(Bd * x.scale / target));
+        xx = op_mul_const(c, x, std::ldexp(1.0, -e), x.scale);
+    } else {
+        xx = ct_copy(c, x);
+        const double kf = std::floor(target / (Bd * x.scale));
+        if (kf >= 2.0) {
+            const long long K = (long long)std::min(kf, 1e15);
+            op_mul_int_inplace(c, xx, K);
+            xx.scale = x.scale * (double)K;
+        }
+    }
+    const double s_msg = xx.scale;
+    Ct x0 = ct_drop(c, xx, 0);
+    ct_free(c, xx);
+    Ct t = op_mod_raise(c, x0, c.L);
+    ct_free(c, x0);
+    t.scale = B.s0;
+    if (stop == 1) return t;
+    // 2. CoeffToSlot
+    for (auto& lv : B.cts) {
+        Ct nx = apply_level(c, lv, t);
+        ct_free(c, t);
+        t = nx;
+    }
+    if (stop == 2) return t;
+    // 3. real / imaginary split: u_re = t + conj t, u_im = -i (t - conj t)
+    Ct cj = op_conjugate(c, t);
+    Ct ure = op_add(c, t, cj);
+    Ct dif = op_sub(c, t, cj);
+    ct_free(c, t);
+    ct_free(c, cj);
+    Ct uim = op_mul_monomial(c, dif, 3 * c.N / 2);
+    ct_free(c, dif);
+    if (stop == 3) {
+        ct_free(c, uim);
+        return ure;
+    }
+    std::vector<const Ct*> parts{&ure, &uim};
+    Ct u = ct_gather(c, parts);
+    const int m = x.m;
+    ct_free(c, ure);
+    ct_free(c, uim);
+    // 4. EvalMod: cos(2 pi ((K+1) u - 1/4) / 2^r), then r double angles
+    Ct v = eval_cheb(c, u, B.pcos, Db);
+    ct_free(c, u);
+    if (stop == 4) {
+        Ct r = ct_slice(c, v, 0, m);
+        ct_free(c, v);
+        return r;
+    }
+    for (int r = 0; r < bp.double_angle; r++) {
+        Ct s = op_mult(c, v, v);
+        ct_free(c, v);
+        op_mul_int_inplace(c, s, 2);
+        op_add_const_inplace(c, s, -1.0);
+        v = s;
+    }
+    if (stop == 5) {
+        Ct r = ct_slice(c, v, 0, m);
+        ct_free(c, v);
+        return r;
+    }
+    // 5. recombine (re + i im) and SlotToCoeff
+    Ct vre = ct_slice(c, v, 0, m);
+    Ct vim = ct_slice(c, v, m, m);
+    ct_free(c, v);
+    Ct vi = op_mul_monomial(c, vim, c.N / 2);
+    ct_free(c, vim);
+    op_add_inplace(c, vre, vi);
+    ct_free(c, vi);
+    encode_stc(c, B, vre.scale);
+    Ct y = vre;
+    for (auto& lv : B.stc) {
+        Ct ny = apply_level(c, lv, y);
+        ct_free(c, y);
+        y = ny;
+    }
+    // the StC output encodes v * s_msg / Delta at its computed scale
+    const double Dout = std::ldexp(1.0, c.prm.log_scale);
+    y.scale = y.scale * s_msg / Dout;
+    if (e > 0) {
+        op_mul_int_inplace(c, y, 1LL << e);
+    }
+    return y;
+}
+
+void boot_release(const Context* c) {
+    auto& reg = boot_registry();
+    auto it = reg.find(c);
+    if (it != reg.end()) {
+        delete it->second;
+        reg.erase(it);
+    }
 }
 
 }  // namespace hs

@@ -582,4 +582,33 @@ hs_status hs_bootstrap(hs_ctx* ctx, const hs_ct* a, hs_ct** out) {
     });
 }
 
+hs_status hs_prof_enable(hs_ctx* ctx, int on) {
+    return guard([&] {
+        NEED(ctx);
+        hs::prof_enable(ctx->c->T.prof, on != 0);
+    });
+}
+
+hs_status hs_prof_collect(hs_ctx* ctx, double* out, size_t n) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(out);
+        HS_REQUIRE(n >= 3 * (size_t)hs::PK_COUNT, hs::E_ARG, "buffer too small");
+        hs::prof_collect(ctx->c->T.prof, out);
+    });
+}
+
+hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(hs::can_bootstrap(c), hs::E_PARAM, "no bootstrapping parameters");
+        HS_REQUIRE(stage >= 1 && stage <= 5, hs::E_ARG, "stage must be 1..5");
+        *out = wrap(&c, hs::bootstrap_stage(c, a->ct, 1.0, stage));
+    });
+}
+
 }  // extern "C"

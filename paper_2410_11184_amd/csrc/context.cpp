@@ -214,7 +214,8 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     std::vector<int> bits = p.q_bits;
     bits.insert(bits.end(), p.p_bits.begin(), p.p_bits.end());
     primes = find_primes(logN, bits);
-    // every digit must be smaller than P (key-switching noise; AMB-16 reading)
+    // every key-switching digit must be smaller than P, or the switching
+    // noise (about digit / P times the key error) swamps the message
     double logP = 0;
     for (int k = 0; k < np; k++) logP += std::log2((double)primes[nq + k]);
     for (int j = 0; j < dnum; j++) {
@@ -266,6 +267,7 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     T.ninv = (const u64*)dev_table(ninv.data(), ninv.size() * 8);
     T.logN = logN;
     T.N = N;
+    T.prof = prof_create();
 
     // encoding twiddles: correctly rounded (cos, sin)(pi e / N), e in [0, 2N),
     // from binary128 values on the quarter circle and exact symmetries
@@ -326,6 +328,8 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
 }
 
 Context::~Context() {
+    boot_release(this);
+    prof_destroy(T.prof);
     for (auto& kv : keys) pool.free(kv.second);
     if (s_ntt) pool.free(s_ntt);
     if (pk) pool.free(pk);
@@ -344,7 +348,7 @@ CtHandle::~CtHandle() {
 
 // ------------------------------------------------- base-conversion tables
 static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vector<int>& src_row,
-                         const std::vector<int>& dst, const std::vector<int>& dst_row) {
+                         const std::vector<int>& dst, const std::vector<int>& dst_row, bool centered) {
     const int k = (int)src.size(), m = (int)dst.size();
     std::vector<u64> inv_hat(k), inv_hat_s(k), hat((size_t)k * m), hat_s((size_t)k * m);
     for (int i = 0; i < k; i++) {
@@ -379,8 +383,17 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
     cd.t.dst_prime = (const int*)put(dst.data(), m * 4);
     cd.t.src_row = (const int*)put(src_row.data(), k * 4);
     cd.t.dst_row = (const int*)put(dst_row.data(), m * 4);
+    std::vector<u64> dmod(m);
+    for (int t = 0; t < m; t++) {
+        const u64 qt = c.primes[dst[t]];
+        u64 g = 1;
+        for (int j = 0; j < k; j++) g = mulmod_h(g, c.primes[src[j]] % qt, qt);
+        dmod[t] = g;
+    }
+    cd.t.dmod = (const u64*)put(dmod.data(), m * 8);
     cd.t.k = k;
     cd.t.m = m;
+    cd.t.centered = centered ? 1 : 0;
     return cd;
 }
 
@@ -408,11 +421,12 @@ const ConvDev& Context::modup_tables(int level, int j) {
         drow.push_back(level + 1 + k);
     }
     HS_REQUIRE((int)src.size() <= 16, E_PARAM, "digit too large");
-    return modup.emplace(key, make_conv(*this, src, srow, dst, drow)).first->second;
+    return modup.emplace(key, make_conv(*this, src, srow, dst, drow, false)).first->second;
 }
 
 // ModDown at level l: sources are P (rows l+1.. of the extended layout),
-// targets q_0..q_l (rows 0..l of a level-l buffer).
+// targets q_0..q_l (rows 0..l of a level-l buffer).  Centred conversion, so
+// the division by P rounds with a zero-mean error.
 const ConvDev& Context::moddown_tables(int level) {
     auto it = moddown.find(level);
     if (it != moddown.end()) return it->second;
@@ -426,7 +440,7 @@ const ConvDev& Context::moddown_tables(int level) {
         drow.push_back(i);
     }
     HS_REQUIRE((int)src.size() <= 16, E_PARAM, "too many special primes");
-    return moddown.emplace(level, make_conv(*this, src, srow, dst, drow)).first->second;
+    return moddown.emplace(level, make_conv(*this, src, srow, dst, drow, true)).first->second;
 }
 
 // X -> X^g in the bit-reversed NTT domain: out[i] = in[perm[i]] with

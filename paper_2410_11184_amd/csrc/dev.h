@@ -18,6 +18,16 @@ struct PrimeInfo {
     int pad;
 };
 
+// Per-launch timing with HIP events (off unless enabled): each profiled
+// launch wrapper records an event pair and its algorithmic bytes.
+struct Profiler;
+enum ProfKind { PK_NTT = 0, PK_KEYIP, PK_CONV, PK_TENSOR, PK_EW, PK_PERM, PK_LIFT, PK_OTHER, PK_COUNT };
+Profiler* prof_create();
+void prof_destroy(Profiler* p);
+void prof_enable(Profiler* p, bool on);
+// totals since the last call, per kind: [count, milliseconds, bytes]; syncs the events
+void prof_collect(Profiler* p, double* out);
+
 // Device-resident tables of one context (negacyclic NTT twiddles in
 // bit-reversed order, with Shoup companions floor(w 2^64 / q)).
 struct DevTables {
@@ -29,6 +39,7 @@ struct DevTables {
     const u64* ninv;          // [n_primes][2]   N^-1 mod q, Shoup companion
     int logN;
     int N;
+    Profiler* prof;           // optional launch profiler (host object)
 };
 
 // A set of rows: ngroups groups of rpg consecutive rows (N words each);
@@ -62,8 +73,10 @@ struct ConvTables {
     const int* dst_prime;   // [m]
     const int* src_row;     // [k] row offsets (within the input group)
     const int* dst_row;     // [m] row offsets (within the output group)
+    const u64* dmod;        // [m]  D mod q_t (centred conversion only)
     int k;
     int m;
+    int centered;           // 1: [x_i inv_hat_i] taken in (-d_i/2, d_i/2]
 };
 
 // ------------------------------------------------------------- launches

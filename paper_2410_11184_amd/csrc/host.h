@@ -179,6 +179,7 @@ u64 powmod_h(u64 a, u64 e, u64 q);
 u64 invmod_h(u64 a, u64 q);
 u64 shoup_h(u64 w, u64 q);
 int galois_rot(int r, int N);
+void boot_release(const Context* c);
 
 // --------------------------------------------------------- ciphertexts
 Ct ct_alloc(Context& c, int m, int ncomp, int level);

@@ -7,9 +7,85 @@
 // and Barrett reduction for products of two variables.  All kernels keep
 // values fully reduced in [0, q) at their boundaries.
 #include <hip/hip_runtime.h>
+
+#include <vector>
+
 #include "dev.h"
 
 namespace hs {
+
+// ------------------------------------------------------------- profiler
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+    hipEvent_t get() {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+};
+
+Profiler* prof_create() { return new Profiler(); }
+void prof_destroy(Profiler* p) {
+    if (!p) return;
+    for (auto& r : p->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : p->spare) (void)hipEventDestroy(e);
+    delete p;
+}
+void prof_enable(Profiler* p, bool on) {
+    if (p) p->on = on;
+}
+void prof_collect(Profiler* p, double* out) {
+    for (int k = 0; k < 3 * PK_COUNT; k++) out[k] = 0;
+    if (!p) return;
+    for (auto& r : p->recs) {
+        (void)hipEventSynchronize(r.b);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        out[3 * r.kind] += 1;
+        out[3 * r.kind + 1] += ms;
+        out[3 * r.kind + 2] += r.bytes;
+        p->spare.push_back(r.a);
+        p->spare.push_back(r.b);
+    }
+    p->recs.clear();
+}
+
+// RAII scope recording an event pair around the launches it encloses
+struct ProfScope {
+    Profiler* p;
+    hipStream_t st;
+    hipEvent_t a{}, b{};
+    int kind;
+    double bytes;
+    ProfScope(Profiler* pp, int k, double by, void* stream) : p(pp), st((hipStream_t)stream), kind(k), bytes(by) {
+        if (p && p->on) {
+            a = p->get();
+            (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (p && p->on) {
+            b = p->get();
+            (void)hipEventRecord(b, st);
+            p->recs.push_back({kind, a, b, bytes});
+        }
+    }
+};
 
 // ------------------------------------------------------------- arithmetic
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
@@ -251,6 +327,7 @@ __global__ void __launch_bounds__(256) ntt_pass2_kernel(DevTables T, Rows x, int
 void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) {
     const int nrows = x.ngroups * x.rpg;
     if (nrows == 0) return;
+    ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
     hipStream_t st = (hipStream_t)stream;
     if (T.N <= 4096) {
         hipLaunchKernelGGL(ntt_small_kernel, dim3(nrows), dim3(256), T.N * sizeof(u64), st, T, x,
@@ -329,6 +406,7 @@ static inline dim3 ew_grid(const DevTables& T, const Rows& x) {
 #define EW_LAUNCH(kern, out, ...)                                                        \
     do {                                                                                 \
         if ((out).ngroups * (out).rpg == 0) return;                                      \
+        ProfScope ps_(T.prof, PK_EW, 24.0 * T.N * (out).ngroups * (out).rpg, stream);    \
         hipLaunchKernelGGL(kern, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, T, out, \
                            __VA_ARGS__);                                                 \
     } while (0)
@@ -381,6 +459,7 @@ __global__ void tensor_kernel(DevTables T, Rows d, Rows a, Rows b, size_t ac, si
 void k_tensor(const DevTables& T, const Rows& d, const Rows& a, const Rows& b, size_t a_comp, size_t b_comp,
               size_t d_comp, void* stream) {
     if (d.ngroups * d.rpg == 0) return;
+    ProfScope ps(T.prof, PK_TENSOR, 56.0 * T.N * d.ngroups * d.rpg, stream);
     hipLaunchKernelGGL(tensor_kernel, ew_grid(T, d), dim3(256), 0, (hipStream_t)stream, T, d, a, b, a_comp,
                        b_comp, d_comp);
 }
@@ -408,6 +487,7 @@ __global__ void square_sum_kernel(DevTables T, u64* d, size_t dc, Rows a, size_t
 }
 
 void k_square_sum(const DevTables& T, u64* d, size_t d_comp, const Rows& a, size_t a_comp, void* stream) {
+    ProfScope ps(T.prof, PK_TENSOR, 8.0 * T.N * a.rpg * (2.0 * a.ngroups + 3.0), stream);
     hipLaunchKernelGGL(square_sum_kernel, dim3((T.N + 255) / 256, a.rpg), dim3(256), 0, (hipStream_t)stream, T,
                        d, d_comp, a, a_comp);
 }
@@ -422,6 +502,7 @@ __global__ void permute_kernel(Rows out, Rows in, const int* perm, int N) {
 
 void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* perm, void* stream) {
     if (out.ngroups * out.rpg == 0) return;
+    ProfScope ps(T.prof, PK_PERM, 16.0 * T.N * out.ngroups * out.rpg, stream);
     hipLaunchKernelGGL(permute_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, in, perm, T.N);
 }
 
@@ -434,16 +515,23 @@ __global__ void base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t 
     const int N = T.N;
     if (i >= N) return;
     u64 xh[kMaxConvSrc];
+    int nneg = 0;
     for (int s = 0; s < C.k; s++) {
         const u64 x = in[(size_t)g * ig + (size_t)C.src_row[s] * N + i];
         const u64 d = T.prime[C.src_prime[s]].q;
         xh[s] = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
+        // centred: xh - d_s contributes xh * hat - D
+        if (C.centered && xh[s] > (d - 1) / 2) nneg++;
     }
     for (int t = 0; t < C.m; t++) {
         const u64 q = T.prime[C.dst_prime[t]].q;
         u64 acc = 0;
         for (int s = 0; s < C.k; s++)
             acc = add_mod(acc, mul_shoup(xh[s], C.hat[s * C.m + t], C.hat_s[s * C.m + t], q), q);
+        if (nneg) {
+            const u64 dm = C.dmod[t];
+            for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, q);
+        }
         out[(size_t)g * og + (size_t)C.dst_row[t] * N + i] = acc;
     }
 }
@@ -451,6 +539,7 @@ __global__ void base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t 
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride, const u64* in,
                     size_t in_gstride, int ngroups, void* stream) {
     if (ngroups == 0 || C.m == 0) return;
+    ProfScope ps(T.prof, PK_CONV, 8.0 * T.N * ngroups * (double)(C.k + C.m), stream);
     hipLaunchKernelGGL(base_convert_kernel, dim3((T.N + 255) / 256, ngroups), dim3(256), 0, (hipStream_t)stream,
                        T, C, out, out_gstride, in, in_gstride);
 }
@@ -479,6 +568,7 @@ __global__ void lift_centered_kernel(DevTables T, Rows out, const u64* in, size_
 void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t in_gstride, int src_prime,
                      void* stream) {
     if (out.ngroups * out.rpg == 0) return;
+    ProfScope ps(T.prof, PK_LIFT, 8.0 * T.N * out.ngroups * (out.rpg + 1.0), stream);
     hipLaunchKernelGGL(lift_centered_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, T, out, in,
                        in_gstride, src_prime);
 }
@@ -517,6 +607,8 @@ __global__ void key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u6
 void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta, int ext_rows,
                  int nq_level, int key_rows, int key_nq, int alpha, void* stream) {
     (void)alpha;
+    // algorithmic bytes: the key once per launch, ext read and acc written per ciphertext
+    ProfScope ps(T.prof, PK_KEYIP, 8.0 * T.N * ext_rows * (2.0 * beta + ncts * (beta + 2.0)), stream);
     hipLaunchKernelGGL(key_inner_kernel, dim3((T.N + 255) / 256, ext_rows), dim3(256), 0, (hipStream_t)stream, T,
                        acc, ext, key, ncts, beta, ext_rows, nq_level, key_rows, key_nq);
 }

@@ -164,19 +164,19 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
                 y = y2;
             }
         }
-        // AUX step 1: S = sum over the m ciphertexts of y^2 (one relinearisation)
+        // auxiliary thread, squaring: S = sum over the m ciphertexts of y^2 (one relinearisation)
         Ct d = op_square_sum(c, y);
         Ct r = op_relin(c, d);
         ct_free(c, d);
         Ct S = op_rescale(c, r);
         ct_free(c, r);
-        // AUX steps 2-4: rotate-and-add with strides -L 2^t
+        // auxiliary thread, summation: rotate-and-add with strides -L 2^t
         for (int t = 0; t < nrot; t++) {
             Ct rr = op_rotate(c, S, -(L << t));
             op_add_inplace(c, S, rr);
             ct_free(c, rr);
         }
-        // AUX step 5 budget: the polynomial (mask folded into its leaves)
+        // budget of the normalisation polynomial (mask folded into its leaves)
         {
             bool rep;
             Ct S2 = ensure_level(c, S, cheb_depth(deg) + 1, hi * 1.1, st, rep);
@@ -185,10 +185,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
                 S = S2;
             }
         }
-        // AUX steps 5-6: lambda = P(S) * mask
+        // normalisation and mask: lambda = P(S) * mask
         Ct lam = eval_cheb(c, S, pinv, Delta, mask);
         ct_free(c, S);
-        // AUX steps 7-9: broadcast slots [0, L) to all n/m positions
+        // broadcast of slots [0, L) to all n/m positions
         for (int t = 0; t < nrot; t++) {
             Ct rr = op_rotate(c, lam, L << t);
             op_add_inplace(c, lam, rr);

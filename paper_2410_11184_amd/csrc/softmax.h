@@ -26,5 +26,6 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
 bool can_bootstrap(const Context& c);
 // Refresh x (any level) to the top user level; `bound` bounds |slot values|.
 Ct bootstrap(Context& c, const Ct& x, double bound);
+Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop);
 
 }  // namespace hs

@@ -106,6 +106,9 @@ def lib():
     }
     optional = {
         "hs_bootstrap": [_vp, _vp, ctypes.POINTER(_vp)],
+        "hs_dbg_bootstrap_stage": [_vp, _vp, S, ctypes.POINTER(_vp)],
+        "hs_prof_enable": [_vp, S],
+        "hs_prof_collect": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
         "hs_softmax": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_uint32, ctypes.c_double,
                        ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_stats": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
@@ -335,6 +338,20 @@ class Context:
 
     def bootstrap(self, a):
         return self._op("hs_bootstrap", a.h)
+
+    PROF_KINDS = ("ntt", "keyip", "conv", "tensor", "ew", "perm", "lift", "other")
+
+    def prof_enable(self, on=True):
+        _check(lib().hs_prof_enable(self.h, 1 if on else 0))
+
+    def prof_collect(self):
+        buf = (ctypes.c_double * 24)()
+        _check(lib().hs_prof_collect(self.h, buf, 24))
+        return {k: dict(launches=int(buf[3 * i]), ms=float(buf[3 * i + 1]), bytes=float(buf[3 * i + 2]))
+                for i, k in enumerate(self.PROF_KINDS)}
+
+    def bootstrap_stage(self, a, stage):
+        return self._op("hs_dbg_bootstrap_stage", a.h, stage)
 
     def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0)):
         """hs_softmax over the packed ciphertexts `cts`; returns new handles."""

@@ -37,26 +37,26 @@ PRESETS = {
     # (dnum = 3), twelve user levels above q0, full-slot bootstrapping.
     "fgb16": dict(
         logN=16,
-        q_bits=[52] + [40] * 12 + [40] * 3 + [50] * 10 + [50] * 2 + [52],
-        p_bits=[58] * 8,
+        q_bits=[53] + [40] * 12 + [40] * 3 + [58] * 10 + [60] * 3,
+        p_bits=[59] * 9,
         digit=10,
         hamming=192,
         log_scale=40,
         user_top=12,
         boot=dict(stc_levels=3, evalmod_levels=10, cts_levels=3,
-                  K=32, double_angle=3, cos_degree=63, log_boot_scale=50),
+                  K=32, double_angle=3, cos_degree=63, log_boot_scale=58),
     ),
     # Small ring with the same bootstrapping structure, for fast tests.
     "boot10": dict(
         logN=10,
-        q_bits=[52] + [40] * 4 + [40] * 3 + [50] * 10 + [50] * 2 + [52],
-        p_bits=[58] * 8,
-        digit=10,
+        q_bits=[53] + [40] * 4 + [40] * 3 + [58] * 10 + [60] * 3,
+        p_bits=[59] * 8,
+        digit=7,
         hamming=64,
         log_scale=40,
         user_top=4,
         boot=dict(stc_levels=3, evalmod_levels=10, cts_levels=3,
-                  K=32, double_angle=3, cos_degree=63, log_boot_scale=50),
+                  K=32, double_angle=3, cos_degree=63, log_boot_scale=58),
     ),
 }
 

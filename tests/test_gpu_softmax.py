@@ -1,7 +1,7 @@
 """Encrypted Softmax on the GPU against the FP64 definition.
 
 The method approximates Softmax (polynomial exp and normalisation factors),
-so the check is the spec precision bar, >= 16 bits worst case against
+so the check is the precision bar of the method, >= 16 bits worst case against
 the FP64 Softmax, plus the paper's invariants: rows sum to 1, special cases.
 Toy parameters (N = 2^12, 23 levels, no bootstrapping)."""
 import numpy as np
