@@ -183,6 +183,8 @@ typedef struct hs_softmax_opts {
     int inv_degree_last;  /* last iteration                                   */
     double alpha;         /* reserved (0)                                     */
     int plain_per_ct;     /* reserved (0)                                     */
+    int debug_stop;       /* tests: >= 0 returns y after that iteration
+                             (0 = after the exponential); -1 = off          */
 } hs_softmax_opts;
 
 /* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n

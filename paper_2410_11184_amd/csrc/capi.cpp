@@ -507,6 +507,7 @@ hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double
             if (opts->inv_degree_first > 0) o.inv_degree_first = opts->inv_degree_first;
             if (opts->inv_degree_mid > 0) o.inv_degree_mid = opts->inv_degree_mid;
             if (opts->inv_degree_last > 0) o.inv_degree_last = opts->inv_degree_last;
+            o.debug_stop = opts->debug_stop;
         }
         auto t0 = std::chrono::steady_clock::now();
         hs::Ct batch = hs::ct_gather(c, parts);

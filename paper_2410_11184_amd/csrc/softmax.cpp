@@ -137,6 +137,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
                              -2.0, 0.0, o.exp_degree);
     Ct y0 = eval_cheb(c, v, pexp, Delta);
     ct_free(c, v);
+    if (o.debug_stop == 0) return y0;
     const double* mask = mask_coeffs(c, L);
 
     Ct y = ct_copy(c, y0);      // y^(j-1)
@@ -195,8 +196,12 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             ct_free(c, rr);
         }
         if (!smb_step) {
-            // SM step (and the last step of version B): z = lambda y, y = z^2
-            if (!last && can_bootstrap(c) && lam.level < y.level) {
+            // SM step (and the last step of version B): z = lambda y, y = z^2.
+            // y ends at min(y, lambda) - 2; bootstrap lambda only when it is the
+            // ciphertext that leaves y short of the next iteration's need (3, or
+            // 2 before the last step).
+            const int need_next = (j + 1 == k) ? 2 : 3;
+            if (!last && can_bootstrap(c) && lam.level < y.level && lam.level - 2 < need_next) {
                 bool rep;
                 Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep);
                 if (rep) {
@@ -248,6 +253,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             hi = std::pow(1.0 + delta, ej) * 1.0001;
         }
         st.levels_left = y.level;
+        if (o.debug_stop == j) break;
     }
     ct_free(c, y0);
     if (have_big) ct_free(c, big);

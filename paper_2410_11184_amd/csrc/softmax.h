@@ -10,6 +10,7 @@ struct SoftmaxOpts {
     int inv_degree_first = 15;
     int inv_degree_mid = 15;
     int inv_degree_last = 31;
+    int debug_stop = -1;      // >= 0: return y after that iteration (0 = after exp)
 };
 
 struct SoftmaxStats {

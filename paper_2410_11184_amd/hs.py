@@ -52,7 +52,7 @@ class hs_softmax_opts(ctypes.Structure):
         ("variant", ctypes.c_int), ("k", ctypes.c_int), ("exp_degree", ctypes.c_int),
         ("inv_degree_first", ctypes.c_int), ("inv_degree_mid", ctypes.c_int),
         ("inv_degree_last", ctypes.c_int), ("alpha", ctypes.c_double),
-        ("plain_per_ct", ctypes.c_int),
+        ("plain_per_ct", ctypes.c_int), ("debug_stop", ctypes.c_int),
     ]
 
 
@@ -353,14 +353,14 @@ class Context:
     def bootstrap_stage(self, a, stage):
         return self._op("hs_dbg_bootstrap_stage", a.h, stage)
 
-    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0)):
+    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), debug_stop=-1):
         """hs_softmax over the packed ciphertexts `cts`; returns new handles."""
         m = len(cts)
         arr = (_vp * m)(*[c.h for c in cts])
         out = (_vp * m)()
         o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
                             inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
-                            plain_per_ct=0)
+                            plain_per_ct=0, debug_stop=debug_stop)
         _check(lib().hs_softmax(self.h, arr, m, n, M, ctypes.byref(o), out))
         return [Ciphertext(self, _vp(out[i])) for i in range(m)]
 
