@@ -230,7 +230,9 @@ hs_status hs_prof_collect(hs_ctx* ctx, double* out, size_t n);
 /* Intermediate ciphertexts of hs_bootstrap, for tests: stage 1 = after
  * ModRaise (declared scale 2 q0 (K+1) N/2), 2 = after CoeffToSlot, 3 = real
  * part after the conjugation split, 4 = real part after the cosine
- * polynomial, 5 = real part after the double-angle steps. */
+ * polynomial, 5 / 6 = real / imaginary part after the double-angle steps,
+ * 7 = recombined input of SlotToCoeff, 8 / 9 = after its first / second
+ * level. */
 hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct** out);
 
 /* Raw negacyclic NTT (forward or inverse) of `nrows` rows of N residues

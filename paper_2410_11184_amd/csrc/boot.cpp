@@ -4,7 +4,7 @@
 // precision (Section 5.1, Table "tab:fgb_data"); this pipeline is the
 // standard one for full-slot CKKS and is this library's own design:
 //
-//  1. scale the message so that |m| ~ q0 / 2^14 at the stated bound, keep
+//  1. scale the message so that |m| ~ q0 / 2^13 at the stated bound, keep
 //     the q0 limb and lift it to every Q prime (ModRaise): the result
 //     decrypts to t = m + q0 I with |I| <= K;
 //  2. CoeffToSlot: the inverse special FFT (without its bit reversal) as a
@@ -303,7 +303,8 @@ static void ensure_keys(Context& c, BootCtx& B) {
 }
 
 // baby-step giant-step application of one encoded level; one rescale
-static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x) {
+// (skipped when do_rescale is false: the caller rescales later)
+static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x, bool do_rescale = true) {
     HS_REQUIRE(x.level == lv.level, E_LEVEL, "linear transform: unexpected input level");
     std::map<int, Ct> baby;
     std::set<int> need;
@@ -340,6 +341,7 @@ static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x) {
         }
     }
     for (auto& kv : baby) ct_free(c, kv.second);
+    if (!do_rescale) return acc;
     Ct out = op_rescale(c, acc);
     ct_free(c, acc);
     return out;
@@ -383,8 +385,8 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
     const double q0 = (double)c.primes[0];
     const double Db = std::ldexp(1.0, bp.log_boot_scale);
     const double Bd = std::max(bound, std::ldexp(1.0, -20));
-    // 1. message size |m| ~ q0 / 2^14 at the bound
-    const double target = q0 / 16384.0;
+    // 1. message size |m| ~ q0 / 2^13 at the bound
+    const double target = q0 / 8192.0;
     Ct xx;
     int e = 0;
     if (Bd * x.scale > 2.0 * target && x.level >= 1) {
@@ -406,30 +408,43 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
     ct_free(c, x0);
     t.scale = B.s0;
     if (stop == 1) return t;
-    // 2. CoeffToSlot
-    for (auto& lv : B.cts) {
-        Ct nx = apply_level(c, lv, t);
+    // 2. CoeffToSlot; the last level is left unrescaled so that the
+    // conjugation's key-switching noise is added at scale s * pt_scale and
+    // vanishes in the rescale (it is the largest noise of the pipeline
+    // otherwise: it reaches the output amplified by sqrt(N/2) (K+1) 2^14)
+    for (size_t li = 0; li < B.cts.size(); li++) {
+        const bool last = li + 1 == B.cts.size();
+        Ct nx = apply_level(c, B.cts[li], t, !last);
         ct_free(c, t);
         t = nx;
     }
-    if (stop == 2) return t;
     // 3. real / imaginary split: u_re = t + conj t, u_im = -i (t - conj t)
     Ct cj = op_conjugate(c, t);
     Ct ure = op_add(c, t, cj);
     Ct dif = op_sub(c, t, cj);
-    ct_free(c, t);
-    ct_free(c, cj);
     Ct uim = op_mul_monomial(c, dif, 3 * c.N / 2);
     ct_free(c, dif);
-    if (stop == 3) {
+    ct_free(c, cj);
+    if (stop == 2) {
+        ct_free(c, ure);
         ct_free(c, uim);
-        return ure;
+        Ct r = op_rescale(c, t);
+        ct_free(c, t);
+        return r;
     }
+    ct_free(c, t);
     std::vector<const Ct*> parts{&ure, &uim};
-    Ct u = ct_gather(c, parts);
+    Ct ug = ct_gather(c, parts);
     const int m = x.m;
     ct_free(c, ure);
     ct_free(c, uim);
+    Ct u = op_rescale(c, ug);
+    ct_free(c, ug);
+    if (stop == 3) {
+        Ct r = ct_slice(c, u, 0, m);
+        ct_free(c, u);
+        return r;
+    }
     // 4. EvalMod: cos(2 pi ((K+1) u - 1/4) / 2^r), then r double angles
     Ct v = eval_cheb(c, u, B.pcos, Db);
     ct_free(c, u);
@@ -445,8 +460,8 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
         op_add_const_inplace(c, s, -1.0);
         v = s;
     }
-    if (stop == 5) {
-        Ct r = ct_slice(c, v, 0, m);
+    if (stop == 5 || stop == 6) {
+        Ct r = ct_slice(c, v, stop == 5 ? 0 : m, m);
         ct_free(c, v);
         return r;
     }
@@ -460,10 +475,14 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
     ct_free(c, vi);
     encode_stc(c, B, vre.scale);
     Ct y = vre;
+    if (stop == 7) return y;
+    int lvl_i = 0;
     for (auto& lv : B.stc) {
         Ct ny = apply_level(c, lv, y);
         ct_free(c, y);
         y = ny;
+        lvl_i++;
+        if (stop == 7 + lvl_i) return y;
     }
     // the StC output encodes v * s_msg / Delta at its computed scale
     const double Dout = std::ldexp(1.0, c.prm.log_scale);

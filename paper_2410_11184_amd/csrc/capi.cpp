@@ -607,7 +607,7 @@ hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct**
         NEED(out);
         hs::Context& c = *ctx->c;
         HS_REQUIRE(hs::can_bootstrap(c), hs::E_PARAM, "no bootstrapping parameters");
-        HS_REQUIRE(stage >= 1 && stage <= 5, hs::E_ARG, "stage must be 1..5");
+        HS_REQUIRE(stage >= 1 && stage <= 9, hs::E_ARG, "stage must be 1..9");
         *out = wrap(&c, hs::bootstrap_stage(c, a->ct, 1.0, stage));
     });
 }
