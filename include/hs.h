@@ -58,8 +58,8 @@ typedef struct hs_ct hs_ct;
  * candidates are 2^b + 1 + j 2N for j = 1, -1, 2, -2, ...; the chain takes,
  * in the order q_0..q_{n_q-1} then p_0..p_{n_p-1}, the next unused prime of
  * its size.  Key-switching digits are consecutive blocks of `digit` Q primes;
- * a parameter set whose digit product exceeds P = prod p_k is rejected with
- * HS_E_PARAM.  The bootstrapping fields are ignored when boot_cts_levels is
+ * a parameter set with a digit product above P / 2^20 (P = prod p_k) is
+ * rejected with HS_E_PARAM.  The bootstrapping fields are ignored when boot_cts_levels is
  * 0; otherwise the top boot_cts_levels + boot_evalmod_levels +
  * boot_stc_levels Q primes are reserved for bootstrapping and user_top must
  * equal n_q - 1 minus that count. */
@@ -177,10 +177,14 @@ hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out);
 typedef struct hs_softmax_opts {
     int variant;
     int k;
-    int exp_degree;       /* degree of the exp approximation (2^t - 1)        */
+    int exp_degree;       /* degree of the exp approximation, 2^t - 1; 0 = 15 */
     int inv_degree_first; /* degree of the first normalisation polynomial     */
     int inv_degree_mid;   /* intermediate iterations                          */
-    int inv_degree_last;  /* last iteration                                   */
+    int inv_degree_last;  /* last iteration; 0 for any of the three: 2^d - 1  */
+                          /* with the paper's depths d for dimension n        */
+                          /* (Section 5, auxiliary-thread level table):       */
+                          /* 6, then 4 / 5 / 6 (n <= 128 / <= 512 / larger),  */
+                          /* last 7 / 7 / 8                                   */
     double alpha;         /* reserved (0)                                     */
     int plain_per_ct;     /* reserved (0)                                     */
     int debug_stop;       /* tests: >= 0 returns y after that iteration

@@ -4,7 +4,7 @@
 // precision (Section 5.1, Table "tab:fgb_data"); this pipeline is the
 // standard one for full-slot CKKS and is this library's own design:
 //
-//  1. scale the message so that |m| ~ q0 / 2^13 at the stated bound, keep
+//  1. scale the message so that |m| ~ q0 / 2^9 at the stated bound, keep
 //     the q0 limb and lift it to every Q prime (ModRaise): the result
 //     decrypts to t = m + q0 I with |I| <= K;
 //  2. CoeffToSlot: the inverse special FFT (without its bit reversal) as a
@@ -13,11 +13,19 @@
 //     baby-step giant-step rotations and plaintext products; the slots then
 //     hold (t_lo + i t_hi) / (2 q0 (K+1));
 //  3. split real and imaginary parts with one conjugation;
-//  4. EvalMod on both halves at once: a Chebyshev approximation of
-//     cos(2 pi ((K+1) u - 1/4) / 2^r) followed by r double-angle steps
-//     c -> 2 c^2 - 1, which gives sin(2 pi t / q0) ~ 2 pi m / q0;
-//  5. recombine and SlotToCoeff (the forward butterfly stages), with the
-//     factor q0 / (2 pi Delta) folded into its first matrix.
+//  4. EvalMod on both halves at once, in exponential form:
+//     z = exp(2 pi i (K+1) u / 2^r) from two Chebyshev approximations
+//     (cosine and sine parts, one shared basis), then r squarings give
+//     exp(2 pi i t / q0); a squaring of a unit-modulus value only doubles
+//     its error, where the double-angle formula for the cosine multiplies
+//     it by up to 4 per step;
+//  5. harmonic correction: with x = 2 pi t / q0, z (8 - z) = 8 e^(ix) -
+//     e^(2ix), whose imaginary part 8 sin x - sin 2x = 6 x + O(x^5) has no
+//     cubic term (one level), so the message may sit at q0 / 2^9 instead of
+//     the q0 / 2^13 that the cubic error of sin x alone would demand;
+//  6. V - conj(V) = 2 i Im V: one conjugation of the recombined halves, then
+//     SlotToCoeff (the forward butterfly stages) with the factor
+//     q0 / (24 pi Delta) folded into its first matrix.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -141,7 +149,8 @@ struct BootCtx {
     std::vector<Mat> stc_mats;     // unencoded (scales known at first use)
     std::vector<int> stc_units;
     double stc_in_scale = 0;       // scale the StC plaintexts were made for
-    ChebPoly pcos;
+    std::map<int, LinLevel> stc_masked;  // L -> last StC level times the 0/1 mask of slots [0, L)
+    ChebPoly pcos, psin;          // cos / sin (2 pi (K+1) u / 2^r) on [-1, 1]
     double s0 = 1;                 // declared scale after ModRaise
     bool keys_done = false;
 };
@@ -213,6 +222,8 @@ static BootCtx& boot_ctx(Context& c) {
     const BootParams& bp = c.prm.boot;
     HS_REQUIRE(c.prm.user_top + bp.cts_levels + bp.evalmod_levels + bp.stc_levels == c.L, E_PARAM,
                "bootstrapping levels do not match the modulus chain");
+    HS_REQUIRE(cheb_depth(bp.cos_degree) + bp.double_angle + 1 == bp.evalmod_levels, E_PARAM,
+               "EvalMod levels must be the polynomial depth + squarings + 1");
     BootCtx* B = new BootCtx();
     const int n = c.N / 2;
     int nst = 0;
@@ -281,13 +292,13 @@ static BootCtx& boot_ctx(Context& c) {
             B->stc.push_back(lv);
         }
     }
-    // ---- EvalMod polynomial
+    // ---- EvalMod polynomials (parity enforced: cos is even, sin is odd)
     {
         const long double two_pi = 6.283185307179586476925286766559005768L;
-        const long double K1 = bp.K + 1;
-        const long double sc = ldexpl(1.0L, -bp.double_angle);
-        B->pcos = cheb_fit([&](long double u) { return cosl(two_pi * (K1 * u - 0.25L) * sc); }, -1.0, 1.0,
-                           bp.cos_degree);
+        const long double w = two_pi * (bp.K + 1) * ldexpl(1.0L, -bp.double_angle);
+        B->pcos = cheb_fit([&](long double u) { return cosl(w * u); }, -1.0, 1.0, bp.cos_degree);
+        B->psin = cheb_fit([&](long double u) { return sinl(w * u); }, -1.0, 1.0, bp.cos_degree);
+        for (size_t j = 0; j < B->pcos.c.size(); j++) (j % 2 ? B->pcos.c[j] : B->psin.c[j]) = 0.0;
     }
     reg[&c] = B;
     return *B;
@@ -347,14 +358,19 @@ static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x, bool do_resca
     return out;
 }
 
+// SlotToCoeff plaintexts, encoded once for the EvalMod output scale of an
+// unscaled message (`in_scale`); apply_level tracks the actual scale.
 static void encode_stc(Context& c, BootCtx& B, double in_scale) {
-    if (B.stc_in_scale == in_scale) return;
-    HS_REQUIRE(B.stc_in_scale == 0, E_STATE, "bootstrapping: EvalMod output scale changed");
+    if (B.stc_in_scale != 0) {
+        HS_REQUIRE(std::fabs(B.stc_in_scale / in_scale - 1.0) < 1e-9, E_STATE,
+                   "bootstrapping: EvalMod output scale changed");
+        return;
+    }
     const BootParams& bp = c.prm.boot;
     const double q0 = (double)c.primes[0];
     const double Dout = std::ldexp(1.0, c.prm.log_scale);
     const double two_pi = 6.283185307179586;
-    const double cst = q0 / (two_pi * Dout);
+    const double cst = q0 / (12.0 * two_pi * Dout);   // the input holds 2 (8 sin x - sin 2x), x = 2 pi t / q0
     double s_prev = in_scale;
     for (int gi = 0; gi < bp.stc_levels; gi++) {
         LinLevel& lv = B.stc[gi];
@@ -369,14 +385,42 @@ static void encode_stc(Context& c, BootCtx& B, double in_scale) {
     B.stc_in_scale = in_scale;
 }
 
-Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop);
+// The last SlotToCoeff level with the slot mask [0, L) folded into its
+// diagonals: diag(mask) sum_k diag(d_k) rot_k = sum_k diag(mask d_k) rot_k,
+// so the output is the refreshed value on slots [0, L) and exactly zero (up
+// to the rescaling error) elsewhere, at no extra level.
+static const LinLevel& stc_masked_level(Context& c, BootCtx& B, int L) {
+    auto it = B.stc_masked.find(L);
+    if (it != B.stc_masked.end()) return it->second;
+    const int n = c.N / 2;
+    HS_REQUIRE(L >= 1 && L <= n, E_ARG, "bootstrap: mask length out of range");
+    HS_REQUIRE(B.stc_in_scale != 0, E_STATE, "bootstrap: SlotToCoeff not encoded");
+    const LinLevel& base = B.stc.back();
+    LinLevel lv;
+    lv.level = base.level;
+    lv.unit = base.unit;
+    lv.n1 = base.n1;
+    lv.in_scale = base.in_scale;
+    lv.pt_scale = base.pt_scale;
+    Mat M = B.stc_mats.back();
+    for (auto& kv : M)
+        for (int i = L; i < n; i++) kv.second[i] = 0.0;
+    double constant = 1.0;
+    if (B.stc.size() == 1) {
+        const double two_pi = 6.283185307179586;
+        constant = (double)c.primes[0] / (12.0 * two_pi * std::ldexp(1.0, c.prm.log_scale));
+    }
+    encode_level(c, lv, M, constant);
+    return B.stc_masked.emplace(L, lv).first->second;
+}
 
-Ct bootstrap(Context& c, const Ct& x, double bound) { return bootstrap_stage(c, x, bound, 0); }
+Ct bootstrap(Context& c, const Ct& x, double bound, int mask_L) { return bootstrap_stage(c, x, bound, 0, mask_L); }
 
 // stop: 0 = full; 1 = after ModRaise; 2 = after CoeffToSlot; 3 = real part
-// after the split; 4 = real part after the cosine polynomial; 5 = real part
-// after the double angles (intermediate results for tests)
-Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
+// after the split; 4 = real-part half of z after the polynomials; 5 / 6 =
+// real / imaginary half of z after the squarings; 7 = SlotToCoeff input;
+// 8, 9 = after the first SlotToCoeff levels (intermediate results for tests)
+Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop, int mask_L) {
     HS_REQUIRE(can_bootstrap(c), E_PARAM, "no bootstrapping parameters");
     HS_REQUIRE(x.ncomp == 2, E_ARG, "bootstrap: degree-1 ciphertext expected");
     BootCtx& B = boot_ctx(c);
@@ -385,20 +429,24 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
     const double q0 = (double)c.primes[0];
     const double Db = std::ldexp(1.0, bp.log_boot_scale);
     const double Bd = std::max(bound, std::ldexp(1.0, -20));
-    // 1. message size |m| ~ q0 / 2^13 at the bound
-    const double target = q0 / 8192.0;
+    // 1. message size |m| ~ q0 / 2^9 at the bound
+    const double target = q0 / 512.0;
     Ct xx;
     int e = 0;
+    double kfac = 1.0;   // integer factor the message was scaled up by
     if (Bd * x.scale > 2.0 * target && x.level >= 1) {
         e = (int)std::ceil(std::log2(Bd * x.scale / target));
         xx = op_mul_const(c, x, std::ldexp(1.0, -e), x.scale);
     } else {
         xx = ct_copy(c, x);
-        const double kf = std::floor(target / (Bd * x.scale));
+        // at most 16: the factor is undone inside EvalMod (below), which
+        // lowers the SlotToCoeff scales by the same factor
+        const double kf = std::min(std::floor(target / (Bd * x.scale)), 16.0);
         if (kf >= 2.0) {
-            const long long K = (long long)std::min(kf, 1e15);
+            const long long K = (long long)kf;
             op_mul_int_inplace(c, xx, K);
             xx.scale = x.scale * (double)K;
+            kfac = (double)K;
         }
     }
     const double s_msg = xx.scale;
@@ -445,39 +493,70 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop) {
         ct_free(c, u);
         return r;
     }
-    // 4. EvalMod: cos(2 pi ((K+1) u - 1/4) / 2^r), then r double angles
-    Ct v = eval_cheb(c, u, B.pcos, Db);
-    ct_free(c, u);
+    // 4. EvalMod: z = exp(2 pi i (K+1) u / 2^r), then r squarings.  The
+    // polynomial's output scale Db kfac^(-2^-(r+1)) becomes, after the r
+    // squarings and the product of step 5, a physical scale kfac times
+    // lower than for kfac = 1: the SlotToCoeff output then carries the
+    // message at the input's scale instead of kfac times it.
+    Ct z;
+    {
+        const double Dp = Db * std::pow(kfac, -std::ldexp(1.0, -(bp.double_angle + 1)));
+        std::vector<Ct> pq = eval_cheb_many(c, u, {&B.pcos, &B.psin}, Dp);
+        ct_free(c, u);
+        Ct is = op_mul_monomial(c, pq[1], c.N / 2);
+        z = op_add(c, pq[0], is);
+        ct_free(c, is);
+        ct_free(c, pq[0]);
+        ct_free(c, pq[1]);
+    }
     if (stop == 4) {
-        Ct r = ct_slice(c, v, 0, m);
-        ct_free(c, v);
+        Ct r = ct_slice(c, z, 0, m);
+        ct_free(c, z);
         return r;
     }
     for (int r = 0; r < bp.double_angle; r++) {
-        Ct s = op_mult(c, v, v);
-        ct_free(c, v);
-        op_mul_int_inplace(c, s, 2);
-        op_add_const_inplace(c, s, -1.0);
-        v = s;
+        Ct s = op_mult(c, z, z);
+        ct_free(c, z);
+        z = s;
     }
     if (stop == 5 || stop == 6) {
-        Ct r = ct_slice(c, v, stop == 5 ? 0 : m, m);
-        ct_free(c, v);
+        Ct r = ct_slice(c, z, stop == 5 ? 0 : m, m);
+        ct_free(c, z);
         return r;
     }
-    // 5. recombine (re + i im) and SlotToCoeff
-    Ct vre = ct_slice(c, v, 0, m);
-    Ct vim = ct_slice(c, v, m, m);
-    ct_free(c, v);
-    Ct vi = op_mul_monomial(c, vim, c.N / 2);
-    ct_free(c, vim);
-    op_add_inplace(c, vre, vi);
-    ct_free(c, vi);
-    encode_stc(c, B, vre.scale);
+    // 5. V = z (8 - z)
+    {
+        Ct w = ct_copy(c, z);
+        op_neg_inplace(c, w);
+        op_add_const_inplace(c, w, 8.0);
+        Ct v = op_mult(c, z, w);
+        ct_free(c, w);
+        ct_free(c, z);
+        z = v;
+    }
+    // 6. y = 2 (Im V_re + i Im V_im) = A - conj(B) with
+    //    A = -i V_re + V_im and B = i V_re + V_im
+    Ct zre = ct_slice(c, z, 0, m);
+    Ct zim = ct_slice(c, z, m, m);
+    ct_free(c, z);
+    Ct A = op_mul_monomial(c, zre, 3 * c.N / 2);
+    op_add_inplace(c, A, zim);
+    Ct Bp = op_mul_monomial(c, zre, c.N / 2);
+    op_add_inplace(c, Bp, zim);
+    ct_free(c, zre);
+    ct_free(c, zim);
+    Ct cB = op_conjugate(c, Bp);
+    ct_free(c, Bp);
+    Ct vre = op_sub(c, A, cB);
+    ct_free(c, A);
+    ct_free(c, cB);
+    encode_stc(c, B, vre.scale * kfac);
     Ct y = vre;
     if (stop == 7) return y;
+    const LinLevel* last_masked = mask_L > 0 ? &stc_masked_level(c, B, mask_L) : nullptr;
     int lvl_i = 0;
-    for (auto& lv : B.stc) {
+    for (size_t gi = 0; gi < B.stc.size(); gi++) {
+        const LinLevel& lv = (last_masked && gi + 1 == B.stc.size()) ? *last_masked : B.stc[gi];
         Ct ny = apply_level(c, lv, y);
         ct_free(c, y);
         y = ny;

@@ -214,14 +214,17 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     std::vector<int> bits = p.q_bits;
     bits.insert(bits.end(), p.p_bits.begin(), p.p_bits.end());
     primes = find_primes(logN, bits);
-    // every key-switching digit must be smaller than P, or the switching
-    // noise (about digit / P times the key error) swamps the message
+    // every key-switching digit must be far below P: the switching noise is
+    // about (digit / P) * (primes per digit) * sigma * sqrt(N) per coefficient
+    // on top of the ModDown rounding, and it lands on the raw message (in
+    // bootstrapping, before CoeffToSlot has scaled anything up); a 2^20
+    // margin keeps it below the rounding term
     double logP = 0;
     for (int k = 0; k < np; k++) logP += std::log2((double)primes[nq + k]);
     for (int j = 0; j < dnum; j++) {
         double lg = 0;
         for (int i = j * p.digit; i < std::min(nq, (j + 1) * p.digit); i++) lg += std::log2((double)primes[i]);
-        HS_REQUIRE(lg <= logP + 1.0, E_PARAM, "a key-switching digit exceeds the special modulus P");
+        HS_REQUIRE(lg + 20.0 <= logP, E_PARAM, "a key-switching digit is not 2^20 below the special modulus P");
     }
     const int nt = nq + np;
     pinfo.resize(nt);

@@ -6,14 +6,20 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "host.h"
 
 namespace hs {
 
-static void check_scales(double a, double b) {
-    HS_REQUIRE(std::fabs(a / b - 1.0) < 1e-9, E_SCALE, "operands have different scales");
+static void check_scales(double a, double b, const char* op) {
+    if (!(std::fabs(a / b - 1.0) < 1e-9)) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "%s: operands have different scales (2^%.9f vs 2^%.9f)", op, std::log2(a),
+                      std::log2(b));
+        throw Error(E_SCALE, msg);
+    }
 }
 
 static Rows comp_rows_bcast(const Context& c, const Ct& a, int comp, int m_target) {
@@ -29,7 +35,7 @@ void op_add_inplace(Context& c, Ct& a, const Ct& b) {
     HS_REQUIRE(a.level == b.level, E_LEVEL, "add: levels differ");
     HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "add: batch sizes differ");
     HS_REQUIRE(b.ncomp <= a.ncomp, E_ARG, "add: component count");
-    check_scales(a.scale, b.scale);
+    check_scales(a.scale, b.scale, "add");
     for (int k = 0; k < b.ncomp; k++) {
         Rows o = c.comp_rows(a, k);
         k_add(c.T, o, o, comp_rows_bcast(c, b, k, a.m), c.stream);
@@ -40,7 +46,7 @@ void op_sub_inplace(Context& c, Ct& a, const Ct& b) {
     HS_REQUIRE(a.level == b.level, E_LEVEL, "sub: levels differ");
     HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "sub: batch sizes differ");
     HS_REQUIRE(b.ncomp <= a.ncomp, E_ARG, "sub: component count");
-    check_scales(a.scale, b.scale);
+    check_scales(a.scale, b.scale, "sub");
     for (int k = 0; k < b.ncomp; k++) {
         Rows o = c.comp_rows(a, k);
         k_sub(c.T, o, o, comp_rows_bcast(c, b, k, a.m), c.stream);

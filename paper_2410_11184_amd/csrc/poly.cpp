@@ -13,6 +13,7 @@
 //    sum_j c_j T_j multiplies T_j by the integer rint(c_j S q / s_j) so that
 //    all terms share the scale S q before the single rescale of the leaf.
 //    Depth: ceil(log2(d+1)) + 1 (the +1 is the leaf's constant products).
+#include <algorithm>
 #include <cmath>
 #include <functional>
 #include <map>
@@ -75,7 +76,7 @@ struct Val {
 struct Evaluator {
     Context& c;
     std::map<int, Ct> T;          // Chebyshev basis polynomials of u
-    std::map<std::pair<int, long long>, Ct> t1_at;  // T_1 adjusted to (level, scale key)
+    std::map<std::pair<int, double>, Ct> t1_at;  // T_1 adjusted to (level, exact scale)
     int B = 2;
     // When set: every leaf constant c is replaced by the plaintext c * mask
     // (mask = device coefficients of a 0/1 slot vector), which multiplies the
@@ -115,8 +116,10 @@ struct Evaluator {
 
     // T_1 brought to (level, scale) by a scale-exact constant product
     const Ct& t1_adjusted(int level, double scale) {
-        long long key = (long long)std::llround(std::log2(scale) * 1e6);
-        auto k = std::make_pair(level, key);
+        // keyed by the exact scale: scales of one level differ by the primes'
+        // offsets from a power of two (~2^-40 relative), and a T_1 at a
+        // neighbouring scale would add that relative error to T_j
+        auto k = std::make_pair(level, scale);
         auto it = t1_at.find(k);
         if (it != t1_at.end()) return it->second;
         const Ct& t1 = T.at(1);
@@ -267,6 +270,29 @@ struct Evaluator {
 };
 
 }  // namespace
+
+std::vector<Ct> eval_cheb_many(Context& c, const Ct& x, const std::vector<const ChebPoly*>& ps, double target_scale) {
+    HS_REQUIRE(!ps.empty(), E_ARG, "no polynomial");
+    int d = 0;
+    for (const ChebPoly* p : ps) {
+        HS_REQUIRE(p->a == -1.0 && p->b == 1.0, E_ARG, "shared-basis evaluation expects polynomials on [-1, 1]");
+        d = std::max(d, (int)p->c.size() - 1);
+    }
+    HS_REQUIRE(d >= 1, E_ARG, "polynomial degree must be >= 1");
+    const int t = ceil_log2(d + 1);
+    const int out_level = x.level - (t + 1);
+    HS_REQUIRE(out_level >= 0, E_LEVEL, "polynomial evaluation: level budget exhausted");
+    Evaluator ev(c);
+    ev.B = 1 << std::max(1, (t + 1) / 2);
+    ev.T[1] = ct_copy(c, x);
+    std::vector<Ct> out;
+    for (const ChebPoly* p : ps) {
+        Val v = ev.eval(p->c, target_scale, out_level);
+        HS_REQUIRE(!v.is_const, E_ARG, "constant polynomial");
+        out.push_back(v.ct);
+    }
+    return out;
+}
 
 Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, const double* mask) {
     const int d = (int)p.c.size() - 1;

@@ -19,8 +19,15 @@
 //    the many ciphertexts case"): bootstrap the auxiliary ciphertext before
 //    the normalisation polynomial when its budget is short, again afterwards
 //    if its level is below what the main thread needs, and the main thread
-//    only when its own budget runs out.
+//    only when its own budget runs out.  The normalisation factors (lambda_j,
+//    and Lambda in version B) are bootstrapped while they sit on slots
+//    [0, L) only, with the mask folded into the bootstrap, and broadcast
+//    afterwards: the bootstrapping error is then one value per Softmax, a
+//    common factor that the next renormalisation removes, instead of an
+//    independent error per element that the squarings amplify by 2^k.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "host.h"
@@ -89,15 +96,32 @@ static void free_interval(double lo, double hi, double& a, double& b) {
 // bound on |Lambda| used to scale it into the bootstrapping range
 static double lam_bound_big(Context&, const Ct&, double lam_bound) { return std::max(64.0, lam_bound); }
 
-static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxStats& st, bool& replaced) {
+// Bootstrap x when its level is below `need`.  mask_L > 0: x is zero off
+// slots [0, L) and the refreshed value is masked the same way, so that its
+// bootstrapping error, once broadcast, is the same for every element of a
+// Softmax and is removed by the next renormalisation.
+static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxStats& st, bool& replaced,
+                       const char* what, int iter, int mask_L = 0) {
     replaced = false;
     if (x.level >= need) return x;
     HS_REQUIRE(can_bootstrap(c), E_LEVEL, "Softmax: level budget exhausted and no bootstrapping configured");
-    Ct b = bootstrap(c, x, bound);
+    if (std::getenv("HS_TRACE"))
+        std::fprintf(stderr, "[hs] softmax iteration %d: bootstrap %s (%d ct, level %d -> need %d, bound %g%s)\n",
+                     iter, what, x.m, x.level, need, bound, mask_L ? ", masked" : "");
+    Ct b = bootstrap(c, x, bound, mask_L);
     st.bootstraps += x.m;
     replaced = true;
     HS_REQUIRE(b.level >= need, E_LEVEL, "Softmax: bootstrapping does not restore enough levels");
     return b;
+}
+
+// rotate-and-add with strides +L 2^t: slots [0, L) copied to all n/m blocks
+static void broadcast(Context& c, Ct& a, int L, int nrot) {
+    for (int t = 0; t < nrot; t++) {
+        Ct rr = op_rotate(c, a, L << t);
+        op_add_inplace(c, a, rr);
+        ct_free(c, rr);
+    }
 }
 
 Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats) {
@@ -141,15 +165,21 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     const double* mask = mask_coeffs(c, L);
 
     Ct y = ct_copy(c, y0);      // y^(j-1)
-    Ct big;                     // Lambda (version B)
+    Ct big;                     // Lambda (version B), on slots [0, L) only
     bool have_big = false;
+    double ybound = isn * 1.05; // bound on |y^(j-1)| for its bootstrapping
     double lo = std::exp(-2.0 * M / std::ldexp(1.0, k)) * 0.98, hi = 1.0;
     for (int j = 1; j <= k; j++) {
         const bool last = j == k;
         const bool smb_step = smb && !last;
         // exponent of the normalisation: 1/2 (SM, and the last step of B) or 2^-j
         const double e = smb_step ? std::ldexp(1.0, -j) : 0.5;
-        const int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
+        int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
+        if (deg <= 0) {
+            const int dmid = n <= 128 ? 4 : (n <= 512 ? 5 : 6);
+            const int d = j == 1 ? 6 : (last ? (n <= 512 ? 7 : 8) : dmid);
+            deg = (1 << d) - 1;
+        }
         double a, b;
         free_interval(lo, hi, a, b);
         const double ee = e;
@@ -159,7 +189,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // main thread must keep one level for the square feeding S
         if (!smb) {
             bool rep;
-            Ct y2 = ensure_level(c, y, last ? 2 : 3, 1.0, st, rep);
+            Ct y2 = ensure_level(c, y, last ? 2 : 3, ybound, st, rep, "y", j);
             if (rep) {
                 ct_free(c, y);
                 y = y2;
@@ -180,35 +210,30 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // budget of the normalisation polynomial (mask folded into its leaves)
         {
             bool rep;
-            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 1, hi * 1.1, st, rep);
+            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 1, hi * 1.1, st, rep, "S", j);
             if (rep) {
                 ct_free(c, S);
                 S = S2;
             }
         }
-        // normalisation and mask: lambda = P(S) * mask
+        // normalisation and mask: lambda = P(S) * mask, on slots [0, L)
         Ct lam = eval_cheb(c, S, pinv, Delta, mask);
         ct_free(c, S);
-        // broadcast of slots [0, L) to all n/m positions
-        for (int t = 0; t < nrot; t++) {
-            Ct rr = op_rotate(c, lam, L << t);
-            op_add_inplace(c, lam, rr);
-            ct_free(c, rr);
-        }
         if (!smb_step) {
             // SM step (and the last step of version B): z = lambda y, y = z^2.
-            // y ends at min(y, lambda) - 2; bootstrap lambda only when it is the
-            // ciphertext that leaves y short of the next iteration's need (3, or
-            // 2 before the last step).
+            // y ends at min(y, lambda) - 2; bootstrap lambda (masked, before
+            // its broadcast) only when it is the ciphertext that leaves y
+            // short of the next iteration's need (3, or 2 before the last step).
             const int need_next = (j + 1 == k) ? 2 : 3;
             if (!last && can_bootstrap(c) && lam.level < y.level && lam.level - 2 < need_next) {
                 bool rep;
-                Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep);
+                Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep, "lambda", j, L);
                 if (rep) {
                     ct_free(c, lam);
                     lam = l2;
                 }
             }
+            broadcast(c, lam, L, nrot);
             Ct z = op_mult(c, y, lam);
             ct_free(c, lam);
             ct_free(c, y);
@@ -216,8 +241,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             ct_free(c, z);
             lo = std::pow(1.0 - delta, 4.0) / n * 0.98;
             hi = std::pow(1.0 + delta, 4.0) * 1.0001;
+            ybound = hi * 1.05;
         } else {
-            // version B: Lambda = Lambda * lambda_j; z = Lambda y0; y = z^(2^j)
+            // version B: Lambda = Lambda * lambda_j (both on slots [0, L));
+            // z = broadcast(Lambda) y0; y = z^(2^j)
             if (!have_big) {
                 big = lam;
                 have_big = true;
@@ -234,13 +261,16 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             HS_REQUIRE(y0.level >= want, E_LEVEL, "Softmax version B: main-thread level budget exhausted");
             if (big.level < want) {
                 bool rep;
-                Ct b2 = ensure_level(c, big, want, lam_bound_big(c, big, lam_bound), st, rep);
+                Ct b2 = ensure_level(c, big, want, lam_bound_big(c, big, lam_bound), st, rep, "Lambda", j, L);
                 if (rep) {
                     ct_free(c, big);
                     big = b2;
                 }
             }
-            Ct z = op_mult(c, y0, big);
+            Ct bb = ct_copy(c, big);
+            broadcast(c, bb, L, nrot);
+            Ct z = op_mult(c, y0, bb);
+            ct_free(c, bb);
             ct_free(c, y);
             y = z;
             for (int s = 0; s < j; s++) {

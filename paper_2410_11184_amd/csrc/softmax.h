@@ -7,9 +7,13 @@ struct SoftmaxOpts {
     int variant = 0;          // 0 = SM (Algorithm SM), 1 = SM version B
     int k = 0;                // iterations; 0 = ceil(log M - log ln n)
     int exp_degree = 15;
-    int inv_degree_first = 15;
-    int inv_degree_mid = 15;
-    int inv_degree_last = 31;
+    // 0 = the depths the paper uses for dimension n (Section 5, table of the
+    // auxiliary thread's level usage): degrees 2^d - 1 with d = 6 for the
+    // first iteration, 4 / 5 / 6 for the intermediate ones (n <= 128 /
+    // n <= 512 / larger) and 7 / 7 / 8 for the last one
+    int inv_degree_first = 0;
+    int inv_degree_mid = 0;
+    int inv_degree_last = 0;
     int debug_stop = -1;      // >= 0: return y after that iteration (0 = after exp)
 };
 
@@ -26,7 +30,9 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
 
 bool can_bootstrap(const Context& c);
 // Refresh x (any level) to the top user level; `bound` bounds |slot values|.
-Ct bootstrap(Context& c, const Ct& x, double bound);
-Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop);
+// With mask_L > 0 the result is also multiplied by the 0/1 mask of slots
+// [0, L) (folded into the last SlotToCoeff matrix, no extra level).
+Ct bootstrap(Context& c, const Ct& x, double bound, int mask_L = 0);
+Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop, int mask_L = 0);
 
 }  // namespace hs

@@ -33,30 +33,31 @@ PRESETS = {
         user_top=23,
         boot=None,
     ),
-    # N = 2^16, scale 2^40, sparse ternary secret of weight 192, three digits
-    # (dnum = 3), twelve user levels above q0, full-slot bootstrapping.
+    # N = 2^16, scale 2^40, sparse ternary secret of weight 192, digits of 8
+    # primes (dnum = 4, P 2^60 above the largest digit), twelve user levels
+    # above q0, full-slot bootstrapping.
     "fgb16": dict(
         logN=16,
-        q_bits=[53] + [40] * 12 + [40] * 3 + [58] * 10 + [60] * 3,
-        p_bits=[59] * 9,
-        digit=10,
+        q_bits=[53] + [40] * 12 + [40] * 3 + [60] * 11 + [60] * 3,
+        p_bits=[60] * 9,
+        digit=8,
         hamming=192,
         log_scale=40,
         user_top=12,
-        boot=dict(stc_levels=3, evalmod_levels=10, cts_levels=3,
-                  K=32, double_angle=3, cos_degree=63, log_boot_scale=58),
+        boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
+                  K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
     ),
     # Small ring with the same bootstrapping structure, for fast tests.
     "boot10": dict(
         logN=10,
-        q_bits=[53] + [40] * 4 + [40] * 3 + [58] * 10 + [60] * 3,
+        q_bits=[53] + [40] * 4 + [40] * 3 + [60] * 11 + [60] * 3,
         p_bits=[59] * 8,
         digit=7,
         hamming=64,
         log_scale=40,
         user_top=4,
-        boot=dict(stc_levels=3, evalmod_levels=10, cts_levels=3,
-                  K=32, double_angle=3, cos_degree=63, log_boot_scale=58),
+        boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
+                  K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
     ),
 }
 
