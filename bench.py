@@ -56,7 +56,7 @@ def _traffic(kind):
         return None
 
 
-def cpu_baseline(seconds_budget=20.0):
+def cpu_baseline(seconds_budget=12.0):
     """The oracle (plain single-threaded C + Python) timed on this host on a
     bounded sample: key switches of one ciphertext at N = 2^16, which dominate
     the job.  Returned as Softmax calls/s by scaling with the number of key
@@ -76,9 +76,23 @@ def cpu_baseline(seconds_budget=20.0):
         s = time.perf_counter()
         o.mult(a, a)
         times.append(time.perf_counter() - s)
-        if time.perf_counter() - t0 > seconds_budget or len(times) >= 3:
+        if time.perf_counter() - t0 > seconds_budget or len(times) >= 12:
             break
     return dict(hmult_s=float(np.median(times)), setup_s=setup, samples=len(times))
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain copy kernel of known size: each repetition reads and writes
+    exactly `nbytes`; the counters it produces give the scale of FETCH_SIZE
+    and WRITE_SIZE against true HBM bytes."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
 def main():
@@ -89,7 +103,12 @@ def main():
     ap.add_argument("--workload", default="fgb16_smb64")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the path on a single MI355X; "
               "multi-GPU sharding is design-only (see the repository documentation).", file=sys.stderr)
@@ -155,7 +174,7 @@ def main():
     plain = None
     if not args.no_plain:
         wp = synthetic.WORKLOADS["fgb16_sm"]
-        xp = synthetic.logits_uniform(p["slots"] // n, n, M, seed=4002)
+        xp = synthetic.workload_logits("fgb16_sm")
         ctp = encrypt_logits(ctx, xp, M, seed=5002)
         ctx.softmax(ctp, n, M, variant=0)            # warm the plain schedule
         ctx.sync()

@@ -268,6 +268,17 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     T.itw = (const u64*)dev_table(itw.data(), itw.size() * 8);
     T.itws = (const u64*)dev_table(itws.data(), itws.size() * 8);
     T.ninv = (const u64*)dev_table(ninv.data(), ninv.size() * 8);
+    {
+        std::vector<u64> a(2 * (size_t)nt * N), b(2 * (size_t)nt * N);
+        for (size_t k = 0; k < (size_t)nt * N; k++) {
+            a[2 * k] = tw[k];
+            a[2 * k + 1] = tws[k];
+            b[2 * k] = itw[k];
+            b[2 * k + 1] = itws[k];
+        }
+        T.tw2 = (const u64*)dev_table(a.data(), a.size() * 8);
+        T.itw2 = (const u64*)dev_table(b.data(), b.size() * 8);
+    }
     T.logN = logN;
     T.N = N;
     T.prof = prof_create();

@@ -37,6 +37,8 @@ struct DevTables {
     const u64* itw;           // [n_primes][N]   psi^-brv(k)
     const u64* itws;
     const u64* ninv;          // [n_primes][2]   N^-1 mod q, Shoup companion
+    const u64* tw2;           // [n_primes][N][2] (psi^brv(k), Shoup companion) interleaved
+    const u64* itw2;          // [n_primes][N][2] (psi^-brv(k), Shoup companion) interleaved
     int logN;
     int N;
     Profiler* prof;           // optional launch profiler (host object)

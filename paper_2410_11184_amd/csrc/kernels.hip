@@ -324,6 +324,163 @@ __global__ void __launch_bounds__(256) ntt_pass2_kernel(DevTables T, Rows x, int
     for (int e = threadIdx.x; e < TR * C; e += blockDim.x) p[e] = sm[e];
 }
 
+// ---- N = 2^16: two passes of 256-point sub-transforms (index j = 16 hi + lo)
+// on tiles of 16 sub-transforms.  Pass 1 takes stages 0..7 on columns
+// (stride 256), pass 2 stages 8..15 on contiguous chunks of 256.  Each thread
+// keeps 16 elements in registers and runs 4 stages on them (radix 16); one
+// LDS exchange switches from the hi-stages to the lo-stages.  The twiddle of
+// stage s, group i is tw[2^s + i]; on 16 registers spanning local bits 3..0
+// with prefix P it is tw[((2^S0 + P) << a) + g] for local stage a, group g.
+// Rows are visited prime-major so that the twiddles of one prime stay in L2.
+
+__device__ __forceinline__ int ntt_row_prime_major(const Rows& x, int y) {
+    const int g = y % x.ngroups;
+    return g * x.rpg + y / x.ngroups;
+}
+
+__device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q) {
+    ulonglong2 W[15];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int g = 0; g < (1 << a); g++) W[(1 << a) - 1 + g] = tw[(base << a) + g];
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int h = 8 >> a;
+#pragma unroll
+        for (int g = 0; g < (1 << a); g++) {
+            const ulonglong2 w = W[(1 << a) - 1 + g];
+#pragma unroll
+            for (int j = 0; j < h; j++) {
+                const int k = g * 2 * h + j;
+                const u64 u = E[k];
+                const u64 v = mul_shoup(E[k + h], w.x, w.y, q);
+                E[k] = add_mod(u, v, q);
+                E[k + h] = sub_mod(u, v, q);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q) {
+    ulonglong2 W[15];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int g = 0; g < (1 << a); g++) W[(1 << a) - 1 + g] = tw[(base << a) + g];
+#pragma unroll
+    for (int a = 3; a >= 0; a--) {
+        const int h = 8 >> a;
+#pragma unroll
+        for (int g = 0; g < (1 << a); g++) {
+            const ulonglong2 w = W[(1 << a) - 1 + g];
+#pragma unroll
+            for (int j = 0; j < h; j++) {
+                const int k = g * 2 * h + j;
+                const u64 u = E[k];
+                const u64 v = E[k + h];
+                E[k] = add_mod(u, v, q);
+                E[k + h] = mul_shoup(sub_mod(u, v, q), w.x, w.y, q);
+            }
+        }
+    }
+}
+
+// LDS tile layouts (u64 units), conflict-free for both access patterns:
+// pass 1 element (hi, lo, column c) at hi*272 + lo*16 + c,
+// pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
+#define NTT16_LDS (16 * 272)
+
+__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, int inverse) {
+    __shared__ u64 sm[NTT16_LDS];
+    const int row = ntt_row_prime_major(x, blockIdx.y);
+    u64* p = row_ptr(x, row, 65536) + blockIdx.x * 16;
+    const int pi = prime_of(x, row % x.rpg);
+    const u64 q = T.prime[pi].q;
+    const int t = threadIdx.x, c = t & 15, hl = t >> 4;
+    u64 E[16];
+    if (!inverse) {
+        const ulonglong2* tw = (const ulonglong2*)T.tw2 + (size_t)pi * 65536;
+        // thread (lo = hl, c): hi = 0..15, stages 0..3
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) E[hi] = p[(size_t)(hi * 16 + hl) * 256 + c];
+        fwd16(E, tw, 1, q);
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) sm[hi * 272 + hl * 16 + c] = E[hi];
+        __syncthreads();
+        // thread (hi = hl, c): lo = 0..15, stages 4..7
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) E[lo] = sm[hl * 272 + lo * 16 + c];
+        fwd16(E, tw, 16 + hl, q);
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) p[(size_t)(hl * 16 + lo) * 256 + c] = E[lo];
+    } else {
+        const ulonglong2* tw = (const ulonglong2*)T.itw2 + (size_t)pi * 65536;
+        // thread (hi = hl, c): lo = 0..15, stages 7..4
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) E[lo] = p[(size_t)(hl * 16 + lo) * 256 + c];
+        inv16(E, tw, 16 + hl, q);
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) sm[hl * 272 + lo * 16 + c] = E[lo];
+        __syncthreads();
+        // thread (lo = hl, c): hi = 0..15, stages 3..0, then N^-1
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) E[hi] = sm[hi * 272 + hl * 16 + c];
+        inv16(E, tw, 1, q);
+        const u64 ni = T.ninv[2 * pi], nis = T.ninv[2 * pi + 1];
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) p[(size_t)(hi * 16 + hl) * 256 + c] = mul_shoup(E[hi], ni, nis, q);
+    }
+}
+
+__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, int inverse) {
+    __shared__ u64 sm[NTT16_LDS];
+    const int row = ntt_row_prime_major(x, blockIdx.y);
+    const int pi = prime_of(x, row % x.rpg);
+    const u64 q = T.prime[pi].q;
+    const int t = threadIdx.x, w = t >> 4, l = t & 15;
+    const u32 R = blockIdx.x * 16 + w;             // chunk index
+    u64* p = row_ptr(x, row, 65536) + (size_t)R * 256;
+    const ulonglong2* tw = (const ulonglong2*)(inverse ? T.itw2 : T.tw2) + (size_t)pi * 65536;
+    u64* s = sm + w * 272;
+    u64 E[16];
+    // coalesced load: thread (w, lo = l) takes hi = 0..15
+#pragma unroll
+    for (int hi = 0; hi < 16; hi++) E[hi] = p[hi * 16 + l];
+    if (!inverse) {
+        fwd16(E, tw, 256 + R, q);                   // stages 8..11
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) s[hi * 17 + l] = E[hi];
+        __syncthreads();
+        // thread (w, hi = l): lo = 0..15, stages 12..15 (in place in LDS)
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) E[lo] = s[l * 17 + lo];
+        fwd16(E, tw, 4096 + R * 16 + l, q);
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) s[l * 17 + lo] = E[lo];
+        __syncthreads();
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = s[hi * 17 + l];
+    } else {
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) s[hi * 17 + l] = E[hi];
+        __syncthreads();
+        // thread (w, hi = l): lo = 0..15, stages 15..12
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) E[lo] = s[l * 17 + lo];
+        inv16(E, tw, 4096 + R * 16 + l, q);
+#pragma unroll
+        for (int lo = 0; lo < 16; lo++) s[l * 17 + lo] = E[lo];
+        __syncthreads();
+        // thread (w, lo = l): hi = 0..15, stages 11..8
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) E[hi] = s[hi * 17 + l];
+        inv16(E, tw, 256 + R, q);
+#pragma unroll
+        for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = E[hi];
+    }
+}
+
 void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) {
     const int nrows = x.ngroups * x.rpg;
     if (nrows == 0) return;
@@ -332,6 +489,17 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) {
     if (T.N <= 4096) {
         hipLaunchKernelGGL(ntt_small_kernel, dim3(nrows), dim3(256), T.N * sizeof(u64), st, T, x,
                            inverse ? 1 : 0);
+        return;
+    }
+    if (T.logN == 16) {
+        const dim3 g(16, nrows);
+        if (!inverse) {
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, 0);
+            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, 0);
+        } else {
+            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, 1);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, 1);
+        }
         return;
     }
     const int logC = (T.logN + 1) / 2, logR = T.logN - logC;

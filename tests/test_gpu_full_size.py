@@ -1,0 +1,101 @@
+"""Full-size parity: the N = 2^16 parameter set of the Softmax benchmark.
+
+* Ring level: the batched NTT (the two-pass radix-16 kernels used only at
+  N = 2^16) on rows of every prime size, keys, encryption, one homomorphic
+  multiplication at the top user level and one rotation by a Softmax stride,
+  compared bit for bit with the CPU oracle on the same seeds.
+* Softmax level: the oracle cannot run an encrypted Softmax at this size (no
+  bootstrapping), so the full workloads are checked by the property that
+  defines the target: >= 16 bits worst case against the FP64 Softmax, and rows
+  summing to 1.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+SEED = 31337
+
+
+@pytest.fixture(scope="module")
+def pair():
+    from paper_2410_11184_amd import hs
+    from oracle import ckks
+    p = synthetic.preset("fgb16")
+    g = hs.Context(p)
+    o = ckks.Context(**p)
+    L = 64 * o.slots // 256            # Softmax stride of the batched workload
+    g.keygen(SEED, rotations=[-L])
+    o.keygen(SEED, galois=[o.galois_rot(-L, o.N)])
+    return g, o, L
+
+
+def _same(gct, oct_):
+    w = gct.export()
+    assert w.shape[0] == len(oct_.c) and w.shape[1] == oct_.level + 1
+    for k in range(len(oct_.c)):
+        assert np.array_equal(w[k], oct_.c[k]), "component %d differs" % k
+
+
+def test_ntt_every_prime_size(pair):
+    g, o, _ = pair
+    rng = np.random.default_rng(3)
+    nq = len(o.q)
+    # q0 (53 bits), a user prime (40), an EvalMod prime (60), a CtS prime (60), two P primes
+    for idx in (0, 5, 20, nq - 1, nq, nq + len(o.p) - 1):
+        q = o.primes[idx]
+        x = rng.integers(0, q, (2, o.N), dtype=np.uint64)
+        x[1, :8] = q - 1                        # extreme residues
+        f = g.ntt(x, idx)
+        for r in range(2):
+            assert np.array_equal(f[r], o.ntt(x[r], idx)), idx
+        assert np.array_equal(g.ntt(f, idx, inverse=True), x), idx
+
+
+def test_keys_and_encryption(pair):
+    g, o, L = pair
+    assert g.primes() == o.primes
+    assert np.array_equal(g.secret(), o.s_coeff)
+    kg = g.key_export(0)
+    for j in range(o.dnum):
+        assert np.array_equal(kg[j, 0], np.stack(o.keys[0][j][0])), j
+        assert np.array_equal(kg[j, 1], np.stack(o.keys[0][j][1])), j
+    z = np.random.default_rng(4).uniform(-1, 1, o.slots)
+    _same(g.encrypt(z, 12, o.delta, 5), o.encode_encrypt(z, o.delta, 12, 5))
+
+
+def test_mult_and_rotation_at_top_user_level(pair):
+    g, o, L = pair
+    r = np.random.default_rng(5)
+    za, zb = r.uniform(-1, 1, o.slots), r.uniform(-1, 1, o.slots)
+    ga, gb = g.encrypt(za, 12, o.delta, 6), g.encrypt(zb, 12, o.delta, 7)
+    oa, ob = o.encode_encrypt(za, o.delta, 12, 6), o.encode_encrypt(zb, o.delta, 12, 7)
+    m = g.mult(ga, gb)
+    om = o.mult(oa, ob)
+    _same(m, om)
+    rot = g.rotate(m, -L)
+    _same(rot, o.rotate(om, -L))
+    assert np.max(np.abs(g.decrypt(rot) - np.roll(za * zb, L))) < 2 ** -20
+
+
+@pytest.fixture(scope="module")
+def boot_ctx():
+    from paper_2410_11184_amd import hs
+    c = hs.Context(synthetic.preset("fgb16"))
+    c.keygen(2002)
+    return c
+
+
+@pytest.mark.parametrize("workload,variant", [("fgb16_smb64", "B"), ("fgb16_sm", "SM")])
+def test_softmax_workload_precision(boot_ctx, workload, variant):
+    from oracle import softmax as S
+    from paper_2410_11184_amd.softmax import softmax_encrypted
+    w = synthetic.WORKLOADS[workload]
+    x = synthetic.workload_logits(workload)
+    y = softmax_encrypted(boot_ctx, x, w["M"], variant=variant, seed=9)
+    bits = S.precision_bits(S.softmax(x), y)
+    print(workload, variant, bits, boot_ctx.softmax_stats())
+    assert bits["worst"] >= 16.0, bits
+    assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -14
