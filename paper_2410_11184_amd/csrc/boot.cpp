@@ -321,23 +321,26 @@ static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x, bool do_resca
     std::set<int> need;
     for (auto& kv : lv.by_giant)
         for (int b : kv.second) need.insert(b);
-    for (int b : need) baby[b] = b == 0 ? ct_copy(c, x) : op_rotate(c, x, b * lv.unit);
+    {
+        // baby steps: rotations of one ciphertext, sharing one ModUp
+        std::vector<int> bs(need.begin(), need.end()), rs;
+        for (int b : bs) rs.push_back(b * lv.unit);
+        std::vector<Ct> rot = op_rotate_hoisted(c, x, rs);
+        for (size_t i = 0; i < bs.size(); i++) baby[bs[i]] = rot[i];
+    }
     Ct acc;
     bool have = false;
     for (auto& kv : lv.by_giant) {
         const int g = kv.first;
-        Ct inner;
-        bool hi = false;
+        // sum over the babies of baby_b * diag_(g,b), one fused launch
+        Ct inner = ct_alloc(c, x.m, 2, x.level);
+        inner.scale = x.scale * lv.pt_scale;
+        std::vector<const u64*> as, ps;
         for (int b : kv.second) {
-            Ct p = op_mul_plain(c, baby.at(b), lv.pt.at({g, b}), lv.pt_scale, false);
-            if (!hi) {
-                inner = p;
-                hi = true;
-            } else {
-                op_add_inplace(c, inner, p);
-                ct_free(c, p);
-            }
+            as.push_back(baby.at(b).d);
+            ps.push_back(lv.pt.at({g, b}));
         }
+        k_mul_plain_acc(c.T, inner.d, as.data(), ps.data(), (int)as.size(), x.m * 2, x.level + 1, c.stream);
         if (g != 0) {
             Ct r = op_rotate(c, inner, g * lv.n1 * lv.unit);
             ct_free(c, inner);

@@ -88,6 +88,12 @@ void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, vo
 void k_sub(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
 void k_neg(const DevTables& T, const Rows& out, const Rows& a, void* stream);
 void k_mul(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
+// out = sum over t < nterms of a[t] * p[t] mod q: a[t] are groups x rows
+// contiguous rows (rows = level + 1, Q primes from q_0), p[t] are rows
+// plaintext rows broadcast over the groups
+constexpr int kMaxMacTerms = 16;
+void k_mul_plain_acc(const DevTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
+                     int groups, int rows, void* stream);
 void k_mul_add(const DevTables& T, const Rows& acc, const Rows& a, const Rows& b, void* stream);
 void k_mul_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream);
 void k_add_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream);

@@ -586,6 +586,43 @@ void k_sub(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, vo
     EW_LAUNCH(sub_kernel, out, a, b);
 }
 void k_neg(const DevTables& T, const Rows& out, const Rows& a, void* stream) { EW_LAUNCH(neg_kernel, out, a); }
+// out[R] (+)= sum_t a_t[R] * p_t[R mod rows]: ciphertext rows times
+// plaintext rows (broadcast over components and batch), summed mod q.
+struct MacTerms {
+    const u64* a[kMaxMacTerms];
+    const u64* p[kMaxMacTerms];
+    int n;
+};
+
+__global__ void mul_plain_acc_kernel(DevTables T, u64* out, MacTerms L, int rows, int accumulate) {
+    const int R = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    const int r = R % rows;
+    const PrimeInfo P = T.prime[r];
+    const size_t o = (size_t)R * N + i, po = (size_t)r * N + i;
+    u64 acc = accumulate ? out[o] : 0;
+    for (int t = 0; t < L.n; t++) acc = add_mod(acc, mul_mod(L.a[t][o], L.p[t][po], P), P.q);
+    out[o] = acc;
+}
+
+void k_mul_plain_acc(const DevTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
+                     int groups, int rows, void* stream) {
+    if (groups * rows == 0 || nterms == 0) return;
+    ProfScope ps(T.prof, PK_EW, 8.0 * T.N * groups * rows * (2.0 * nterms + 1), stream);
+    for (int t0 = 0; t0 < nterms; t0 += kMaxMacTerms) {
+        MacTerms L;
+        L.n = std::min(kMaxMacTerms, nterms - t0);
+        for (int t = 0; t < L.n; t++) {
+            L.a[t] = a[t0 + t];
+            L.p[t] = p[t0 + t];
+        }
+        hipLaunchKernelGGL(mul_plain_acc_kernel, dim3((T.N + 255) / 256, groups * rows), dim3(256), 0,
+                           (hipStream_t)stream, T, out, L, rows, t0 > 0 ? 1 : 0);
+    }
+}
+
 void k_mul(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream) {
     EW_LAUNCH(mul_kernel, out, a, b);
 }

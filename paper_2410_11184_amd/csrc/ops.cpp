@@ -194,8 +194,10 @@ Ct op_square_sum(Context& c, const Ct& a) {
 // Hybrid key switching of the m polynomials d (level l, NTT domain):
 // ModUp per digit, inner product with the key, ModDown.  Writes
 // out_k[g] = (add_k[g] +) ModDown(acc_k[g]) for k = 0, 1.
-void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1, size_t out_gstride,
-                const Rows* add0, const Rows* add1) {
+// ModUp of d (NTT domain, m groups of level+1 rows): digit j of every group
+// lifted to Q_level u P by fast base conversion and returned in the NTT
+// domain, [m][beta][E][N] with E = level + 1 + n_p.
+static u64* ks_modup(Context& c, const Rows& d, int level) {
     const int m = d.ngroups;
     const int l = level;
     const int nql = l + 1;
@@ -207,7 +209,6 @@ void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0,
     Rows rdc{dc, m, nql, (size_t)nql * N, nql, 0, c.nq};
     k_copy_rows(c.T, rdc, d, c.stream);
     k_ntt(c.T, rdc, true, c.stream);
-    // ModUp: digit j -> extended rows (coefficient domain), then NTT
     u64* ext = c.alloc_words((size_t)m * beta * E * N);
     for (int j = 0; j < beta; j++) {
         const int lo = j * c.prm.digit, hi = std::min((j + 1) * c.prm.digit, nql);
@@ -220,10 +221,21 @@ void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0,
     c.free_words(dc);
     Rows rext{ext, m * beta, E, (size_t)E * N, nql, 0, c.nq};
     k_ntt(c.T, rext, false, c.stream);
+    return ext;
+}
+
+// Inner product of the lifted digits with the key, then ModDown (centred
+// conversion of the P part, times P^-1); out_k = (add_k +) result_k.
+static void ks_finish(Context& c, const u64* ext, int m, int level, const u64* key, u64* out0, u64* out1,
+                      size_t out_gstride, const Rows* add0, const Rows* add1) {
+    const int l = level;
+    const int nql = l + 1;
+    const int E = nql + c.np;
+    const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
+    const size_t N = c.N;
     // inner product with the key: acc [m][2][E][N]
     u64* acc = c.alloc_words((size_t)m * 2 * E * N);
     k_key_inner(c.T, acc, ext, key, m, beta, E, nql, c.nq + c.np, c.nq, c.np, c.stream);
-    c.free_words(ext);
     // ModDown
     Rows accp{acc + (size_t)nql * N, 2 * m, c.np, (size_t)E * N, 0, 0, c.nq};
     k_ntt(c.T, accp, true, c.stream);
@@ -246,6 +258,13 @@ void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0,
     }
     c.free_words(acc);
     c.free_words(conv);
+}
+
+void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1, size_t out_gstride,
+                const Rows* add0, const Rows* add1) {
+    u64* ext = ks_modup(c, d, level);
+    ks_finish(c, ext, d.ngroups, level, key, out0, out1, out_gstride, add0, add1);
+    c.free_words(ext);
 }
 
 Ct op_relin(Context& c, const Ct& d) {
@@ -301,6 +320,54 @@ Ct op_rotate(Context& c, const Ct& a, int r) {
 }
 
 Ct op_conjugate(Context& c, const Ct& a) { return op_apply_galois(c, a, 2 * c.N - 1); }
+
+// Rotations of one ciphertext sharing a single ModUp (hoisting): the
+// automorphism is a slot permutation in the NTT domain, the same for every
+// prime, so it commutes with the lifted digits, which are a valid lift of the
+// rotated digits.  The results decrypt like op_rotate's; their words differ
+// (another valid lift), so this is used where only the values matter.
+std::vector<Ct> op_rotate_hoisted(Context& c, const Ct& a, const std::vector<int>& rots) {
+    HS_REQUIRE(a.ncomp == 2, E_ARG, "automorphism: degree-1 input expected");
+    std::vector<Ct> out;
+    const int half = c.N / 2;
+    bool any = false;
+    for (int r : rots) any |= ((r % half) + half) % half != 0;
+    u64* ext = nullptr;
+    u64* extg = nullptr;
+    const int nql = a.level + 1;
+    const int E = nql + c.np;
+    const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
+    const size_t ew = (size_t)a.m * beta * E * c.N;
+    if (any) {
+        ext = ks_modup(c, c.comp_rows(a, 1), a.level);
+        extg = c.alloc_words(ew);
+    }
+    for (int r : rots) {
+        if (((r % half) + half) % half == 0) {
+            out.push_back(ct_copy(c, a));
+            continue;
+        }
+        const int g = galois_rot(r, c.N);
+        HS_REQUIRE(has_key(c, g), E_KEY, "Galois key missing");
+        const int* perm = c.perm(g);
+        Rows re_in{ext, a.m * beta, E, (size_t)E * c.N, E, 0, c.nq};
+        Rows re_out{extg, a.m * beta, E, (size_t)E * c.N, E, 0, c.nq};
+        k_permute(c.T, re_out, re_in, perm, c.stream);
+        Ct b0 = ct_alloc(c, a.m, 1, a.level);
+        k_permute(c.T, c.ct_rows(b0), c.comp_rows(a, 0), perm, c.stream);
+        Ct o = ct_alloc(c, a.m, 2, a.level);
+        o.scale = a.scale;
+        Rows rb0 = c.comp_rows(b0, 0);
+        ks_finish(c, extg, a.m, a.level, c.keys.at(g), o.d, o.d + o.comp_words(c.N), o.ct_words(c.N), &rb0, nullptr);
+        ct_free(c, b0);
+        out.push_back(o);
+    }
+    if (ext) {
+        c.free_words(ext);
+        c.free_words(extg);
+    }
+    return out;
+}
 
 Ct op_mod_raise(Context& c, const Ct& a, int level) {
     HS_REQUIRE(a.level == 0, E_LEVEL, "ModRaise expects a level-0 ciphertext");
