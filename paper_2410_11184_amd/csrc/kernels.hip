@@ -332,10 +332,20 @@ __global__ void __launch_bounds__(256) ntt_pass2_kernel(DevTables T, Rows x, int
 // stage s, group i is tw[2^s + i]; on 16 registers spanning local bits 3..0
 // with prefix P it is tw[((2^S0 + P) << a) + g] for local stage a, group g.
 // Rows are visited prime-major so that the twiddles of one prime stay in L2.
+// Both passes belong to one transform (k_ntt): the rows between them hold
+// values in [0, 4q) (forward) or [0, 2q) (inverse).
 
 __device__ __forceinline__ int ntt_row_prime_major(const Rows& x, int y) {
     const int g = y % x.ngroups;
     return g * x.rpg + y / x.ngroups;
+}
+
+// Lazy (Harvey) butterflies: a*w - floor(a*ws/2^64)*q lies in [0, 2q) for
+// any a < 2^64, so forward values are kept in [0, 4q) and inverse values in
+// [0, 2q) (4q < 2^63 for q < 2^61) and reduced once at the end of the
+// transform; between the two passes the rows hold these unreduced values.
+__device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
+    return a * w - __umul64hi(a, ws) * q;
 }
 
 __device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q) {
@@ -344,6 +354,7 @@ __device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 ba
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int g = 0; g < (1 << a); g++) W[(1 << a) - 1 + g] = tw[(base << a) + g];
+    const u64 q2 = 2 * q;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
         const int h = 8 >> a;
@@ -353,10 +364,11 @@ __device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 ba
 #pragma unroll
             for (int j = 0; j < h; j++) {
                 const int k = g * 2 * h + j;
-                const u64 u = E[k];
-                const u64 v = mul_shoup(E[k + h], w.x, w.y, q);
-                E[k] = add_mod(u, v, q);
-                E[k + h] = sub_mod(u, v, q);
+                u64 u = E[k];
+                u = u >= q2 ? u - q2 : u;
+                const u64 v = mul_shoup_lazy(E[k + h], w.x, w.y, q);
+                E[k] = u + v;
+                E[k + h] = u - v + q2;
             }
         }
     }
@@ -368,6 +380,7 @@ __device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 ba
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int g = 0; g < (1 << a); g++) W[(1 << a) - 1 + g] = tw[(base << a) + g];
+    const u64 q2 = 2 * q;
 #pragma unroll
     for (int a = 3; a >= 0; a--) {
         const int h = 8 >> a;
@@ -377,13 +390,19 @@ __device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 ba
 #pragma unroll
             for (int j = 0; j < h; j++) {
                 const int k = g * 2 * h + j;
-                const u64 u = E[k];
-                const u64 v = E[k + h];
-                E[k] = add_mod(u, v, q);
-                E[k + h] = mul_shoup(sub_mod(u, v, q), w.x, w.y, q);
+                const u64 u = E[k], v = E[k + h];
+                const u64 s = u + v;
+                E[k] = s >= q2 ? s - q2 : s;
+                E[k + h] = mul_shoup_lazy(u - v + q2, w.x, w.y, q);
             }
         }
     }
+}
+
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ u64 reduce4q(u64 x, u64 q) {
+    x = x >= 2 * q ? x - 2 * q : x;
+    return x >= q ? x - q : x;
 }
 
 // LDS tile layouts (u64 units), conflict-free for both access patterns:
@@ -391,10 +410,11 @@ __device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 ba
 // pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
 #define NTT16_LDS (16 * 272)
 
-__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, int inverse) {
+__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse) {
     __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row_prime_major(x, blockIdx.y);
     u64* p = row_ptr(x, row, 65536) + blockIdx.x * 16;
+    const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * 16;
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
     const int t = threadIdx.x, c = t & 15, hl = t >> 4;
@@ -403,7 +423,7 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, int 
         const ulonglong2* tw = (const ulonglong2*)T.tw2 + (size_t)pi * 65536;
         // thread (lo = hl, c): hi = 0..15, stages 0..3
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) E[hi] = p[(size_t)(hi * 16 + hl) * 256 + c];
+        for (int hi = 0; hi < 16; hi++) E[hi] = ps[(size_t)(hi * 16 + hl) * 256 + c];
         fwd16(E, tw, 1, q);
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) sm[hi * 272 + hl * 16 + c] = E[hi];
@@ -418,7 +438,7 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, int 
         const ulonglong2* tw = (const ulonglong2*)T.itw2 + (size_t)pi * 65536;
         // thread (hi = hl, c): lo = 0..15, stages 7..4
 #pragma unroll
-        for (int lo = 0; lo < 16; lo++) E[lo] = p[(size_t)(hl * 16 + lo) * 256 + c];
+        for (int lo = 0; lo < 16; lo++) E[lo] = ps[(size_t)(hl * 16 + lo) * 256 + c];
         inv16(E, tw, 16 + hl, q);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) sm[hl * 272 + lo * 16 + c] = E[lo];
@@ -433,7 +453,7 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, int 
     }
 }
 
-__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, int inverse) {
+__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse) {
     __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row_prime_major(x, blockIdx.y);
     const int pi = prime_of(x, row % x.rpg);
@@ -441,12 +461,13 @@ __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, int 
     const int t = threadIdx.x, w = t >> 4, l = t & 15;
     const u32 R = blockIdx.x * 16 + w;             // chunk index
     u64* p = row_ptr(x, row, 65536) + (size_t)R * 256;
+    const u64* ps = row_ptr(src, row, 65536) + (size_t)R * 256;
     const ulonglong2* tw = (const ulonglong2*)(inverse ? T.itw2 : T.tw2) + (size_t)pi * 65536;
     u64* s = sm + w * 272;
     u64 E[16];
     // coalesced load: thread (w, lo = l) takes hi = 0..15
 #pragma unroll
-    for (int hi = 0; hi < 16; hi++) E[hi] = p[hi * 16 + l];
+    for (int hi = 0; hi < 16; hi++) E[hi] = ps[hi * 16 + l];
     if (!inverse) {
         fwd16(E, tw, 256 + R, q);                   // stages 8..11
 #pragma unroll
@@ -460,7 +481,7 @@ __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, int 
         for (int lo = 0; lo < 16; lo++) s[l * 17 + lo] = E[lo];
         __syncthreads();
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = s[hi * 17 + l];
+        for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = reduce4q(s[hi * 17 + l], q);
     } else {
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) s[hi * 17 + l] = E[hi];
@@ -481,25 +502,29 @@ __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, int 
     }
 }
 
-void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) {
+void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) { k_ntt_from(T, x, x, inverse, stream); }
+
+void k_ntt_from(const DevTables& T, const Rows& x, const Rows& src, bool inverse, void* stream) {
     const int nrows = x.ngroups * x.rpg;
     if (nrows == 0) return;
     ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
     hipStream_t st = (hipStream_t)stream;
+    if (T.logN == 16) {
+        // the first pass reads src, the second works in place on x
+        const dim3 g(16, nrows);
+        if (!inverse) {
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, src, 0);
+            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, x, 0);
+        } else {
+            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, src, 1);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, x, 1);
+        }
+        return;
+    }
+    if (src.base != x.base || src.gstride != x.gstride) k_copy_rows(T, x, src, stream);
     if (T.N <= 4096) {
         hipLaunchKernelGGL(ntt_small_kernel, dim3(nrows), dim3(256), T.N * sizeof(u64), st, T, x,
                            inverse ? 1 : 0);
-        return;
-    }
-    if (T.logN == 16) {
-        const dim3 g(16, nrows);
-        if (!inverse) {
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, 0);
-            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, 0);
-        } else {
-            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, 1);
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, 1);
-        }
         return;
     }
     const int logC = (T.logN + 1) / 2, logR = T.logN - logC;

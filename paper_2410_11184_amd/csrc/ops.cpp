@@ -207,20 +207,23 @@ static u64* ks_modup(Context& c, const Rows& d, int level) {
     // coefficient-domain copy of d
     u64* dc = c.alloc_words((size_t)m * nql * N);
     Rows rdc{dc, m, nql, (size_t)nql * N, nql, 0, c.nq};
-    k_copy_rows(c.T, rdc, d, c.stream);
-    k_ntt(c.T, rdc, true, c.stream);
+    k_ntt_from(c.T, rdc, d, true, c.stream);
     u64* ext = c.alloc_words((size_t)m * beta * E * N);
+    const size_t xg = (size_t)beta * E * N;
     for (int j = 0; j < beta; j++) {
         const int lo = j * c.prm.digit, hi = std::min((j + 1) * c.prm.digit, nql);
+        u64* xj = ext + (size_t)j * E * N;
         const ConvDev& cv = c.modup_tables(l, j);
-        k_base_convert(c.T, cv.t, ext + (size_t)j * E * N, (size_t)beta * E * N, dc, (size_t)nql * N, m, c.stream);
-        Rows own_out{ext + (size_t)j * E * N + (size_t)lo * N, m, hi - lo, (size_t)beta * E * N, hi - lo, lo, c.nq};
+        k_base_convert(c.T, cv.t, xj, xg, dc, (size_t)nql * N, m, c.stream);
+        Rows own_out{xj + (size_t)lo * N, m, hi - lo, xg, hi - lo, lo, c.nq};
         Rows own_in{dc + (size_t)lo * N, m, hi - lo, (size_t)nql * N, hi - lo, lo, c.nq};
         k_copy_rows(c.T, own_out, own_in, c.stream);
     }
     c.free_words(dc);
-    Rows rext{ext, m * beta, E, (size_t)E * N, nql, 0, c.nq};
-    k_ntt(c.T, rext, false, c.stream);
+    // one launch for every row of every digit (the digit's own rows come
+    // back to d's values; a launch per row range would under-fill the GPU
+    // for single ciphertexts)
+    k_ntt(c.T, Rows{ext, m * beta, E, (size_t)E * N, nql, 0, c.nq}, false, c.stream);
     return ext;
 }
 
