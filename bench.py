@@ -231,6 +231,9 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "launches": d["launches"], "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
         "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+        "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] // args.steps,
+                        "algorithmic_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+                    for k, v in prof.items() if v["launches"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

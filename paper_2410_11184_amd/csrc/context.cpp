@@ -277,6 +277,9 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
             b[2 * k + 1] = itws[k];
         }
         T.tw2 = (const u64*)dev_table(a.data(), a.size() * 8);
+        std::vector<u64> r64(nt);
+        for (int t = 0; t < nt; t++) r64[t] = (u64)(((u128)1 << 64) % primes[t]);
+        T.r64 = (const u64*)dev_table(r64.data(), r64.size() * 8);
         T.itw2 = (const u64*)dev_table(b.data(), b.size() * 8);
     }
     T.logN = logN;
@@ -405,6 +408,9 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
         dmod[t] = g;
     }
     cd.t.dmod = (const u64*)put(dmod.data(), m * 8);
+    std::vector<u64> r64(m);
+    for (int t = 0; t < m; t++) r64[t] = (u64)(((u128)1 << 64) % c.primes[dst[t]]);
+    cd.t.r64 = (const u64*)put(r64.data(), m * 8);
     cd.t.k = k;
     cd.t.m = m;
     cd.t.centered = centered ? 1 : 0;

@@ -39,6 +39,7 @@ struct DevTables {
     const u64* ninv;          // [n_primes][2]   N^-1 mod q, Shoup companion
     const u64* tw2;           // [n_primes][N][2] (psi^brv(k), Shoup companion) interleaved
     const u64* itw2;          // [n_primes][N][2] (psi^-brv(k), Shoup companion) interleaved
+    const u64* r64;           // [n_primes]      2^64 mod q
     int logN;
     int N;
     Profiler* prof;           // optional launch profiler (host object)
@@ -76,6 +77,7 @@ struct ConvTables {
     const int* src_row;     // [k] row offsets (within the input group)
     const int* dst_row;     // [m] row offsets (within the output group)
     const u64* dmod;        // [m]  D mod q_t (centred conversion only)
+    const u64* r64;         // [m]  2^64 mod q_t
     int k;
     int m;
     int centered;           // 1: [x_i inv_hat_i] taken in (-d_i/2, d_i/2]

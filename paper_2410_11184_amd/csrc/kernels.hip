@@ -121,6 +121,12 @@ __device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const PrimeInfo& P) {
 // x mod q for any 64-bit x (valid since 2^64 <= 2^(2b) for b >= 32)
 __device__ __forceinline__ u64 reduce64(u64 x, const PrimeInfo& P) { return barrett128(0, x, P); }
 
+// w mod q for w < 2^128 given r64 = 2^64 mod q: (hi mod q) r64 + lo mod q
+__device__ __forceinline__ u64 reduce_wide(unsigned __int128 w, const PrimeInfo& P, u64 r64) {
+    const u64 h = reduce64((u64)(w >> 64), P);
+    return add_mod(mul_mod(h, r64, P), reduce64((u64)w, P), P.q);
+}
+
 __device__ __forceinline__ int prime_of(const Rows& x, int r) {
     return r < x.nq ? x.q_off + r : x.p_base + (r - x.nq);
 }
@@ -627,9 +633,9 @@ __global__ void mul_plain_acc_kernel(DevTables T, u64* out, MacTerms L, int rows
     const int r = R % rows;
     const PrimeInfo P = T.prime[r];
     const size_t o = (size_t)R * N + i, po = (size_t)r * N + i;
-    u64 acc = accumulate ? out[o] : 0;
-    for (int t = 0; t < L.n; t++) acc = add_mod(acc, mul_mod(L.a[t][o], L.p[t][po], P), P.q);
-    out[o] = acc;
+    unsigned __int128 w = accumulate ? out[o] : 0;
+    for (int t = 0; t < L.n; t++) w += (unsigned __int128)L.a[t][o] * L.p[t][po];
+    out[o] = reduce_wide(w, P, T.r64[r]);
 }
 
 void k_mul_plain_acc(const DevTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
@@ -754,10 +760,13 @@ __global__ void base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t 
         if (C.centered && xh[s] > (d - 1) / 2) nneg++;
     }
     for (int t = 0; t < C.m; t++) {
-        const u64 q = T.prime[C.dst_prime[t]].q;
-        u64 acc = 0;
-        for (int s = 0; s < C.k; s++)
-            acc = add_mod(acc, mul_shoup(xh[s], C.hat[s * C.m + t], C.hat_s[s * C.m + t], q), q);
+        const PrimeInfo P = T.prime[C.dst_prime[t]];
+        const u64 q = P.q;
+        // exact sum of k < 16 products below 2^122, then one reduction of its
+        // two 64-bit words: (hi mod q) 2^64 + lo
+        unsigned __int128 wide = 0;
+        for (int s = 0; s < C.k; s++) wide += (unsigned __int128)xh[s] * C.hat[s * C.m + t];
+        u64 acc = reduce_wide(wide, P, C.r64[t]);
         if (nneg) {
             const u64 dm = C.dmod[t];
             for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, q);
@@ -822,15 +831,17 @@ __global__ void key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u6
         kb[j] = key[((size_t)(2 * j) * key_rows + kr) * N + i];
         ka[j] = key[((size_t)(2 * j + 1) * key_rows + kr) * N + i];
     }
+    const u64 r64 = T.r64[kr];
     for (int g = 0; g < ncts; g++) {
-        u64 s0 = 0, s1 = 0;
+        // exact sums of beta <= 16 products below 2^122, reduced once
+        unsigned __int128 s0 = 0, s1 = 0;
         for (int j = 0; j < beta; j++) {
             const u64 x = ext[(((size_t)g * beta + j) * E + r) * N + i];
-            s0 = add_mod(s0, mul_mod(x, kb[j], P), P.q);
-            s1 = add_mod(s1, mul_mod(x, ka[j], P), P.q);
+            s0 += (unsigned __int128)x * kb[j];
+            s1 += (unsigned __int128)x * ka[j];
         }
-        acc[(((size_t)g * 2 + 0) * E + r) * N + i] = s0;
-        acc[(((size_t)g * 2 + 1) * E + r) * N + i] = s1;
+        acc[(((size_t)g * 2 + 0) * E + r) * N + i] = reduce_wide(s0, P, r64);
+        acc[(((size_t)g * 2 + 1) * E + r) * N + i] = reduce_wide(s1, P, r64);
     }
 }
 
