@@ -24,34 +24,43 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+# 32-bit integer multiplier peak: 256 CUs x 64 lanes per cycle x 2.4 GHz for
+# full-rate VALU work, v_mad_u64_u32 at half rate -> 19.66 x 10^12 per second
+PEAK_MUL32_T = 256 * 64 * 2.4e9 / 2 / 1e12
+# a butterfly's 64-bit Shoup product w*b mod q: the high half of b*w' (four
+# 32x32 partial products) and the low halves of b*w and h*q (three each)
+MUL32_PER_BUTTERFLY = 10
 
 
 def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def _kernel_hash():
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2410_11184_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+def _kernel_hash(kind="ntt"):
+    """sha256 (16 hex) of the source of the kernel kind the counters describe:
+    the N = 2^16 NTT section of kernels.hip."""
+    src = open(os.path.join(ROOT, "paper_2410_11184_amd", "csrc", "kernels.hip")).read()
+    a = src.index("// ---- N = 2^16")
+    b = src.index("// ----------------------------------------------------------- elementwise")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def _traffic(kind):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None when absent or stale."""
+def _traffic(kind, algorithmic_bytes_per_launch):
+    """HBM bytes per launch of the dominant kernel: the committed counter
+    summary's ratio of measured to algorithmic bytes times this run's
+    algorithmic bytes per launch; None when absent or stale."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_fgb16.txt" % kind)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line:
+        if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256") != _kernel_hash():
+    if vals.get("kernel_source_sha256") != _kernel_hash(kind):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_algorithmic_byte"]) * algorithmic_bytes_per_launch
     except (KeyError, ValueError):
         return None
 
@@ -168,8 +177,22 @@ def main():
     launches = max(d["launches"], 1)
     avg_ms = d["ms"] / launches
     bytes_per_launch = d["bytes"] / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic(dom)
+    hbm_achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic(dom, bytes_per_launch)
+    mul_rate = ctx.mul_rate()
+    if dom == "ntt":
+        # the NTT is bound by the integer multipliers: N/2 log N butterflies per row
+        rows = bytes_per_launch / (16.0 * p["N"])
+        work = rows * (p["N"] // 2) * p["logN"] * MUL32_PER_BUTTERFLY
+        achieved = work / (avg_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_MUL32_T, "unit": "Tmul32/s",
+                    "frac": achieved / PEAK_MUL32_T, "traffic": traffic,
+                    "measured_mul32_peak": mul_rate, "mul32_per_launch": work}
+    else:
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": hbm_achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": hbm_achieved / PEAK_HBM_GBS, "traffic": traffic}
+    roofline.update({"launches": d["launches"], "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "hbm_algorithmic_GBps": hbm_achieved, "hbm_frac": hbm_achieved / PEAK_HBM_GBS})
 
     plain = None
     if not args.no_plain:
@@ -227,9 +250,7 @@ def main():
         "precision_bits": bits,
         "plain": plain,
         "speedup_vs_plain": (value / plain["calls_per_s"]) if plain else None,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "launches": d["launches"], "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline": roofline,
         "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] // args.steps,
                         "algorithmic_GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}

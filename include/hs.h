@@ -233,15 +233,22 @@ hs_status hs_prof_collect(hs_ctx* ctx, double* out, size_t n);
 
 /* Intermediate ciphertexts of hs_bootstrap, for tests: stage 1 = after
  * ModRaise (declared scale 2 q0 (K+1) N/2), 2 = after CoeffToSlot, 3 = real
- * part after the conjugation split, 4 = real part after the cosine
- * polynomial, 5 / 6 = real / imaginary part after the double-angle steps,
- * 7 = recombined input of SlotToCoeff, 8 / 9 = after its first / second
- * level. */
+ * part u after the conjugation split, 4 = real-part half of
+ * z = exp(2 pi i (K+1) u / 2^r) after the two Chebyshev polynomials,
+ * 5 / 6 = real / imaginary half of z after the r squarings, 7 = input of
+ * SlotToCoeff (2 (8 sin x - sin 2x) per coefficient, recombined), 8 / 9 =
+ * after its first / second level. */
 hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct** out);
 
 /* Raw negacyclic NTT (forward or inverse) of `nrows` rows of N residues
  * modulo prime index `prime` (host buffer, in place); for parity tests. */
 hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse);
+
+/* Measured throughput of v_mad_u64_u32 (32 x 32 + 64 -> 64 bit), the
+ * instruction the 64-bit modular products are built from, in 10^12 lane
+ * operations per second (eight independent chains per lane, about 1 ms on
+ * the context's device and stream).  HS_E_DEVICE if the probe fails. */
+hs_status hs_dbg_mul_rate(hs_ctx* ctx, double* tops);
 
 #ifdef __cplusplus
 }

@@ -463,6 +463,15 @@ hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out) {
     });
 }
 
+hs_status hs_dbg_mul_rate(hs_ctx* ctx, double* tops) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(tops);
+        *tops = hs::k_mul_rate(ctx->c->stream);
+        HS_REQUIRE(*tops > 0, hs::E_DEVICE, "multiplier probe failed");
+    });
+}
+
 hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse) {
     return guard([&] {
         NEED(ctx);

@@ -86,6 +86,8 @@ struct ConvTables {
 // ------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` (a hipStream_t).
 void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream);
+// measured v_mad_u64_u32 rate of the device (10^12 lane operations / s)
+double k_mul_rate(void* stream);
 // x = NTT(src) (or its inverse); src has x's shape and may be x itself
 void k_ntt_from(const DevTables& T, const Rows& x, const Rows& src, bool inverse, void* stream);
 void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);

@@ -973,4 +973,45 @@ void k_encode_real(const DevTables& T, const Rows& out, const double* w, size_t 
     EW_LAUNCH(encode_real_kernel, out, w, w_gstride, scale);
 }
 
+// ------------------------------------------------ multiplier throughput probe
+// Eight independent chains of v_mad_u64_u32 (32 x 32 + 64 -> 64) per lane:
+// the rate of the instruction every 64-bit modular product here is built from.
+__global__ void __launch_bounds__(256) mul_rate_kernel(u64* out, u64 seed, int iters) {
+    u64 a[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) a[c] = seed + threadIdx.x * 17 + c * 131;
+    const u32 b = (u32)(seed >> 3) | 1;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+#pragma unroll
+            for (int c = 0; c < 8; c++) a[c] = (u64)(u32)a[c] * b + a[c];
+    }
+    u64 r = 0;
+#pragma unroll
+    for (int c = 0; c < 8; c++) r ^= a[c];
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+double k_mul_rate(void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int blocks = 256 * 16, iters = 512;
+    u64* d = nullptr;
+    if (hipMalloc((void**)&d, sizeof(u64) * blocks * 256) != hipSuccess) return 0.0;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    hipLaunchKernelGGL(mul_rate_kernel, dim3(blocks), dim3(256), 0, st, d, 12345ull, iters);
+    (void)hipEventRecord(e0, st);
+    hipLaunchKernelGGL(mul_rate_kernel, dim3(blocks), dim3(256), 0, st, d, 12345ull, iters);
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d);
+    return 64.0 * iters * (double)blocks * 256 / (ms * 1e-3) / 1e12;
+}
+
 }  // namespace hs

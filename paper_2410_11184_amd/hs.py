@@ -103,6 +103,7 @@ def lib():
         "hs_mod_raise": [_vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_mul_monomial": [_vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_dbg_ntt": [_vp, S, _u64p, ctypes.c_size_t, S],
+        "hs_dbg_mul_rate": [_vp, ctypes.POINTER(ctypes.c_double)],
     }
     optional = {
         "hs_bootstrap": [_vp, _vp, ctypes.POINTER(_vp)],
@@ -368,6 +369,12 @@ class Context:
         buf = (ctypes.c_double * 4)()
         _check(lib().hs_softmax_stats(self.h, buf, 4))
         return dict(k=int(buf[0]), bootstraps=int(buf[1]), levels_left=int(buf[2]), ms=float(buf[3]))
+
+    def mul_rate(self):
+        """Measured v_mad_u64_u32 throughput of the device (10^12 ops/s)."""
+        t = ctypes.c_double()
+        _check(lib().hs_dbg_mul_rate(self.h, ctypes.byref(t)))
+        return t.value
 
     def ntt(self, rows, prime, inverse=False):
         x = np.ascontiguousarray(rows, dtype=np.uint64).copy()
