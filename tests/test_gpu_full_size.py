@@ -88,6 +88,23 @@ def boot_ctx():
     return c
 
 
+@pytest.mark.parametrize("level,scale_bits,amp", [(0, 40, 1.0), (3, 40, 1.0), (5, 42, 1.0 / 64)])
+def test_bootstrap_precision(boot_ctx, level, scale_bits, amp):
+    """dec(BTS(ct)) against dec(ct): absolute error <= 2^-22 for values bounded
+    by 1 (hs_bootstrap's bound; the paper's library reaches about 22 bits,
+    Section 5.1), output at the top user level and at the input's scale."""
+    c = boot_ctx
+    z = np.random.default_rng(level).uniform(-1, 1, c.slots) * amp
+    ct = c.encrypt(z, level, 2.0 ** scale_bits, 21)
+    before = c.decrypt(ct)
+    out = c.bootstrap(ct)
+    err = np.max(np.abs(c.decrypt(out) - before))
+    print("bootstrap level", level, "bits", -np.log2(err))
+    assert -np.log2(err) >= 22.0
+    assert out.level == 12
+    assert abs(np.log2(out.scale) - scale_bits) < 1e-6
+
+
 @pytest.mark.parametrize("workload,variant", [("fgb16_smb64", "B"), ("fgb16_sm", "SM")])
 def test_softmax_workload_precision(boot_ctx, workload, variant):
     from oracle import softmax as S
