@@ -105,6 +105,76 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": reps}), flush=True)
 
 
+def run_uneven(args):
+    """The uneven batch (32 layer jobs of 4096 Softmax of dim 128 in lockstep,
+    then one Softmax of dim 32768): one JSON line with total calls/s and the
+    precision of each group (dimension 32768 reported, not gated)."""
+    import torch
+    import synthetic
+    from paper_2410_11184_amd import hs
+    from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
+    from oracle import softmax as S
+    w = synthetic.WORKLOADS[args.workload]
+    p = synthetic.preset(w["preset"])
+    ctx = hs.Context(p, device=0, stream=hs.current_stream())
+    ctx.keygen(2003)
+    groups = []
+    for gi, g in enumerate(w["groups"]):
+        xs = [synthetic.group_logits(args.workload, gi, j) for j in range(g["jobs"])]
+        cts = []
+        for j, x in enumerate(xs):
+            cts += encrypt_logits(ctx, x, g["M"], seed=4000 + 100 * gi + j)
+        groups.append((g, xs, cts))
+    ctx.sync()
+    _log("encrypted %s ciphertexts" % [len(c) for _, _, c in groups])
+
+    def job():
+        outs, stats = [], []
+        for g, _, cts in groups:
+            outs.append(ctx.softmax(cts, g["n"], g["M"], variant=g["variant"], jobs=g["jobs"]))
+            stats.append(ctx.softmax_stats())
+        return outs, stats
+
+    for i in range(args.warmup):
+        job()
+        _log("warmup %d done" % i)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.prof_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        outs, stats = job()
+        _log("step %d done" % i)
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.prof_enable(False)
+    prof = ctx.prof_collect()
+    calls = sum(g["jobs"] * g["L"] for g, _, _ in groups)
+    prec = []
+    for (g, xs, _), out, st in zip(groups, outs, stats):
+        per = len(out) // g["jobs"]
+        worst = []
+        for j, x in enumerate(xs):
+            y = decrypt_outputs(ctx, out[j * per:(j + 1) * per], g["n"])
+            worst.append(S.precision_bits(S.softmax(x), y)["worst"])
+        prec.append({"n": g["n"], "jobs": g["jobs"], "m": g["m"], "variant": "SM-B" if g["variant"] else "SM",
+                     "worst_bits": min(worst),
+                     "bootstraps": st["bootstraps"], "ms": st["ms"]})
+    gated = all(q["worst_bits"] >= 16.0 for q in prec if q["n"] <= 256)
+    value = calls * args.steps / elapsed
+    rec = {"metric": "encrypted Softmax calls/s, uneven batch (32 layer jobs of dim 128 + one of dim 32768)",
+           "value": value if gated else 0.0, "unit": "Softmax calls/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "N=2^16 RNS-CKKS; 32 jobs x 16 ciphertexts x 4096 Softmax of dim 128 "
+                                  "(N(0,4^2) clipped to [-64,0]) in lockstep + 1 Softmax of dim 32768 (U[-256,0])",
+                      "global_batch": calls, "parallelism": "single-gpu"},
+           "groups": prec,
+           "kernel_time_ms": {k: round(v["ms"] / args.steps, 1) for k, v in prof.items() if v["launches"]}}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +194,9 @@ def main():
               "multi-GPU sharding is design-only (see the repository documentation).", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "fgb16_uneven":
+        run_uneven(args)
+        return
     import torch
     import synthetic
     from paper_2410_11184_amd import hs

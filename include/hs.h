@@ -202,8 +202,21 @@ typedef struct hs_softmax_opts {
  * on first use. */
 hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double M, const hs_softmax_opts* opts,
                      hs_ct** out);
-/* Statistics of the last hs_softmax call: [k, bootstraps, levels_left,
- * milliseconds]; writes min(n, 4) values. */
+/* Several independent Softmax jobs of one shape in lockstep (batched
+ * many-Softmax, Section 4.2, applied to njobs jobs at once): in[0..m) holds
+ * njobs consecutive jobs of m / njobs ciphertexts each, every job packed as
+ * hs_pack_softmax packs it, all with the same n, M, level and scale.  Every
+ * launch of the main thread covers all m ciphertexts; the njobs auxiliary
+ * ciphertexts (Algorithm "alg:AuxThread") form one batch, so each of their
+ * key switches and bootstraps reads its keys once for all jobs.  Every
+ * operation acts per ciphertext, so job j's outputs are bit for bit those of
+ * hs_softmax on job j alone.  Writes m new handles, job by job.  Errors as
+ * hs_softmax; HS_E_ARG when njobs does not divide m. */
+hs_status hs_softmax_jobs(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
+                          const hs_softmax_opts* opts, hs_ct** out);
+/* Statistics of the last hs_softmax(_jobs) call: [k, bootstraps (auxiliary
+ * and main ciphertexts refreshed), levels_left, milliseconds]; writes
+ * min(n, 4) values. */
 hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n);
 
 /* Packing of Section 4 (host only).  logits: [L][n] row-major, L n =

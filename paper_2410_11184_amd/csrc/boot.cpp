@@ -155,10 +155,6 @@ struct BootCtx {
     bool keys_done = false;
 };
 
-static std::map<const Context*, BootCtx*>& boot_registry() {
-    static std::map<const Context*, BootCtx*> r;
-    return r;
-}
 
 bool can_bootstrap(const Context& c) { return c.prm.boot.cts_levels > 0; }
 
@@ -202,9 +198,7 @@ static void encode_level(Context& c, LinLevel& lv, const Mat& M, double constant
             w[k + n] = im[k];
         }
         c.upload(dw, w.data(), sizeof(double) * c.N);
-        u64* pt = nullptr;
-        if (hipMalloc((void**)&pt, sizeof(u64) * rows * c.N) != hipSuccess) throw Error(E_OOM, "bootstrap plaintexts");
-        c.owned.push_back(pt);
+        u64* pt = (u64*)c.persistent_alloc(sizeof(u64) * rows * c.N, "bootstrap plaintexts");
         Rows r = c.rows(pt, 1, rows, (size_t)rows * c.N);
         k_encode_real(c.T, r, dw, 0, lv.pt_scale, c.stream);
         k_ntt(c.T, r, false, c.stream);
@@ -214,10 +208,10 @@ static void encode_level(Context& c, LinLevel& lv, const Mat& M, double constant
     c.pool.free(dw);
 }
 
+// per-context tables (no global state: contexts on different host threads
+// bootstrap independently)
 static BootCtx& boot_ctx(Context& c) {
-    auto& reg = boot_registry();
-    auto it = reg.find(&c);
-    if (it != reg.end()) return *it->second;
+    if (c.boot) return *(BootCtx*)c.boot;
     HS_REQUIRE(can_bootstrap(c), E_PARAM, "no bootstrapping parameters");
     const BootParams& bp = c.prm.boot;
     HS_REQUIRE(c.prm.user_top + bp.cts_levels + bp.evalmod_levels + bp.stc_levels == c.L, E_PARAM,
@@ -300,7 +294,7 @@ static BootCtx& boot_ctx(Context& c) {
         B->psin = cheb_fit([&](long double u) { return sinl(w * u); }, -1.0, 1.0, bp.cos_degree);
         for (size_t j = 0; j < B->pcos.c.size(); j++) (j % 2 ? B->pcos.c[j] : B->psin.c[j]) = 0.0;
     }
-    reg[&c] = B;
+    c.boot = B;
     return *B;
 }
 
@@ -575,13 +569,9 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop, int mask_L) 
     return y;
 }
 
-void boot_release(const Context* c) {
-    auto& reg = boot_registry();
-    auto it = reg.find(c);
-    if (it != reg.end()) {
-        delete it->second;
-        reg.erase(it);
-    }
+void boot_release(Context* c) {
+    delete (BootCtx*)c->boot;
+    c->boot = nullptr;
 }
 
 }  // namespace hs

@@ -492,8 +492,8 @@ hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int i
     });
 }
 
-hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double M, const hs_softmax_opts* opts,
-                     hs_ct** out) {
+static hs_status softmax_impl(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
+                              const hs_softmax_opts* opts, hs_ct** out) {
     if (out)
         for (size_t i = 0; i < m; i++) out[i] = nullptr;
     return guard([&] {
@@ -501,6 +501,7 @@ hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double
         NEED(in);
         NEED(out);
         HS_REQUIRE(m >= 1, hs::E_ARG, "m must be >= 1");
+        HS_REQUIRE(njobs >= 1 && m % njobs == 0, hs::E_ARG, "the ciphertext count must be a multiple of the job count");
         hs::Context& c = *ctx->c;
         std::vector<const hs::Ct*> parts;
         for (size_t i = 0; i < m; i++) {
@@ -523,7 +524,7 @@ hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double
         hs::SoftmaxStats st;
         hs::Ct y;
         try {
-            y = hs::softmax(c, batch, (int)n, M, o, &st);
+            y = hs::softmax(c, batch, (int)n, M, o, &st, (int)njobs);
         } catch (...) {
             hs::ct_free(c, batch);
             throw;
@@ -538,6 +539,16 @@ hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double
         ctx->last_stats[2] = st.levels_left;
         ctx->last_stats[3] = std::chrono::duration<double, std::milli>(t1 - t0).count();
     });
+}
+
+hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double M, const hs_softmax_opts* opts,
+                     hs_ct** out) {
+    return softmax_impl(ctx, in, m, 1, n, M, opts, out);
+}
+
+hs_status hs_softmax_jobs(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
+                          const hs_softmax_opts* opts, hs_ct** out) {
+    return softmax_impl(ctx, in, m, njobs, n, M, opts, out);
 }
 
 hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n) {

@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "host.h"
@@ -122,43 +124,118 @@ static u64 brv(u64 x, int bits) {
 }
 
 // ----------------------------------------------------------------- pool
-void* Pool::alloc(size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    auto it = free_.find(bytes);
-    void* p = nullptr;
-    if (it != free_.end()) {
-        p = it->second;
-        free_.erase(it);
-    } else {
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            // drop the cache and retry once
-            for (auto& kv : free_) hipFree(kv.second);
-            free_.clear();
-            e = hipMalloc(&p, bytes);
-            if (e != hipSuccess) throw Error(E_OOM, "device allocation failed");
+static constexpr size_t kChunk = (size_t)8 << 30;
+
+void Pool::add_free(int c, size_t off, size_t size) {
+    chunks_[c].free_[off] = size;
+    by_size_.emplace(size, std::make_pair(c, off));
+}
+
+void Pool::remove_free(int c, size_t off, size_t size) {
+    chunks_[c].free_.erase(off);
+    auto range = by_size_.equal_range(size);
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second.first == c && it->second.second == off) {
+            by_size_.erase(it);
+            return;
         }
+}
+
+void* Pool::alloc(size_t bytes) {
+    bytes = ((bytes ? bytes : 1) + 255) & ~(size_t)255;
+    auto it = by_size_.lower_bound(bytes);
+    if (it == by_size_.end()) {
+        // new chunk: 8 GiB, or the request rounded up to 1 GiB
+        size_t want = std::max(kChunk, (bytes + ((size_t)1 << 30) - 1) & ~(((size_t)1 << 30) - 1));
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim(want);
+            e = hipMalloc(&p, want);
+        }
+        if (e != hipSuccess && want > bytes) {
+            (void)hipGetLastError();
+            want = bytes;   // as much as the request alone
+            e = hipMalloc(&p, want);
+        }
+        if (e != hipSuccess) throw Error(E_OOM, "device allocation failed");
+        if (std::getenv("HS_TRACE"))
+            std::fprintf(stderr, "[hs] pool: new chunk of %.2f GB (%.2f GB reserved, %.2f GB in use)\n", want / 1e9,
+                         (reserved_ + want) / 1e9, in_use_ / 1e9);
+        Chunk ch;
+        ch.base = (char*)p;
+        ch.size = want;
+        chunks_.push_back(ch);
+        reserved_ += want;
+        add_free((int)chunks_.size() - 1, 0, want);
+        it = by_size_.lower_bound(bytes);
     }
-    size_[p] = bytes;
+    const int c = it->second.first;
+    const size_t off = it->second.second, size = it->first;
+    remove_free(c, off, size);
+    if (size > bytes) add_free(c, off + bytes, size - bytes);
+    void* p = chunks_[c].base + off;
+    live_[p] = std::make_pair(c, bytes);
     in_use_ += bytes;
     return p;
 }
 
 void Pool::free(void* p) {
     if (!p) return;
-    auto it = size_.find(p);
-    if (it == size_.end()) return;
-    in_use_ -= it->second;
-    free_.emplace(it->second, p);
-    size_.erase(it);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    const int c = it->second.first;
+    size_t size = it->second.second;
+    size_t off = (size_t)((char*)p - chunks_[c].base);
+    live_.erase(it);
+    in_use_ -= size;
+    auto& fm = chunks_[c].free_;
+    // coalesce with the following and the preceding free blocks
+    auto nx = fm.find(off + size);
+    if (nx != fm.end()) {
+        const size_t ns = nx->second;
+        remove_free(c, off + size, ns);
+        size += ns;
+    }
+    auto pv = fm.lower_bound(off);
+    if (pv != fm.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+            const size_t po = pv->first, ps = pv->second;
+            remove_free(c, po, ps);
+            off = po;
+            size += ps;
+        }
+    }
+    add_free(c, off, size);
+}
+
+size_t Pool::trim(size_t bytes) {
+    // only chunks with no live block can go back to the device
+    size_t released = 0;
+    for (int c = (int)chunks_.size() - 1; c >= 0 && released < bytes; c--) {
+        Chunk& ch = chunks_[c];
+        if (!ch.base) continue;
+        auto f = ch.free_.find(0);
+        if (f == ch.free_.end() || f->second != ch.size) continue;
+        remove_free(c, 0, ch.size);
+        hipFree(ch.base);
+        released += ch.size;
+        reserved_ -= ch.size;
+        ch.base = nullptr;
+        ch.size = 0;
+    }
+    return released;
 }
 
 void Pool::release_all() {
-    for (auto& kv : free_) hipFree(kv.second);
-    free_.clear();
-    for (auto& kv : size_) hipFree(kv.first);
-    size_.clear();
-    in_use_ = 0;
+    for (auto& ch : chunks_)
+        if (ch.base) hipFree(ch.base);
+    chunks_.clear();
+    by_size_.clear();
+    live_.clear();
+    in_use_ = reserved_ = 0;
 }
 
 Pool::~Pool() { release_all(); }
@@ -176,10 +253,28 @@ void Context::download(void* dst, const void* src, size_t bytes) {
     sync();
 }
 
-void* Context::dev_table(const void* host, size_t bytes) {
-    void* p = nullptr;
-    check_hip(hipMalloc(&p, bytes ? bytes : 8), "table allocation");
+void* Context::persistent_alloc(size_t bytes, const char* what) {
+    void* p = raw_alloc(bytes, what);
     owned.push_back(p);
+    return p;
+}
+
+void* Context::raw_alloc(size_t bytes, const char* what) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        // the pool's cached blocks may hold the memory
+        (void)hipGetLastError();
+        pool.trim(bytes);
+        e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) throw Error(E_OOM, std::string("device allocation failed: ") + what);
+    return p;
+}
+
+void* Context::dev_table(const void* host, size_t bytes) {
+    void* p = persistent_alloc(bytes, "table");
     if (bytes) upload(p, host, bytes);
     return p;
 }
@@ -386,8 +481,7 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
     }
     ConvDev cd;
     auto put = [&](const void* h, size_t bytes) {
-        void* p = nullptr;
-        check_hip(hipMalloc(&p, bytes ? bytes : 8), "conv table");
+        void* p = c.raw_alloc(bytes, "conversion table");
         if (bytes) c.upload(p, h, bytes);
         cd.bufs.push_back(p);
         return p;
@@ -474,8 +568,7 @@ const int* Context::perm(int g) {
         const u64 e = ((2 * brv((u64)i, logN) + 1) * (u64)g) % M;
         p[i] = (int)brv((e - 1) / 2, logN);
     }
-    int* d = nullptr;
-    check_hip(hipMalloc(&d, sizeof(int) * N), "perm");
+    int* d = (int*)raw_alloc(sizeof(int) * N, "permutation");
     upload(d, p.data(), sizeof(int) * N);
     perms[g] = d;
     return d;

@@ -63,18 +63,34 @@ struct Params {
 };
 
 // --------------------------------------------------------------- memory
+// Device memory arena: chunks obtained from hipMalloc (8 GiB, or the request
+// rounded to 1 GiB when larger) and sub-allocated best-fit in 256-byte units,
+// with neighbouring free blocks coalesced.  Chunks are kept until the context
+// ends, so steady-state work allocates without hipMalloc / hipFree (which
+// synchronise the device).  Every use is on the context's one stream, so a
+// freed block may be reused at once.
 class Pool {
 public:
     void* alloc(size_t bytes);
     void free(void* p);
     void release_all();
+    size_t trim(size_t bytes);   // release wholly free chunks until >= bytes freed
     size_t bytes_in_use() const { return in_use_; }
+    size_t bytes_reserved() const { return reserved_; }
     ~Pool();
 
 private:
-    std::multimap<size_t, void*> free_;
-    std::map<void*, size_t> size_;
-    size_t in_use_ = 0;
+    struct Chunk {
+        char* base = nullptr;
+        size_t size = 0;
+        std::map<size_t, size_t> free_;   // offset -> size
+    };
+    std::vector<Chunk> chunks_;
+    std::multimap<size_t, std::pair<int, size_t>> by_size_;   // size -> (chunk, offset)
+    std::map<void*, std::pair<int, size_t>> live_;            // pointer -> (chunk, size)
+    size_t in_use_ = 0, reserved_ = 0;
+    void add_free(int c, size_t off, size_t size);
+    void remove_free(int c, size_t off, size_t size);
 };
 
 struct DevBuf {
@@ -136,6 +152,7 @@ struct Context {
     std::map<int, ConvDev> moddown;                 // level
     std::map<int, int*> perms;                      // galois element -> device perm
     std::map<int, u64*> monomials;                  // k -> NTT of X^k over all Q primes
+    void* boot = nullptr;                           // bootstrapping tables (boot.cpp), built on first use
     std::map<int, double*> mask_coeffs;             // L -> coefficients of the slot mask [0, L)
     std::vector<void*> owned;                       // device tables
     std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
@@ -166,6 +183,8 @@ struct Context {
     void upload(void* dst, const void* src, size_t bytes);
     void download(void* dst, const void* src, size_t bytes);
     void* dev_table(const void* host, size_t bytes);   // permanent device copy
+    void* persistent_alloc(size_t bytes, const char* what);  // device memory owned until the context ends
+    void* raw_alloc(size_t bytes, const char* what);          // hipMalloc, trimming the pool's cache if needed
 
     const ConvDev& modup_tables(int level, int j);
     const ConvDev& moddown_tables(int level);
@@ -179,7 +198,7 @@ u64 powmod_h(u64 a, u64 e, u64 q);
 u64 invmod_h(u64 a, u64 q);
 u64 shoup_h(u64 w, u64 q);
 int galois_rot(int r, int N);
-void boot_release(const Context* c);
+void boot_release(Context* c);
 
 // --------------------------------------------------------- ciphertexts
 Ct ct_alloc(Context& c, int m, int ncomp, int level);
@@ -213,7 +232,8 @@ void op_add_const_inplace(Context& c, Ct& a, double v);       // adds rint(v * s
 Ct op_mul_const(Context& c, const Ct& a, double v, double target_scale); // const mult + rescale
 Ct op_mul_plain(Context& c, const Ct& a, const u64* pt, double pt_scale, bool rescale);
 Ct op_tensor(Context& c, const Ct& a, const Ct& b);
-Ct op_square_sum(Context& c, const Ct& a);                   // sum_g a_g (x) a_g
+Ct op_square_sum(Context& c, const Ct& a);                 // sum_g a_g (x) a_g
+Ct op_square_sum_jobs(Context& c, const Ct& a, int jobs);  // one such sum per group of a.m / jobs ciphertexts
 Ct op_relin(Context& c, const Ct& d);
 Ct op_rescale(Context& c, const Ct& a);
 Ct op_mult(Context& c, const Ct& a, const Ct& b);            // tensor, relin, rescale

@@ -191,6 +191,21 @@ Ct op_square_sum(Context& c, const Ct& a) {
     return d;
 }
 
+// J sums: output j = sum over ciphertexts [j m, (j + 1) m) of a of their
+// squares (degree 2), m = a.m / J
+Ct op_square_sum_jobs(Context& c, const Ct& a, int jobs) {
+    HS_REQUIRE(a.ncomp == 2, E_ARG, "square_sum: degree-1 inputs expected");
+    HS_REQUIRE(jobs >= 1 && a.m % jobs == 0, E_ARG, "square_sum: batch not divisible into jobs");
+    const int m = a.m / jobs;
+    Ct d = ct_alloc(c, jobs, 3, a.level);
+    d.scale = a.scale * a.scale;
+    for (int j = 0; j < jobs; j++) {
+        Rows ra{a.d + (size_t)j * m * a.ct_words(c.N), m, a.level + 1, a.ct_words(c.N), a.level + 1, 0, c.nq};
+        k_square_sum(c.T, d.d + (size_t)j * d.ct_words(c.N), d.comp_words(c.N), ra, a.comp_words(c.N), c.stream);
+    }
+    return d;
+}
+
 // Hybrid key switching of the m polynomials d (level l, NTT domain):
 // ModUp per digit, inner product with the key, ModDown.  Writes
 // out_k[g] = (add_k[g] +) ModDown(acc_k[g]) for k = 0, 1.
@@ -405,10 +420,7 @@ Ct op_mul_monomial(Context& c, const Ct& a, int k) {
             if (k < c.N) h[(size_t)i * c.N + k] = 1;
             else h[(size_t)i * c.N + (k - c.N)] = c.primes[i] - 1;
         }
-        void* p = nullptr;
-        hipMalloc(&p, w * 8);
-        c.owned.push_back(p);
-        mono = (u64*)p;
+        mono = (u64*)c.persistent_alloc(w * 8, "monomial");
         c.upload(mono, h.data(), w * 8);
         k_ntt(c.T, c.rows(mono, 1, c.L + 1, w), false, c.stream);
         cache[key] = mono;

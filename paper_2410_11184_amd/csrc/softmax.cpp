@@ -124,10 +124,27 @@ static void broadcast(Context& c, Ct& a, int L, int nrot) {
     }
 }
 
-Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats) {
+// a (one ciphertext per job) repeated m times per job, to pair with the main
+// batch; a itself when there is one job (the products broadcast it)
+static Ct per_job(Context& c, const Ct& a, int jobs, int m) {
+    if (jobs == 1) return ct_copy(c, a);
+    Ct o = ct_alloc(c, jobs * m, a.ncomp, a.level);
+    o.scale = a.scale;
+    const size_t w = a.ct_words(c.N);
+    for (int j = 0; j < jobs; j++) {
+        Rows dst{o.d + (size_t)j * m * w, m, a.ncomp * (a.level + 1), w, a.level + 1, 0, c.nq};
+        Rows src{a.d + (size_t)j * w, m, a.ncomp * (a.level + 1), 0, a.level + 1, 0, c.nq};
+        k_copy_rows(c.T, dst, src, c.stream);
+    }
+    return o;
+}
+
+Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats, int jobs) {
     SoftmaxStats st;
     const int N0 = c.N / 2;
-    const int m = x.m;
+    HS_REQUIRE(jobs >= 1 && x.m % jobs == 0, E_ARG, "Softmax: batch not divisible into jobs");
+    const int J = jobs;
+    const int m = x.m / J;
     HS_REQUIRE(n >= 2 && (n & (n - 1)) == 0, E_PARAM, "Softmax dimension must be a power of two >= 2");
     HS_REQUIRE(n <= N0 && m >= 1 && n % m == 0, E_ARG, "need m | n <= N/2");
     HS_REQUIRE(M > 0, E_ARG, "range M must be positive");
@@ -196,7 +213,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             }
         }
         // auxiliary thread, squaring: S = sum over the m ciphertexts of y^2 (one relinearisation)
-        Ct d = op_square_sum(c, y);
+        Ct d = op_square_sum_jobs(c, y, J);
         Ct r = op_relin(c, d);
         ct_free(c, d);
         Ct S = op_rescale(c, r);
@@ -234,8 +251,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
                 }
             }
             broadcast(c, lam, L, nrot);
-            Ct z = op_mult(c, y, lam);
+            Ct lj = per_job(c, lam, J, m);
             ct_free(c, lam);
+            Ct z = op_mult(c, y, lj);
+            ct_free(c, lj);
             ct_free(c, y);
             y = op_mult(c, z, z);
             ct_free(c, z);
@@ -269,8 +288,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             }
             Ct bb = ct_copy(c, big);
             broadcast(c, bb, L, nrot);
-            Ct z = op_mult(c, y0, bb);
+            Ct bj = per_job(c, bb, J, m);
             ct_free(c, bb);
+            Ct z = op_mult(c, y0, bj);
+            ct_free(c, bj);
             ct_free(c, y);
             y = z;
             for (int s = 0; s < j; s++) {

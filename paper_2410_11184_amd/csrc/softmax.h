@@ -26,7 +26,12 @@ struct SoftmaxStats {
 int theorem_k(int n, double M);
 // Softmax of the L = m N0 / n vectors packed in the batch x (Section 4.2
 // layout); inputs in [-M, 0].  Returns the batch of outputs.
-Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats);
+// jobs > 1: x holds `jobs` independent batches of x.m / jobs ciphertexts each
+// (same n, M), run in lockstep: the main-thread operations cover every
+// ciphertext in each launch and the jobs' auxiliary ciphertexts form one batch
+// (one key read per operation, one batched bootstrap).  Every operation acts
+// per ciphertext, so each job's result equals its result alone.
+Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats, int jobs = 1);
 
 bool can_bootstrap(const Context& c);
 // Refresh x (any level) to the top user level; `bound` bounds |slot values|.

@@ -112,6 +112,8 @@ def lib():
         "hs_prof_collect": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
         "hs_softmax": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_uint32, ctypes.c_double,
                        ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
+        "hs_softmax_jobs": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_uint32,
+                            ctypes.c_double, ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_stats": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
         "hs_pack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double, _vp,
                             ctypes.POINTER(ctypes.c_size_t)],
@@ -354,15 +356,19 @@ class Context:
     def bootstrap_stage(self, a, stage):
         return self._op("hs_dbg_bootstrap_stage", a.h, stage)
 
-    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), debug_stop=-1):
-        """hs_softmax over the packed ciphertexts `cts`; returns new handles."""
+    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), debug_stop=-1, jobs=1):
+        """hs_softmax (jobs = 1) or hs_softmax_jobs over the packed ciphertexts
+        `cts` (jobs consecutive groups of len(cts) / jobs); returns new handles."""
         m = len(cts)
         arr = (_vp * m)(*[c.h for c in cts])
         out = (_vp * m)()
         o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
                             inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
                             plain_per_ct=0, debug_stop=debug_stop)
-        _check(lib().hs_softmax(self.h, arr, m, n, M, ctypes.byref(o), out))
+        if jobs == 1:
+            _check(lib().hs_softmax(self.h, arr, m, n, M, ctypes.byref(o), out))
+        else:
+            _check(lib().hs_softmax_jobs(self.h, arr, m, jobs, n, M, ctypes.byref(o), out))
         return [Ciphertext(self, _vp(out[i])) for i in range(m)]
 
     def softmax_stats(self):

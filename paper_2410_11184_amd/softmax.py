@@ -28,3 +28,24 @@ def softmax_encrypted(ctx, logits, M, variant="SM", seed=1, k=0, exp_degree=0, i
     out = ctx.softmax(cts, n, M, variant=1 if variant in ("B", "SMB", 1) else 0, k=k,
                       exp_degree=exp_degree, inv_degrees=inv_degrees)
     return decrypt_outputs(ctx, out, n)
+
+
+def softmax_jobs_encrypted(ctx, logits_list, M, variant="B", seed=1, k=0, exp_degree=0, inv_degrees=(0, 0, 0)):
+    """Several independent Softmax jobs of one shape (same n and vector count)
+    evaluated in lockstep by hs_softmax_jobs.  Returns one (L, n) array per job."""
+    logits_list = [np.asarray(x, dtype=np.float64) for x in logits_list]
+    n = logits_list[0].shape[1]
+    cts, counts = [], []
+    for j, x in enumerate(logits_list):
+        if x.shape != logits_list[0].shape:
+            raise ValueError("jobs of one lockstep group must share their shape")
+        c = encrypt_logits(ctx, x, M, seed + 1000 * j)
+        cts += c
+        counts.append(len(c))
+    out = ctx.softmax(cts, n, M, variant=1 if variant in ("B", "SMB", 1) else 0, k=k, exp_degree=exp_degree,
+                      inv_degrees=inv_degrees, jobs=len(logits_list))
+    res, o = [], 0
+    for cnt in counts:
+        res.append(decrypt_outputs(ctx, out[o:o + cnt], n))
+        o += cnt
+    return res

@@ -105,7 +105,24 @@ WORKLOADS = {
     "fgb16_sm": dict(preset="fgb16", n=256, M=128.0, m=1, L=128, law="clipped", sigma=16.0, seed=1001),
     # batched: 64 ciphertexts, 8192 Softmax of dim 256, U[-128, 0]
     "fgb16_smb64": dict(preset="fgb16", n=256, M=128.0, m=64, L=8192, law="uniform", seed=1002),
+    # uneven batch: attention-score shapes of 32 layers x 32 heads x 128 queries
+    # (each layer 4096 Softmax of dim 128 in 16 ciphertexts, N(0,4^2) clipped to
+    # [-64, 0]) plus one Softmax of dim 32768 filling a ciphertext, U[-256, 0]
+    "fgb16_uneven": dict(preset="fgb16", seed=1003, groups=[
+        dict(jobs=32, n=128, M=64.0, m=16, L=4096, law="clipped", sigma=4.0, variant=1),
+        dict(jobs=1, n=32768, M=256.0, m=1, L=1, law="uniform", variant=0),
+    ]),
 }
+
+
+def group_logits(name, gi, job):
+    """Logits of job `job` of group `gi` of a multi-group workload."""
+    w = WORKLOADS[name]
+    g = w["groups"][gi]
+    seed = w["seed"] * 1000 + gi * 100 + job
+    if g["law"] == "uniform":
+        return logits_uniform(g["L"], g["n"], g["M"], seed)
+    return logits_clipped_normal(g["L"], g["n"], g["M"], g["sigma"], seed)
 
 
 def workload_logits(name, L=None, seed=None):
