@@ -175,6 +175,56 @@ def run_uneven(args):
     print(json.dumps(rec), flush=True)
 
 
+def run_serve(args):
+    """The serving loop under a Poisson request stream: one JSON line with
+    Softmax calls/s over the run, p50 / p99 request latency and the precision
+    per dimension (>= 16 bits required up to dimension 256)."""
+    import synthetic
+    from paper_2410_11184_amd import serve
+    from oracle import softmax as S
+    w = synthetic.WORKLOADS[args.workload]
+    p = synthetic.preset(w["preset"])
+    stream = synthetic.serve_stream(w["count"], w["rate"], seed=w["seed"], M=w["M"])
+    t0 = time.perf_counter()
+    srv = serve.SoftmaxServer(p, workers=2, hbm_budget_gb=120.0, variant=1, key_seed=2004, warm_dims=(256,))
+    _log("server ready in %.1fs" % (time.perf_counter() - t0))
+    start = time.perf_counter()
+    reqs = []
+    for rid, (t_arr, n, x) in enumerate(stream):
+        delay = start + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        reqs.append(srv.submit(rid, x, w["M"], t_arrival=start + t_arr))
+        _log("submitted request %d (n=%d, %d vectors)" % (rid, n, x.shape[0]))
+    for r in reqs:
+        if not r.done.wait(900):
+            raise RuntimeError("request %d did not complete" % r.rid)
+        _log("request %d (n=%d, %d vectors) done: %.2fs%s" % (r.rid, r.n, r.V, r.latency,
+                                                             " ERROR %s" % r.error if r.error else ""))
+    end = max(r.t_done for r in reqs)
+    srv.close()
+    errors = [str(r.error) for r in reqs if r.error is not None]
+    calls = sum(r.V for r in reqs if r.error is None)
+    per_dim = {}
+    for r in reqs:
+        if r.error is None:
+            b = S.precision_bits(S.softmax(r.logits), r.result)["worst"]
+            per_dim[r.n] = min(per_dim.get(r.n, 99.0), b)
+    gated = all(b >= 16.0 for n, b in per_dim.items() if n <= 256) and not errors
+    elapsed = end - start
+    rec = {"metric": "encrypted Softmax calls/s, serving loop (Poisson stream, dims 64..32768)",
+           "value": calls / elapsed if gated else 0.0, "unit": "Softmax calls/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": 1e3 * elapsed, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "%d requests, Poisson %.1f/s, dims log-uniform 64..32768, 1-512 vectors, "
+                                  "U[-128,0], 2 workers, lockstep batching by shape" % (w["count"], w["rate"]),
+                      "parallelism": "single-gpu"},
+           "latency": serve.latency_stats(reqs), "requests": len(reqs), "errors": errors,
+           "batched_requests": sum(1 for r in reqs if r.batch_jobs > 1),
+           "worst_bits_by_dim": {str(k): round(v, 2) for k, v in sorted(per_dim.items())}}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +246,9 @@ def main():
 
     if args.workload == "fgb16_uneven":
         run_uneven(args)
+        return
+    if args.workload == "fgb16_serve":
+        run_serve(args)
         return
     import torch
     import synthetic

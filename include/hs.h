@@ -102,6 +102,19 @@ hs_status hs_ctx_get_info(const hs_ctx* ctx, hs_ctx_info* info);
 hs_status hs_ctx_primes(const hs_ctx* ctx, uint64_t* out, size_t cap, size_t* n);
 /* Block until all work issued on the context's stream has finished. */
 hs_status hs_sync(hs_ctx* ctx);
+/* A new HIP stream (default priority, non-blocking) on `device`, for a
+ * context of its own (contexts on different streams overlap on the GPU);
+ * destroy it after its contexts. */
+hs_status hs_stream_create(int device, void** stream);
+hs_status hs_stream_destroy(void* stream);
+/* Device memory of the context's arena: bytes held by live objects (keys,
+ * tables, ciphertexts) and bytes reserved from the device (8 GiB chunks). */
+hs_status hs_ctx_memory(const hs_ctx* ctx, size_t* in_use, size_t* reserved);
+/* Return the arena's wholly unused chunks to the device (e.g. after a large
+ * batch, so another context on the same GPU can use the memory); waits for
+ * the context's stream first.  Writes the bytes released to *released (may
+ * be NULL). */
+hs_status hs_ctx_trim(hs_ctx* ctx, size_t* released);
 
 /* KeyGen (Section 2.2): secret, public and relinearisation keys from one
  * 64-bit seed.  Every draw is Philox4x32-10 (Salmon et al., SC11) with
@@ -176,15 +189,15 @@ hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out);
  * k = ceil(log2 M - log2 ln n) (Theorem "th:prec_softmax"). */
 typedef struct hs_softmax_opts {
     int variant;
-    int k;
+    int k;                /* 0 = the Theorem's k (+1 from n = 4096)           */
     int exp_degree;       /* degree of the exp approximation, 2^t - 1; 0 = 15 */
     int inv_degree_first; /* degree of the first normalisation polynomial     */
     int inv_degree_mid;   /* intermediate iterations                          */
     int inv_degree_last;  /* last iteration; 0 for any of the three: 2^d - 1  */
-                          /* with the paper's depths d for dimension n        */
-                          /* (Section 5, auxiliary-thread level table):       */
-                          /* 6, then 4 / 5 / 6 (n <= 128 / <= 512 / larger),  */
-                          /* last 7 / 7 / 8                                   */
+                          /* by dimension n: up to 256 the paper's depths at  */
+                          /* n = 256 (Section 5, auxiliary-thread level       */
+                          /* table: 6, 5, 7); n <= 1024: 6, 6, 8; larger:     */
+                          /* 7, 7, 8                                          */
     double alpha;         /* reserved (0)                                     */
     int plain_per_ct;     /* reserved (0)                                     */
     int debug_stop;       /* tests: >= 0 returns y after that iteration

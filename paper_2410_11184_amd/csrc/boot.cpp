@@ -411,7 +411,25 @@ static const LinLevel& stc_masked_level(Context& c, BootCtx& B, int L) {
     return B.stc_masked.emplace(L, lv).first->second;
 }
 
-Ct bootstrap(Context& c, const Ct& x, double bound, int mask_L) { return bootstrap_stage(c, x, bound, 0, mask_L); }
+// Large batches are refreshed 16 ciphertexts at a time: every step acts per
+// ciphertext, and the transient memory of a bootstrap (hoisted key-switching
+// buffers and baby-step rotations at the top level, ~1 GB per ciphertext at
+// N = 2^16) would otherwise grow with the batch.
+Ct bootstrap(Context& c, const Ct& x, double bound, int mask_L) {
+    constexpr int kChunk = 16;
+    if (x.m <= kChunk) return bootstrap_stage(c, x, bound, 0, mask_L);
+    std::vector<Ct> parts;
+    for (int i = 0; i < x.m; i += kChunk) {
+        Ct in = ct_slice(c, x, i, std::min(kChunk, x.m - i));
+        parts.push_back(bootstrap_stage(c, in, bound, 0, mask_L));
+        ct_free(c, in);
+    }
+    std::vector<const Ct*> ptrs;
+    for (auto& q : parts) ptrs.push_back(&q);
+    Ct out = ct_gather(c, ptrs);
+    for (auto& q : parts) ct_free(c, q);
+    return out;
+}
 
 // stop: 0 = full; 1 = after ModRaise; 2 = after CoeffToSlot; 3 = real part
 // after the split; 4 = real-part half of z after the polynomials; 5 / 6 =

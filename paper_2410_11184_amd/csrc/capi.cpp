@@ -111,6 +111,42 @@ hs_status hs_ctx_get_info(const hs_ctx* ctx, hs_ctx_info* info) {
     });
 }
 
+hs_status hs_stream_create(int device, void** stream) {
+    return guard([&] {
+        NEED(stream);
+        *stream = nullptr;
+        HS_REQUIRE(hipSetDevice(device) == hipSuccess, hs::E_DEVICE, "hipSetDevice failed");
+        hipStream_t st = nullptr;
+        HS_REQUIRE(hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess, hs::E_DEVICE,
+                   "hipStreamCreate failed");
+        *stream = (void*)st;
+    });
+}
+
+hs_status hs_stream_destroy(void* stream) {
+    return guard([&] {
+        NEED(stream);
+        HS_REQUIRE(hipStreamDestroy((hipStream_t)stream) == hipSuccess, hs::E_DEVICE, "hipStreamDestroy failed");
+    });
+}
+
+hs_status hs_ctx_memory(const hs_ctx* ctx, size_t* in_use, size_t* reserved) {
+    return guard([&] {
+        NEED(ctx);
+        if (in_use) *in_use = ctx->c->pool.bytes_in_use();
+        if (reserved) *reserved = ctx->c->pool.bytes_reserved();
+    });
+}
+
+hs_status hs_ctx_trim(hs_ctx* ctx, size_t* released) {
+    return guard([&] {
+        NEED(ctx);
+        ctx->c->sync();
+        const size_t r = ctx->c->pool.trim(~(size_t)0);
+        if (released) *released = r;
+    });
+}
+
 hs_status hs_ctx_primes(const hs_ctx* ctx, uint64_t* out, size_t cap, size_t* n) {
     return guard([&] {
         NEED(ctx);

@@ -25,6 +25,7 @@
 //    afterwards: the bootstrapping error is then one value per Softmax, a
 //    common factor that the next renormalisation removes, instead of an
 //    independent error per element that the squarings amplify by 2^k.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -93,8 +94,12 @@ static void free_interval(double lo, double hi, double& a, double& b) {
     b = a + w;
 }
 
-// bound on |Lambda| used to scale it into the bootstrapping range
-static double lam_bound_big(Context&, const Ct&, double lam_bound) { return std::max(64.0, lam_bound); }
+// bound on |Lambda| for its bootstrapping: Lambda_j ~ 1 / ||y0||_(2^(j+1))
+// stays below sqrt(n) for rows whose largest logit is near 0; a loose bound
+// costs little since Lambda's bootstrapping error is one factor per Softmax
+static double lam_bound_big(int n, double lam_bound) {
+    return std::max({64.0, lam_bound, 4.0 * std::sqrt((double)n)});
+}
 
 // Bootstrap x when its level is below `need`.  mask_L > 0: x is zero off
 // slots [0, L) and the refreshed value is masked the same way, so that its
@@ -150,7 +155,9 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     HS_REQUIRE(M > 0, E_ARG, "range M must be positive");
     HS_REQUIRE(x.ncomp == 2, E_ARG, "degree-1 ciphertexts expected");
     const int L = (int)((long long)m * N0 / n);
-    const int k = o.k > 0 ? o.k : theorem_k(n, M);
+    // Theorem "th:prec_softmax"'s k; from n = 4096 one more iteration, which
+    // narrows the first normalisation interval [e^(-2M/2^k), 1]
+    const int k = o.k > 0 ? o.k : theorem_k(n, M) + (n >= 4096 ? 1 : 0);
     const int per = n / m;
     const int nrot = ilog2(per);
     const bool smb = o.variant == 1;
@@ -193,8 +200,15 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         const double e = smb_step ? std::ldexp(1.0, -j) : 0.5;
         int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
         if (deg <= 0) {
-            const int dmid = n <= 128 ? 4 : (n <= 512 ? 5 : 6);
-            const int d = j == 1 ? 6 : (last ? (n <= 512 ? 7 : 8) : dmid);
+            // the paper's depths at n = 256 (6, 5, 7) for n <= 256 (its
+            // minimax polynomials allow depth 4 in the middle at n = 128; these
+            // interpolants do not); above, one more level for the first and
+            // middle steps (the interpolants' relative error at the low end of
+            // [~1/n, 1] would otherwise widen every later interval)
+            int d;
+            if (n <= 256) d = j == 1 ? 6 : (last ? 7 : 5);
+            else if (n <= 1024) d = last ? 8 : 6;
+            else d = last ? 8 : 7;
             deg = (1 << d) - 1;
         }
         double a, b;
@@ -280,7 +294,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             HS_REQUIRE(y0.level >= want, E_LEVEL, "Softmax version B: main-thread level budget exhausted");
             if (big.level < want) {
                 bool rep;
-                Ct b2 = ensure_level(c, big, want, lam_bound_big(c, big, lam_bound), st, rep, "Lambda", j, L);
+                Ct b2 = ensure_level(c, big, want, lam_bound_big(n, lam_bound), st, rep, "Lambda", j, L);
                 if (rep) {
                     ct_free(c, big);
                     big = b2;

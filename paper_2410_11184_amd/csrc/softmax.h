@@ -7,10 +7,9 @@ struct SoftmaxOpts {
     int variant = 0;          // 0 = SM (Algorithm SM), 1 = SM version B
     int k = 0;                // iterations; 0 = ceil(log M - log ln n)
     int exp_degree = 15;
-    // 0 = the depths the paper uses for dimension n (Section 5, table of the
-    // auxiliary thread's level usage): degrees 2^d - 1 with d = 6 for the
-    // first iteration, 4 / 5 / 6 for the intermediate ones (n <= 128 /
-    // n <= 512 / larger) and 7 / 7 / 8 for the last one
+    // 0 = by dimension (degrees 2^d - 1): n <= 256 the depths of the paper's
+    // table of the auxiliary thread's level usage at n = 256 (Section 5: 6,
+    // 5, 7); n <= 1024: 6, 6, 8; larger: 7, 7, 8
     int inv_degree_first = 0;
     int inv_degree_mid = 0;
     int inv_degree_last = 0;

@@ -104,6 +104,10 @@ def lib():
         "hs_mul_monomial": [_vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_dbg_ntt": [_vp, S, _u64p, ctypes.c_size_t, S],
         "hs_dbg_mul_rate": [_vp, ctypes.POINTER(ctypes.c_double)],
+        "hs_ctx_memory": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+        "hs_stream_create": [S, ctypes.POINTER(_vp)],
+        "hs_stream_destroy": [_vp],
+        "hs_ctx_trim": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     }
     optional = {
         "hs_bootstrap": [_vp, _vp, ctypes.POINTER(_vp)],
@@ -138,6 +142,17 @@ def lib():
 def _check(st):
     if st != 0:
         raise HSError(st, lib().hs_last_error().decode())
+
+
+def stream_create(device=0):
+    """A new HIP stream owned by the caller (hs_stream_create)."""
+    st = _vp()
+    _check(lib().hs_stream_create(device, ctypes.byref(st)))
+    return st
+
+
+def stream_destroy(stream):
+    _check(lib().hs_stream_destroy(stream))
 
 
 def current_stream():
@@ -375,6 +390,18 @@ class Context:
         buf = (ctypes.c_double * 4)()
         _check(lib().hs_softmax_stats(self.h, buf, 4))
         return dict(k=int(buf[0]), bootstraps=int(buf[1]), levels_left=int(buf[2]), ms=float(buf[3]))
+
+    def memory(self):
+        """(bytes in use, bytes reserved) of the context's device arena."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().hs_ctx_memory(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def trim(self):
+        """Return unused arena chunks to the device; bytes released."""
+        r = ctypes.c_size_t()
+        _check(lib().hs_ctx_trim(self.h, ctypes.byref(r)))
+        return r.value
 
     def mul_rate(self):
         """Measured v_mad_u64_u32 throughput of the device (10^12 ops/s)."""

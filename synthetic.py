@@ -112,7 +112,23 @@ WORKLOADS = {
         dict(jobs=32, n=128, M=64.0, m=16, L=4096, law="clipped", sigma=4.0, variant=1),
         dict(jobs=1, n=32768, M=256.0, m=1, L=1, law="uniform", variant=0),
     ]),
+    # serving: Poisson arrivals, dimensions log-uniform over 64..32768, 1-512
+    # vectors per request, logits U[-128, 0]
+    "fgb16_serve": dict(preset="fgb16", seed=1004, count=12, rate=1.0, M=128.0),
 }
+
+
+def serve_stream(count, rate, seed=1004, dims=tuple(2 ** e for e in range(6, 16)), vmax=512, M=128.0):
+    """Poisson request stream: (arrival time, dimension, logits) with
+    dimensions log-uniform over `dims`, 1..vmax vectors, logits U[-M, 0]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(dims[rng.integers(0, len(dims))])
+        V = int(rng.integers(1, vmax + 1))
+        out.append((t, n, logits_uniform(V, n, M, seed * 1000 + i)))
+    return out
 
 
 def group_logits(name, gi, job):
