@@ -462,6 +462,8 @@ CtHandle::~CtHandle() {
 static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vector<int>& src_row,
                          const std::vector<int>& dst, const std::vector<int>& dst_row, bool centered) {
     const int k = (int)src.size(), m = (int)dst.size();
+    // the conversion kernel holds k sources in registers and m targets in LDS
+    HS_REQUIRE(k >= 1 && k <= 16 && m <= kMaxRows, E_PARAM, "base conversion shape out of range");
     std::vector<u64> inv_hat(k), inv_hat_s(k), hat((size_t)k * m), hat_s((size_t)k * m);
     for (int i = 0; i < k; i++) {
         const u64 di = c.primes[src[i]];

@@ -743,44 +743,82 @@ void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* p
 }
 
 // --------------------------------------------------------- base conversion
+// One thread per coefficient, K (the number of source primes) a template
+// argument so the lifted sources stay in registers; the conversion constants
+// (K x m products [D/d_s]_t and the target primes) are staged in LDS once per
+// workgroup and read as broadcasts inside the product loop.
 constexpr int kMaxConvSrc = 16;
+constexpr int kMaxConvDst = 64;
 
-__global__ void base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t og, const u64* in, size_t ig) {
+template <int K>
+__global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t og,
+                                                           const u64* in, size_t ig) {
+    __shared__ u64 s_hat[K * kMaxConvDst];
+    __shared__ u64 s_q[kMaxConvDst], s_mu[kMaxConvDst], s_r64[kMaxConvDst], s_dmod[kMaxConvDst];
+    __shared__ int s_bits[kMaxConvDst], s_row[kMaxConvDst];
+    const int m = C.m;
+    for (int e = threadIdx.x; e < K * m; e += blockDim.x) s_hat[e] = C.hat[e];
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        const PrimeInfo P = T.prime[C.dst_prime[t]];
+        s_q[t] = P.q;
+        s_mu[t] = P.mu;
+        s_bits[t] = P.bits;
+        s_r64[t] = C.r64[t];
+        s_dmod[t] = C.dmod[t];
+        s_row[t] = C.dst_row[t];
+    }
+    __syncthreads();
     const int g = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = T.N;
     if (i >= N) return;
-    u64 xh[kMaxConvSrc];
+    u64 xh[K];
     int nneg = 0;
-    for (int s = 0; s < C.k; s++) {
+#pragma unroll
+    for (int s = 0; s < K; s++) {
         const u64 x = in[(size_t)g * ig + (size_t)C.src_row[s] * N + i];
         const u64 d = T.prime[C.src_prime[s]].q;
         xh[s] = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
         // centred: xh - d_s contributes xh * hat - D
         if (C.centered && xh[s] > (d - 1) / 2) nneg++;
     }
-    for (int t = 0; t < C.m; t++) {
-        const PrimeInfo P = T.prime[C.dst_prime[t]];
-        const u64 q = P.q;
-        // exact sum of k < 16 products below 2^122, then one reduction of its
-        // two 64-bit words: (hi mod q) 2^64 + lo
+    u64* o = out + (size_t)g * og + i;
+#pragma unroll 2
+    for (int t = 0; t < m; t++) {
+        // exact sum of K <= 16 products below 2^122, then one reduction of
+        // its two 64-bit words: (hi mod q) 2^64 + lo
         unsigned __int128 wide = 0;
-        for (int s = 0; s < C.k; s++) wide += (unsigned __int128)xh[s] * C.hat[s * C.m + t];
-        u64 acc = reduce_wide(wide, P, C.r64[t]);
+#pragma unroll
+        for (int s = 0; s < K; s++) wide += (unsigned __int128)xh[s] * s_hat[s * m + t];
+        PrimeInfo P;
+        P.q = s_q[t];
+        P.mu = s_mu[t];
+        P.bits = s_bits[t];
+        u64 acc = reduce_wide(wide, P, s_r64[t]);
         if (nneg) {
-            const u64 dm = C.dmod[t];
-            for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, q);
+            const u64 dm = s_dmod[t];
+            for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, P.q);
         }
-        out[(size_t)g * og + (size_t)C.dst_row[t] * N + i] = acc;
+        o[(size_t)s_row[t] * N] = acc;
     }
+}
+
+template <int K>
+static void launch_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in,
+                                size_t ig, int ngroups, hipStream_t st) {
+    if (C.k == K)
+        hipLaunchKernelGGL(base_convert_kernel<K>, dim3((T.N + 255) / 256, ngroups), dim3(256), 0, st, T, C, out,
+                           og, in, ig);
+    else if constexpr (K < kMaxConvSrc)
+        launch_base_convert<K + 1>(T, C, out, og, in, ig, ngroups, st);
 }
 
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride, const u64* in,
                     size_t in_gstride, int ngroups, void* stream) {
     if (ngroups == 0 || C.m == 0) return;
+    if (C.k < 1 || C.k > kMaxConvSrc || C.m > kMaxConvDst) return;  // tables are checked when built
     ProfScope ps(T.prof, PK_CONV, 8.0 * T.N * ngroups * (double)(C.k + C.m), stream);
-    hipLaunchKernelGGL(base_convert_kernel, dim3((T.N + 255) / 256, ngroups), dim3(256), 0, (hipStream_t)stream,
-                       T, C, out, out_gstride, in, in_gstride);
+    launch_base_convert<1>(T, C, out, out_gstride, in, in_gstride, ngroups, (hipStream_t)stream);
 }
 
 // centred lift: v = x if x <= (q_s - 1)/2 else x - q_s, reduced mod each row's prime
@@ -818,25 +856,28 @@ void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t 
 // acc:  [ncts][2][E][N]
 constexpr int kMaxDigits = 16;
 
-__global__ void key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u64* key, int ncts, int beta,
-                                 int E, int nql, int key_rows, int key_nq) {
+template <int B>
+__global__ void __launch_bounds__(256) key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u64* key,
+                                                        int ncts, int E, int nql, int key_rows, int key_nq) {
     const int r = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = T.N;
     if (i >= N) return;
     const int kr = r < nql ? r : key_nq + (r - nql);
     const PrimeInfo P = T.prime[kr];
-    u64 kb[kMaxDigits], ka[kMaxDigits];
-    for (int j = 0; j < beta; j++) {
+    u64 kb[B], ka[B];
+#pragma unroll
+    for (int j = 0; j < B; j++) {
         kb[j] = key[((size_t)(2 * j) * key_rows + kr) * N + i];
         ka[j] = key[((size_t)(2 * j + 1) * key_rows + kr) * N + i];
     }
     const u64 r64 = T.r64[kr];
     for (int g = 0; g < ncts; g++) {
-        // exact sums of beta <= 16 products below 2^122, reduced once
+        // exact sums of B <= 16 products below 2^122, reduced once
         unsigned __int128 s0 = 0, s1 = 0;
-        for (int j = 0; j < beta; j++) {
-            const u64 x = ext[(((size_t)g * beta + j) * E + r) * N + i];
+#pragma unroll
+        for (int j = 0; j < B; j++) {
+            const u64 x = ext[(((size_t)g * B + j) * E + r) * N + i];
             s0 += (unsigned __int128)x * kb[j];
             s1 += (unsigned __int128)x * ka[j];
         }
@@ -845,13 +886,23 @@ __global__ void key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u6
     }
 }
 
+template <int B>
+static void launch_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta,
+                             int E, int nql, int key_rows, int key_nq, hipStream_t st) {
+    if (beta == B)
+        hipLaunchKernelGGL(key_inner_kernel<B>, dim3((T.N + 255) / 256, E), dim3(256), 0, st, T, acc, ext, key,
+                           ncts, E, nql, key_rows, key_nq);
+    else if constexpr (B < kMaxDigits)
+        launch_key_inner<B + 1>(T, acc, ext, key, ncts, beta, E, nql, key_rows, key_nq, st);
+}
+
 void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta, int ext_rows,
                  int nq_level, int key_rows, int key_nq, int alpha, void* stream) {
     (void)alpha;
+    if (beta < 1 || beta > kMaxDigits) return;  // the digit count is checked when the context is built
     // algorithmic bytes: the key once per launch, ext read and acc written per ciphertext
     ProfScope ps(T.prof, PK_KEYIP, 8.0 * T.N * ext_rows * (2.0 * beta + ncts * (beta + 2.0)), stream);
-    hipLaunchKernelGGL(key_inner_kernel, dim3((T.N + 255) / 256, ext_rows), dim3(256), 0, (hipStream_t)stream, T,
-                       acc, ext, key, ncts, beta, ext_rows, nq_level, key_rows, key_nq);
+    launch_key_inner<1>(T, acc, ext, key, ncts, beta, ext_rows, nq_level, key_rows, key_nq, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------- sampling
