@@ -4,7 +4,10 @@ One step = one batched homomorphic Softmax job (Algorithm SM version B over
 m = 64 ciphertexts, Section 4.3): 8192 Softmax of dimension 256 with inputs
 in [-128, 0], RNS-CKKS N = 2^16 with bootstrapping of the auxiliary thread.
 Encrypted inputs, keys and plaintext tables are resident in HBM before the
-timed region; the decrypted outputs of the last step are checked against the
+timed region; the timed steps replay the whole Softmax schedule captured once
+as a HIP graph (--no-graph: eager launches), and per-kernel durations come
+from an eager pass of the same schedule with an event pair around every
+launch.  The decrypted outputs of the last step are checked against the
 FP64 Softmax (>= 16 bits worst case).  The plain per-ciphertext form (SM on
 one ciphertext of 128 Softmax, Section 3) is timed after the batched steps.
 
@@ -233,6 +236,7 @@ def main():
     ap.add_argument("--workload", default="fgb16_smb64")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured schedule")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -281,24 +285,52 @@ def main():
         out = ctx.softmax(cts, n, M, variant=variant)
         ctx.sync()
         _log("warmup %d: %.3fs %s" % (i, time.perf_counter() - t0, ctx.softmax_stats()))
-    ctx.prof_enable(True)
+    graph = None
+    if not args.no_graph:
+        # the whole Softmax schedule captured once as a HIP graph, replayed per step
+        t0 = time.perf_counter()
+        plan = ctx.softmax_plan(cts, n, M, variant=variant)
+        capture_s = time.perf_counter() - t0
+        nodes, arena = plan.info()
+        plan.run(cts)
+        _log("captured %d graph nodes in %.2fs (arena %.1f GB)" % (nodes, capture_s, arena / 1e9))
+        graph = {"nodes": nodes, "capture_s": capture_s, "arena_GB": arena / 1e9}
+        step = lambda: plan.run(cts)
+    else:
+        step = lambda: ctx.softmax(cts, n, M, variant=variant)
     torch.cuda.synchronize()
     ctx.sync()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        out = ctx.softmax(cts, n, M, variant=variant)
+        out = step()
         _log("step %d done" % i)
     ctx.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ctx.prof_enable(False)
-    prof = ctx.prof_collect()
     stats = ctx.softmax_stats()
     ms_step = 1e3 * elapsed / args.steps
     value = L * args.steps / elapsed
     y = decrypt_outputs(ctx, out, n)
     bits = S.precision_bits(S.softmax(x), y)
-    _log("batched: %.2f ms/step, %.1f calls/s, precision %s" % (ms_step, value, bits))
+    _log("batched (%s): %.2f ms/step, %.1f calls/s, precision %s" %
+         ("graph" if graph else "eager", ms_step, value, bits))
+
+    # per-kernel durations: the same schedule launched eagerly with an event
+    # pair around every launch (graph replays carry no per-kernel events)
+    ctx.prof_enable(True)
+    ctx.sync()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out_e = ctx.softmax(cts, n, M, variant=variant)
+    ctx.sync()
+    eager_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    ctx.prof_enable(False)
+    prof = ctx.prof_collect()
+    if graph:
+        same = all(np.array_equal(a.export(), b.export()) for a, b in zip(out[:4], out_e[:4]))
+        graph.update({"eager_profiled_ms_per_step": eager_ms, "replay_equals_eager_first4": same})
+    del out_e
+    _log("eager with per-launch events: %.2f ms/step" % eager_ms)
 
     # dominant kernel by measured time
     dom = max(prof, key=lambda k: prof[k]["ms"])
@@ -374,7 +406,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "N=2^16 RNS-CKKS, m=64 ciphertexts, 8192 Softmax of dim 256, logits U[-128,0], "
-                               "SM version B, k=%d, aux bootstraps per job=%d" % (stats["k"], stats["bootstraps"]),
+                               "SM version B, k=%d, aux bootstraps per job=%d, %s schedule" %
+                               (stats["k"], stats["bootstraps"], "HIP-graph" if graph else "eager"),
                    "global_batch": L, "seq_len": n, "parallelism": "single-gpu"},
         "precision_bits": bits,
         "plain": plain,
@@ -382,6 +415,8 @@ def main():
         # not the metric: the client side (pack, encode, PCIe upload, encrypt) and decryption
         "client_encrypt_s": client_encrypt_s,
         "calls_per_s_including_client_encrypt": L / (ms_step * 1e-3 + client_encrypt_s),
+        "schedule": "hip_graph" if graph else "eager",
+        "graph": graph,
         "roofline": roofline,
         "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] // args.steps,

@@ -53,6 +53,7 @@ typedef int hs_status;
 
 typedef struct hs_ctx hs_ctx;
 typedef struct hs_ct hs_ct;
+typedef struct hs_softmax_plan hs_softmax_plan;
 
 /* Parameter set.  Primes are found by the rule: for a bit size b the
  * candidates are 2^b + 1 + j 2N for j = 1, -1, 2, -2, ...; the chain takes,
@@ -231,6 +232,31 @@ hs_status hs_softmax_jobs(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs,
  * and main ciphertexts refreshed), levels_left, milliseconds]; writes
  * min(n, 4) values. */
 hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n);
+
+/* Captured Softmax schedule (a HIP graph).  The schedule of hs_softmax_jobs
+ * (Algorithms SM / SM-B with the many-ciphertext packing of Section 4.2) is
+ * fixed by the ciphertext count, job count, n, M, the options and the input
+ * level and scale, so it is recorded once and replayed.
+ * hs_softmax_plan_create: `in` (m handles of one ciphertext each, one level,
+ * one scale) is both the shape template and the input of one eager warm-up
+ * run, which builds every table and key the schedule needs; the schedule is
+ * then captured on a stream of the plan's own.  The plan owns a private
+ * device arena (its input, intermediate and output buffers keep their
+ * addresses across replays); it borrows the context, which must outlive it.
+ * Errors as hs_softmax_jobs; HS_E_STATE when the launch profiler is enabled
+ * or another capture is in progress.
+ * hs_softmax_plan_run: copies the m inputs (same level, size and scale as
+ * the template, else HS_E_LEVEL / HS_E_SCALE) into the plan, replays the
+ * graph and writes m new output handles (results bit for bit those of
+ * hs_softmax_jobs on the same inputs).  Synchronous; updates
+ * hs_softmax_stats.  Replays of one plan must not overlap (one host thread).
+ * hs_softmax_plan_info: graph node count and arena bytes (either may be NULL).
+ * hs_softmax_plan_destroy: waits for the plan's stream and frees everything. */
+hs_status hs_softmax_plan_create(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
+                                 const hs_softmax_opts* opts, hs_softmax_plan** out);
+hs_status hs_softmax_plan_run(hs_softmax_plan* plan, hs_ct* const* in, size_t m, hs_ct** out);
+hs_status hs_softmax_plan_info(const hs_softmax_plan* plan, size_t* nodes, size_t* arena_bytes);
+void hs_softmax_plan_destroy(hs_softmax_plan* plan);
 
 /* Packing of Section 4 (host only).  logits: [L][n] row-major, L n =
  * m (N/2); out: [m][slots] with ciphertext j holding coordinate

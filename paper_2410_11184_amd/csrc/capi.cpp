@@ -8,6 +8,7 @@
 #include "host.h"
 #include "softmax.h"
 #include <chrono>
+#include <memory>
 #include <vector>
 
 struct hs_ctx {
@@ -528,6 +529,20 @@ hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int i
     });
 }
 
+static hs::SoftmaxOpts softmax_opts(const hs_softmax_opts* opts) {
+    hs::SoftmaxOpts o;
+    if (opts) {
+        o.variant = opts->variant;
+        o.k = opts->k;
+        if (opts->exp_degree > 0) o.exp_degree = opts->exp_degree;
+        if (opts->inv_degree_first > 0) o.inv_degree_first = opts->inv_degree_first;
+        if (opts->inv_degree_mid > 0) o.inv_degree_mid = opts->inv_degree_mid;
+        if (opts->inv_degree_last > 0) o.inv_degree_last = opts->inv_degree_last;
+        o.debug_stop = opts->debug_stop;
+    }
+    return o;
+}
+
 static hs_status softmax_impl(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
                               const hs_softmax_opts* opts, hs_ct** out) {
     if (out)
@@ -545,16 +560,7 @@ static hs_status softmax_impl(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t nj
             HS_REQUIRE(in[i]->ct.scale == in[0]->ct.scale, hs::E_SCALE, "inputs must share one scale");
             parts.push_back(&in[i]->ct);
         }
-        hs::SoftmaxOpts o;
-        if (opts) {
-            o.variant = opts->variant;
-            o.k = opts->k;
-            if (opts->exp_degree > 0) o.exp_degree = opts->exp_degree;
-            if (opts->inv_degree_first > 0) o.inv_degree_first = opts->inv_degree_first;
-            if (opts->inv_degree_mid > 0) o.inv_degree_mid = opts->inv_degree_mid;
-            if (opts->inv_degree_last > 0) o.inv_degree_last = opts->inv_degree_last;
-            o.debug_stop = opts->debug_stop;
-        }
+        const hs::SoftmaxOpts o = softmax_opts(opts);
         auto t0 = std::chrono::steady_clock::now();
         hs::Ct batch = hs::ct_gather(c, parts);
         hs::SoftmaxStats st;
@@ -586,6 +592,173 @@ hs_status hs_softmax_jobs(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs,
                           const hs_softmax_opts* opts, hs_ct** out) {
     return softmax_impl(ctx, in, m, njobs, n, M, opts, out);
 }
+
+// ------------------------------------------------- captured Softmax schedules
+// The schedule of one Softmax call (fixed ciphertext count, job count,
+// dimension, range, options, input level and scale) recorded once as a HIP
+// graph.  The plan owns a private arena: the graph's intermediate buffers keep
+// their addresses for every replay, so no other allocation may ever get them.
+struct hs_softmax_plan {
+    hs_ctx* ctx = nullptr;
+    hs::Pool pool;
+    hipStream_t stream = nullptr;   // capture and replay stream (a context may run on the null stream)
+    hs::Ct in, out;
+    int level = 0, ncomp = 2;
+    double scale = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double stats[3] = {0, 0, 0};
+    ~hs_softmax_plan() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        pool.release_all();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+// Points the context at the plan's arena and stream for the lifetime of the scope.
+struct PlanScope {
+    hs::Context& c;
+    void* stream0;
+    PlanScope(hs::Context& cc, hs_softmax_plan& p) : c(cc), stream0(cc.stream) {
+        c.cur = &p.pool;
+        c.stream = p.stream;
+    }
+    ~PlanScope() {
+        c.capturing = false;
+        c.cur = &c.pool;
+        c.stream = stream0;
+    }
+};
+}  // namespace
+
+hs_status hs_softmax_plan_create(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
+                                 const hs_softmax_opts* opts, hs_softmax_plan** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(in);
+        NEED(out);
+        HS_REQUIRE(m >= 1, hs::E_ARG, "m must be >= 1");
+        HS_REQUIRE(njobs >= 1 && m % njobs == 0, hs::E_ARG, "the ciphertext count must be a multiple of the job count");
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(!c.capturing && c.cur == &c.pool, hs::E_STATE, "a schedule is already being captured");
+        HS_REQUIRE(!hs::prof_enabled(c.T.prof), hs::E_STATE, "disable the launch profiler before capturing");
+        std::vector<const hs::Ct*> parts;
+        for (size_t i = 0; i < m; i++) {
+            HS_REQUIRE(in[i] != nullptr, hs::E_ARG, "null input ciphertext");
+            HS_REQUIRE(in[i]->ct.m == 1, hs::E_ARG, "one ciphertext per handle");
+            HS_REQUIRE(in[i]->ct.scale == in[0]->ct.scale, hs::E_SCALE, "inputs must share one scale");
+            parts.push_back(&in[i]->ct);
+        }
+        const hs::SoftmaxOpts o = softmax_opts(opts);
+        std::unique_ptr<hs_softmax_plan> P(new hs_softmax_plan);
+        P->ctx = ctx;
+        HS_REQUIRE(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) == hipSuccess, hs::E_DEVICE,
+                   "hipStreamCreate failed");
+        c.sync();                                   // inputs were produced on the context's stream
+        PlanScope scope(c, *P);
+        P->in = hs::ct_gather(c, parts);            // the plan's input buffer
+        P->level = P->in.level;
+        P->ncomp = P->in.ncomp;
+        P->scale = P->in.scale;
+        {
+            // eager run: builds every table and key the schedule touches and
+            // sizes the plan's arena, so the recording needs no host work
+            hs::SoftmaxStats st;
+            hs::Ct y = hs::softmax(c, P->in, (int)n, M, o, &st, (int)njobs);
+            hs::ct_free(c, y);
+            c.sync();
+        }
+        HS_REQUIRE(hipStreamBeginCapture(P->stream, hipStreamCaptureModeRelaxed) == hipSuccess, hs::E_DEVICE,
+                   "hipStreamBeginCapture failed");
+        c.capturing = true;
+        hs::SoftmaxStats st;
+        try {
+            P->out = hs::softmax(c, P->in, (int)n, M, o, &st, (int)njobs);
+        } catch (...) {
+            c.capturing = false;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(P->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        c.capturing = false;
+        HS_REQUIRE(hipStreamEndCapture(P->stream, &P->graph) == hipSuccess && P->graph, hs::E_DEVICE,
+                   "hipStreamEndCapture failed");
+        HS_REQUIRE(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) == hipSuccess, hs::E_DEVICE,
+                   "hipGraphInstantiate failed");
+        P->stats[0] = st.k;
+        P->stats[1] = st.bootstraps;
+        P->stats[2] = st.levels_left;
+        *out = P.release();
+    });
+}
+
+hs_status hs_softmax_plan_run(hs_softmax_plan* plan, hs_ct* const* in, size_t m, hs_ct** out) {
+    if (out)
+        for (size_t i = 0; i < m; i++) out[i] = nullptr;
+    return guard([&] {
+        NEED(plan);
+        NEED(in);
+        NEED(out);
+        hs::Context& c = *plan->ctx->c;
+        HS_REQUIRE(m == (size_t)plan->in.m, hs::E_ARG, "ciphertext count differs from the plan's");
+        for (size_t i = 0; i < m; i++) {
+            HS_REQUIRE(in[i] != nullptr, hs::E_ARG, "null input ciphertext");
+            const hs::Ct& a = in[i]->ct;
+            HS_REQUIRE(a.m == 1 && a.level == plan->level && a.ncomp == plan->ncomp, hs::E_LEVEL,
+                       "input level or size differs from the plan's");
+            HS_REQUIRE(a.scale == plan->scale, hs::E_SCALE, "input scale differs from the plan's");
+        }
+        HS_REQUIRE(!c.capturing && c.cur == &c.pool, hs::E_STATE, "a schedule is being captured");
+        auto t0 = std::chrono::steady_clock::now();
+        c.sync();                                   // inputs were produced on the context's stream
+        void* stream0 = c.stream;
+        c.stream = plan->stream;
+        try {
+            const size_t w = plan->in.ct_words(c.N);
+            for (size_t i = 0; i < m; i++) {
+                hs::Rows dst = c.ct_rows(in[i]->ct);
+                dst.base = plan->in.d + i * w;
+                hs::k_copy_rows(c.T, dst, c.ct_rows(in[i]->ct), c.stream);
+            }
+            HS_REQUIRE(hipGraphLaunch(plan->exec, plan->stream) == hipSuccess, hs::E_DEVICE, "hipGraphLaunch failed");
+            for (size_t i = 0; i < m; i++) out[i] = wrap(&c, hs::ct_slice(c, plan->out, (int)i, 1));
+            c.sync();
+        } catch (...) {
+            c.stream = stream0;
+            for (size_t i = 0; i < m; i++) {
+                if (out[i]) hs_ct_destroy(out[i]);
+                out[i] = nullptr;
+            }
+            throw;
+        }
+        c.stream = stream0;
+        auto t1 = std::chrono::steady_clock::now();
+        plan->ctx->last_stats[0] = plan->stats[0];
+        plan->ctx->last_stats[1] = plan->stats[1];
+        plan->ctx->last_stats[2] = plan->stats[2];
+        plan->ctx->last_stats[3] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    });
+}
+
+hs_status hs_softmax_plan_info(const hs_softmax_plan* plan, size_t* nodes, size_t* arena_bytes) {
+    return guard([&] {
+        NEED(plan);
+        if (nodes) {
+            size_t k = 0;
+            HS_REQUIRE(hipGraphGetNodes(plan->graph, nullptr, &k) == hipSuccess, hs::E_DEVICE,
+                       "hipGraphGetNodes failed");
+            *nodes = k;
+        }
+        if (arena_bytes) *arena_bytes = plan->pool.bytes_reserved();
+    });
+}
+
+void hs_softmax_plan_destroy(hs_softmax_plan* plan) { delete plan; }
 
 hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n) {
     return guard([&] {

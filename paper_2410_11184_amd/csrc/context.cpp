@@ -241,14 +241,19 @@ void Pool::release_all() {
 Pool::~Pool() { release_all(); }
 
 // --------------------------------------------------------------- context
-void Context::sync() { check_hip(hipStreamSynchronize((hipStream_t)stream), "stream sync"); }
+void Context::sync() {
+    HS_REQUIRE(!capturing, E_STATE, "stream synchronisation while a schedule is being captured");
+    check_hip(hipStreamSynchronize((hipStream_t)stream), "stream sync");
+}
 
 void Context::upload(void* dst, const void* src, size_t bytes) {
+    HS_REQUIRE(!capturing, E_STATE, "host-to-device copy while a schedule is being captured");
     check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)stream), "upload");
     sync();
 }
 
 void Context::download(void* dst, const void* src, size_t bytes) {
+    HS_REQUIRE(!capturing, E_STATE, "device-to-host copy while a schedule is being captured");
     check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream), "download");
     sync();
 }
@@ -734,6 +739,7 @@ static u64* make_switch_key(Context& c, int key_id, const u64* s_target) {
 }
 
 void keygen(Context& c, u64 seed) {
+    ContextArena arena(c);
     const int nt = c.nq + c.np;
     const size_t rows_words = (size_t)nt * c.N;
     for (auto& kv : c.keys) c.free_words(kv.second);
@@ -784,6 +790,7 @@ void add_galois_key(Context& c, int g) {
     g = ((g % (2 * c.N)) + 2 * c.N) % (2 * c.N);
     HS_REQUIRE(g % 2 == 1, E_ARG, "Galois element must be odd");
     if (c.keys.count(g)) return;
+    ContextArena arena(c);
     const int nt = c.nq + c.np;
     const size_t rows_words = (size_t)nt * c.N;
     u64* sg = c.alloc_words(rows_words);

@@ -25,6 +25,7 @@ enum ProfKind { PK_NTT = 0, PK_KEYIP, PK_CONV, PK_TENSOR, PK_EW, PK_PERM, PK_LIF
 Profiler* prof_create();
 void prof_destroy(Profiler* p);
 void prof_enable(Profiler* p, bool on);
+bool prof_enabled(const Profiler* p);
 // totals since the last call, per kind: [count, milliseconds, bytes]; syncs the events
 void prof_collect(Profiler* p, double* out);
 

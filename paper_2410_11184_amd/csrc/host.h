@@ -75,6 +75,7 @@ public:
     void free(void* p);
     void release_all();
     size_t trim(size_t bytes);   // release wholly free chunks until >= bytes freed
+    bool owns(const void* p) const { return live_.count(const_cast<void*>(p)) != 0; }
     size_t bytes_in_use() const { return in_use_; }
     size_t bytes_reserved() const { return reserved_; }
     ~Pool();
@@ -136,6 +137,10 @@ struct Context {
     void* stream = nullptr;
     int device = 0;
     Pool pool;
+    // arena that alloc_words draws from: `pool`, or a captured Softmax
+    // schedule's own arena while it is being recorded
+    Pool* cur = &pool;
+    bool capturing = false;      // host-device copies and syncs are refused while set
     std::vector<PrimeInfo> pinfo;
     u64 P_mod[kMaxRows];         // P mod q_i for Q primes
     // key material
@@ -177,8 +182,11 @@ struct Context {
     Rows comp_rows(const Ct& c, int comp) const {
         return Rows{c.d + (size_t)comp * c.comp_words(N), c.m, c.level + 1, c.ct_words(N), c.level + 1, 0, nq};
     }
-    u64* alloc_words(size_t w) { return (u64*)pool.alloc(w * sizeof(u64)); }
-    void free_words(u64* p) { pool.free(p); }
+    u64* alloc_words(size_t w) { return (u64*)cur->alloc(w * sizeof(u64)); }
+    void free_words(u64* p) {
+        if (cur != &pool && cur->owns(p)) cur->free(p);
+        else pool.free(p);
+    }
     void sync();
     void upload(void* dst, const void* src, size_t bytes);
     void download(void* dst, const void* src, size_t bytes);
@@ -190,6 +198,15 @@ struct Context {
     const ConvDev& moddown_tables(int level);
     const int* perm(int g);
     RowConsts shoup_consts(const std::vector<u64>& vals, int q_off, bool p_part = false) const;
+};
+
+// Key material lives as long as the context: while in scope, allocations come
+// from the context's own arena even when a captured schedule's arena is active.
+struct ContextArena {
+    Context& c;
+    Pool* prev;
+    explicit ContextArena(Context& cc) : c(cc), prev(cc.cur) { c.cur = &c.pool; }
+    ~ContextArena() { c.cur = prev; }
 };
 
 // ----------------------------------------------------------- arithmetic

@@ -49,6 +49,7 @@ void prof_destroy(Profiler* p) {
 void prof_enable(Profiler* p, bool on) {
     if (p) p->on = on;
 }
+bool prof_enabled(const Profiler* p) { return p && p->on; }
 void prof_collect(Profiler* p, double* out) {
     for (int k = 0; k < 3 * PK_COUNT; k++) out[k] = 0;
     if (!p) return;

@@ -119,6 +119,10 @@ def lib():
         "hs_softmax_jobs": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_uint32,
                             ctypes.c_double, ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_stats": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+        "hs_softmax_plan_create": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_uint32,
+                                   ctypes.c_double, ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
+        "hs_softmax_plan_run": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp)],
+        "hs_softmax_plan_info": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
         "hs_pack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double, _vp,
                             ctypes.POINTER(ctypes.c_size_t)],
         "hs_unpack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, _f64p],
@@ -135,6 +139,9 @@ def lib():
     L.hs_ct_destroy.restype = None
     L.hs_ctx_destroy.argtypes = [_vp]
     L.hs_ctx_destroy.restype = None
+    if hasattr(L, "hs_softmax_plan_destroy"):
+        L.hs_softmax_plan_destroy.argtypes = [_vp]
+        L.hs_softmax_plan_destroy.restype = None
     _lib = L
     return L
 
@@ -192,6 +199,37 @@ class Ciphertext:
         _check(lib().hs_ct_export(self.ctx.h, self.h, out, out.size, ctypes.byref(used)))
         lv, nc, _ = self.info
         return out.reshape(nc, lv + 1, -1)
+
+
+class SoftmaxPlan:
+    """A captured Softmax schedule (hs_softmax_plan_*); keeps its context alive."""
+
+    def __init__(self, ctx, handle, m):
+        self.ctx = ctx
+        self.h = handle
+        self.m = m
+
+    def run(self, cts):
+        if len(cts) != self.m:
+            raise ValueError("plan takes %d ciphertexts" % self.m)
+        arr = (_vp * self.m)(*[c.h for c in cts])
+        out = (_vp * self.m)()
+        _check(lib().hs_softmax_plan_run(self.h, arr, self.m, out))
+        return [Ciphertext(self.ctx, _vp(out[i])) for i in range(self.m)]
+
+    def info(self):
+        """(graph nodes, arena bytes)"""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().hs_softmax_plan_info(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hs_softmax_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Context:
@@ -385,6 +423,19 @@ class Context:
         else:
             _check(lib().hs_softmax_jobs(self.h, arr, m, jobs, n, M, ctypes.byref(o), out))
         return [Ciphertext(self, _vp(out[i])) for i in range(m)]
+
+    def softmax_plan(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), jobs=1):
+        """hs_softmax_plan_create: capture the schedule of softmax(cts, ...)
+        once (after one eager warm-up run on `cts`) for replays on new inputs
+        of the same shape, level and scale."""
+        m = len(cts)
+        arr = (_vp * m)(*[c.h for c in cts])
+        o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
+                            inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
+                            plain_per_ct=0, debug_stop=-1)
+        h = _vp()
+        _check(lib().hs_softmax_plan_create(self.h, arr, m, jobs, n, M, ctypes.byref(o), ctypes.byref(h)))
+        return SoftmaxPlan(self, h, m)
 
     def softmax_stats(self):
         buf = (ctypes.c_double * 4)()

@@ -59,6 +59,19 @@ PRESETS = {
         boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
                   K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
     ),
+    # the same bootstrapping ring with 10 user levels: room for a whole
+    # Softmax schedule (with bootstraps) at test size
+    "boot10u": dict(
+        logN=10,
+        q_bits=[53] + [40] * 10 + [40] * 3 + [60] * 11 + [60] * 3,
+        p_bits=[59] * 8,
+        digit=7,
+        hamming=64,
+        log_scale=40,
+        user_top=10,
+        boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
+                  K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
+    ),
 }
 
 SIGMA = 3.2

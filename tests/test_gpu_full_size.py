@@ -116,3 +116,31 @@ def test_softmax_workload_precision(boot_ctx, workload, variant):
     print(workload, variant, bits, boot_ctx.softmax_stats())
     assert bits["worst"] >= 16.0, bits
     assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -14
+
+
+def test_captured_schedule_at_full_size(boot_ctx):
+    """The launch configuration the benchmark times: the 64-ciphertext
+    version-B job captured as one HIP graph.  Two replays on different inputs
+    (with eager work in between) equal the eager call bit for bit on every
+    output ciphertext and meet the precision bar."""
+    from oracle import softmax as S
+    from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
+    w = synthetic.WORKLOADS["fgb16_smb64"]
+    n, M = w["n"], w["M"]
+    L = w["m"] * boot_ctx.slots // n
+    x0 = synthetic.workload_logits("fgb16_smb64", L=L)
+    cts = encrypt_logits(boot_ctx, x0, M, seed=41)
+    plan = boot_ctx.softmax_plan(cts, n, M, variant=1)
+    for r, x in enumerate([x0, synthetic.logits_uniform(L, n, M, seed=4242)]):
+        if r:
+            cts = encrypt_logits(boot_ctx, x, M, seed=43)
+        g = plan.run(cts)
+        e = boot_ctx.softmax(cts, n, M, variant=1)
+        assert len(g) == len(e) == w["m"]
+        for i, (a, b) in enumerate(zip(e, g)):
+            assert np.array_equal(a.export(), b.export()), "replay %d, ciphertext %d" % (r, i)
+        bits = S.precision_bits(S.softmax(x), decrypt_outputs(boot_ctx, g, n))
+        print("replay", r, bits)
+        assert bits["worst"] >= 16.0, bits
+        del g, e
+    plan.close()
