@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+TUNE_FILE = os.path.join(ROOT, "paper_2410_11184_amd", "tune_gfx950.json")
+
 PEAK_HBM_GBS = 8000.0
 # 32-bit integer multiplier peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz,
 # v_mad_u64_u32 issuing at the full VALU rate (the library's probe,
@@ -237,6 +239,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured schedule")
+    ap.add_argument("--tune", action="store_true",
+                    help="time interchangeable kernels during the warm-up and save the decisions")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -267,6 +271,12 @@ def main():
     n, M, m = w["n"], w["M"], w["m"]
     L = m * p["slots"] // n
     _log("context %s (N=2^%d, %d+%d primes)" % (w["preset"], p["logN"], len(p["q_bits"]), len(p["p_bits"])))
+    tune_src = "defaults"
+    if args.tune:
+        hs.tune_enable(True)        # shapes met in the warm-up time their candidates
+        tune_src = "tuned in this run"
+    elif os.path.exists(TUNE_FILE):
+        tune_src = "%s (%d decisions)" % (os.path.relpath(TUNE_FILE, ROOT), hs.tune_load(TUNE_FILE))
     ctx = hs.Context(p, device=0, stream=hs.current_stream())
     t0 = time.perf_counter()
     ctx.keygen(2002)
@@ -285,6 +295,14 @@ def main():
         out = ctx.softmax(cts, n, M, variant=variant)
         ctx.sync()
         _log("warmup %d: %.3fs %s" % (i, time.perf_counter() - t0, ctx.softmax_stats()))
+    if args.tune:
+        hs.tune_enable(False)
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        hs.tune_save(os.path.join(ROOT, "gpurun_out", "tune_gfx950.json"))
+    rep = hs.tune_report()
+    tuning = {"source": tune_src, "shapes": len(rep),
+              "choices": {c: sum(1 for r in rep if r["choice"] == c) for c in sorted({r["choice"] for r in rep})}}
+    _log("tuning: %s" % tuning)
     graph = None
     if not args.no_graph:
         # the whole Softmax schedule captured once as a HIP graph, replayed per step
@@ -416,6 +434,7 @@ def main():
         "client_encrypt_s": client_encrypt_s,
         "calls_per_s_including_client_encrypt": L / (ms_step * 1e-3 + client_encrypt_s),
         "schedule": "hip_graph" if graph else "eager",
+        "tuning": tuning,
         "graph": graph,
         "roofline": roofline,
         "kernel_time_ms": {k: round(v["ms"], 3) for k, v in prof.items()},

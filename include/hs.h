@@ -258,6 +258,30 @@ hs_status hs_softmax_plan_run(hs_softmax_plan* plan, hs_ct* const* in, size_t m,
 hs_status hs_softmax_plan_info(const hs_softmax_plan* plan, size_t* nodes, size_t* arena_bytes);
 void hs_softmax_plan_destroy(hs_softmax_plan* plan);
 
+/* Autotuner (not in the paper: an implementation choice).  Some operations
+ * have interchangeable kernels that give identical results: the base
+ * conversion of hybrid key switching (exact 128-bit VALU sums, or int8 byte
+ * planes on the matrix cores) and the N = 2^16 NTT (row order, launch
+ * batching over row groups).  While tuning is enabled (or HS_TUNE=1 in the
+ * environment), the first launch of each shape (N, sources, targets, row
+ * groups rounded up to a power of two) times every candidate on scratch
+ * data, rejects any whose output differs from the default kernel's, and keeps
+ * the fastest for the process; never during graph capture.  Decisions are
+ * process-wide and apply to every context.
+ * hs_tune_enable: on != 0 enables tuning of shapes not yet decided.
+ * hs_tune_clear: forgets every decision (the default kernels again).
+ * hs_tune_report: the decisions as text, one JSON object per line
+ * ({"key", "choice", "us": candidate times in microseconds, < 0 rejected});
+ * writes min(cap, size) bytes NUL-terminated and the full size + 1 to *used.
+ * hs_tune_save / hs_tune_load: write / read that text to / from a file;
+ * loaded decisions replace tuned ones of the same key (HS_E_ARG when the
+ * file cannot be opened). */
+hs_status hs_tune_enable(int on);
+hs_status hs_tune_clear(void);
+hs_status hs_tune_report(char* buf, size_t cap, size_t* used);
+hs_status hs_tune_save(const char* path);
+hs_status hs_tune_load(const char* path, int* entries);
+
 /* Packing of Section 4 (host only).  logits: [L][n] row-major, L n =
  * m (N/2); out: [m][slots] with ciphertext j holding coordinate
  * j (n/m) + c of Softmax l in slot c L + l.  Checks every logit is in

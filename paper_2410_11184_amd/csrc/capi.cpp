@@ -1,6 +1,8 @@
 // extern "C" entry points: argument checks, error capture, handle wrapping.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -759,6 +761,55 @@ hs_status hs_softmax_plan_info(const hs_softmax_plan* plan, size_t* nodes, size_
 }
 
 void hs_softmax_plan_destroy(hs_softmax_plan* plan) { delete plan; }
+
+// ------------------------------------------------------------- autotuner
+hs_status hs_tune_enable(int on) {
+    return guard([&] { hs::tune_enable(on != 0); });
+}
+
+hs_status hs_tune_clear(void) {
+    return guard([&] { hs::tune_clear(); });
+}
+
+hs_status hs_tune_report(char* buf, size_t cap, size_t* used) {
+    return guard([&] {
+        NEED(used);
+        const std::string s = hs::tune_dump();
+        *used = s.size() + 1;
+        if (buf && cap) {
+            const size_t n = std::min(cap - 1, s.size());
+            std::memcpy(buf, s.data(), n);
+            buf[n] = 0;
+        }
+    });
+}
+
+hs_status hs_tune_save(const char* path) {
+    return guard([&] {
+        NEED(path);
+        FILE* f = std::fopen(path, "w");
+        HS_REQUIRE(f != nullptr, hs::E_ARG, "cannot open the tuning file for writing");
+        const std::string s = hs::tune_dump();
+        const size_t w = std::fwrite(s.data(), 1, s.size(), f);
+        std::fclose(f);
+        HS_REQUIRE(w == s.size(), hs::E_ARG, "short write of the tuning file");
+    });
+}
+
+hs_status hs_tune_load(const char* path, int* entries) {
+    return guard([&] {
+        NEED(path);
+        FILE* f = std::fopen(path, "r");
+        HS_REQUIRE(f != nullptr, hs::E_ARG, "cannot open the tuning file");
+        std::string s;
+        char buf[4096];
+        size_t r;
+        while ((r = std::fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, r);
+        std::fclose(f);
+        const int n = hs::tune_load(s);
+        if (entries) *entries = n;
+    });
+}
 
 hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n) {
     return guard([&] {

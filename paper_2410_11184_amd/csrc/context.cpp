@@ -515,6 +515,43 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
     cd.t.k = k;
     cd.t.m = m;
     cd.t.centered = centered ? 1 : 0;
+    // byte-plane tables for the matrix-core kernel: the balanced base-256
+    // digits of v < 2^62 are the bytes of (v + c) xor c, c = 0x80..80, and the
+    // plane sums stay exact in int32 when targets are in [2^39, 2^62)
+    cd.t.bfrag = nullptr;
+    cd.t.c48 = cd.t.c48s = nullptr;
+    cd.t.nks = (k + 3) / 4;
+    cd.t.ntb = (m + 15) / 16;
+    bool planes_ok = k <= 16;
+    for (int i : src) planes_ok = planes_ok && c.primes[i] < (1ull << 62);
+    for (int t : dst) planes_ok = planes_ok && c.primes[t] >= (1ull << 39) && c.primes[t] < (1ull << 62);
+    if (planes_ok) {
+        const u64 bias = 0x8080808080808080ull;
+        const int nks = cd.t.nks, ntb = cd.t.ntb;
+        std::vector<u64> bf((size_t)ntb * nks * 8 * 64, 0);
+        for (int tb = 0; tb < ntb; tb++)
+            for (int ks = 0; ks < nks; ks++)
+                for (int lane = 0; lane < 64; lane++) {
+                    const int t = tb * 16 + (lane & 15), i = 4 * ks + (lane >> 4);
+                    if (t >= m || i >= k) continue;
+                    const u64 qt = c.primes[dst[t]];
+                    for (int a = 0; a < 8; a++) {
+                        const u64 H = mulmod_h(powmod_h(2, 8 * a, qt), hat[(size_t)i * m + t], qt);
+                        const u64 Hd = (H + bias) ^ bias;
+                        for (int b = 0; b < 8; b++)
+                            bf[((size_t)(tb * nks + ks) * 8 + b) * 64 + lane] |= ((Hd >> (8 * b)) & 0xff) << (8 * a);
+                    }
+                }
+        std::vector<u64> c48(m), c48s(m);
+        for (int t = 0; t < m; t++) {
+            const u64 qt = c.primes[dst[t]];
+            c48[t] = powmod_h(2, 48, qt);
+            c48s[t] = shoup_h(c48[t], qt);
+        }
+        cd.t.bfrag = (const u64*)put(bf.data(), bf.size() * 8);
+        cd.t.c48 = (const u64*)put(c48.data(), m * 8);
+        cd.t.c48s = (const u64*)put(c48s.data(), m * 8);
+    }
     return cd;
 }
 

@@ -1,6 +1,7 @@
 // Interface between the host runtime (built with g++) and the HIP kernels
 // (built with hipcc for gfx950): plain structs and launch wrappers.
 #pragma once
+#include <string>
 #include <cstdint>
 #include <cstddef>
 
@@ -82,7 +83,23 @@ struct ConvTables {
     int k;
     int m;
     int centered;           // 1: [x_i inv_hat_i] taken in (-d_i/2, d_i/2]
+    // byte-plane form for the matrix cores (null when a prime is out of its
+    // range): sources split into 8 signed base-256 digits, constants
+    // 2^(8a) [D/d_s]_t mod q_t likewise, one MFMA operand per lane
+    const u64* bfrag;       // [ntb][nks][8 planes][64 lanes]
+    const u64* c48;         // [m] 2^48 mod q_t
+    const u64* c48s;        // [m] Shoup companions
+    int nks;                // ceil(k / 4): 32-deep MFMA steps (four sources)
+    int ntb;                // ceil(m / 16): 16-target blocks
 };
+
+// Autotuner over interchangeable kernel variants (base conversion: VALU or
+// matrix cores; N = 2^16 NTT: row order and launch batching).  Off unless
+// enabled (or HS_TUNE=1); decisions are process-wide.
+void tune_enable(bool on);
+void tune_clear();                       // forget every decision (defaults again)
+std::string tune_dump();                 // one JSON object per line
+int tune_load(const std::string& text);  // entries taken
 
 // ------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` (a hipStream_t).

@@ -8,6 +8,12 @@
 // values fully reduced in [0, q) at their boundaries.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "dev.h"
@@ -87,6 +93,10 @@ struct ProfScope {
         }
     }
 };
+
+// autotuner decisions (defined with the tuner below)
+int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st);
+int tune_conv(const DevTables& T, const ConvTables& C, size_t og, size_t ig, int ngroups, hipStream_t st);
 
 // ------------------------------------------------------------- arithmetic
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
@@ -347,6 +357,11 @@ __device__ __forceinline__ int ntt_row_prime_major(const Rows& x, int y) {
     return g * x.rpg + y / x.ngroups;
 }
 
+// row visited by workgroup row y: prime-major (order 0) or in storage order (1)
+__device__ __forceinline__ int ntt_row(const Rows& x, int y, int order) {
+    return order ? y : ntt_row_prime_major(x, y);
+}
+
 // Lazy (Harvey) butterflies: a*w - floor(a*ws/2^64)*q lies in [0, 2q) for
 // any a < 2^64, so forward values are kept in [0, 4q) and inverse values in
 // [0, 2q) (4q < 2^63 for q < 2^61) and reduced once at the end of the
@@ -417,9 +432,9 @@ __device__ __forceinline__ u64 reduce4q(u64 x, u64 q) {
 // pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
 #define NTT16_LDS (16 * 272)
 
-__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse) {
+__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order) {
     __shared__ u64 sm[NTT16_LDS];
-    const int row = ntt_row_prime_major(x, blockIdx.y);
+    const int row = ntt_row(x, blockIdx.y, order);
     u64* p = row_ptr(x, row, 65536) + blockIdx.x * 16;
     const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * 16;
     const int pi = prime_of(x, row % x.rpg);
@@ -460,9 +475,9 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
     }
 }
 
-__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse) {
+__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order) {
     __shared__ u64 sm[NTT16_LDS];
-    const int row = ntt_row_prime_major(x, blockIdx.y);
+    const int row = ntt_row(x, blockIdx.y, order);
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
     const int t = threadIdx.x, w = t >> 4, l = t & 15;
@@ -511,23 +526,41 @@ __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows
 
 void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) { k_ntt_from(T, x, x, inverse, stream); }
 
+// N = 2^16 transform of x (first pass reading src) in one of the tuner's
+// variants: variant & 1 selects the row order (prime-major / storage order),
+// variant & 2 splits the launch into batches of kNttGroupBatch row groups.
+constexpr int kNttGroupBatch = 8;
+static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, bool inverse, int variant,
+                         hipStream_t st) {
+    const int order = variant & 1;
+    const int gb = (variant & 2) ? kNttGroupBatch : x.ngroups;
+    for (int g0 = 0; g0 < x.ngroups; g0 += gb) {
+        Rows xs = x, ss = src;
+        xs.base = x.base + (size_t)g0 * x.gstride;
+        ss.base = src.base + (size_t)g0 * src.gstride;
+        xs.ngroups = ss.ngroups = std::min(gb, x.ngroups - g0);
+        const dim3 g(16, xs.ngroups * xs.rpg);
+        if (!inverse) {
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order);
+            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, xs, xs, 0, order);
+        } else {
+            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, xs, ss, 1, order);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order);
+        }
+    }
+}
+
 void k_ntt_from(const DevTables& T, const Rows& x, const Rows& src, bool inverse, void* stream) {
     const int nrows = x.ngroups * x.rpg;
     if (nrows == 0) return;
-    ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
     hipStream_t st = (hipStream_t)stream;
     if (T.logN == 16) {
-        // the first pass reads src, the second works in place on x
-        const dim3 g(16, nrows);
-        if (!inverse) {
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, src, 0);
-            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, x, 0);
-        } else {
-            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, x, src, 1);
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, x, x, 1);
-        }
+        const int variant = tune_ntt16(T, x, inverse, st);
+        ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
+        ntt16_launch(T, x, src, inverse, variant, st);
         return;
     }
+    ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
     if (src.base != x.base || src.gstride != x.gstride) k_copy_rows(T, x, src, stream);
     if (T.N <= 4096) {
         hipLaunchKernelGGL(ntt_small_kernel, dim3(nrows), dim3(256), T.N * sizeof(u64), st, T, x,
@@ -804,6 +837,119 @@ __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTabl
     }
 }
 
+// Matrix-core form.  With x = sum_a d_a 256^a (balanced digits d_a in
+// [-128, 127], read off as the bytes of (x + c) xor c, c = 0x80..80) and the
+// constants H_(s,a),t = 2^(8a) [D/d_s]_t mod q_t split the same way into
+// planes h_b, the int8 products C_b,t = sum_(s,a) d_(s,a) h_(s,a),t,b
+// (|C| < 2^21) give V = sum_b C_b 2^(8b), congruent to sum_s xh_s [D/d_s]_t
+// modulo q_t, so the reduced result is the VALU kernel's exactly.  One wave
+// takes 16 coefficients per tile: A = 16 x 32 digits (four sources per MFMA
+// step), B = 32 x 16 targets per plane, eight 16 x 16 int32 accumulators;
+// every lane then folds the planes of 4 outputs.
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int kConvTiles = 8;            // 16-coefficient tiles per wave
+constexpr u64 kDigitBias = 0x8080808080808080ull;
+constexpr int kConvPlaneLds = 56 * 1024; // bytes of B operands one workgroup stages
+
+template <int KS>
+__global__ void __launch_bounds__(256) base_convert_mfma_kernel(DevTables T, ConvTables C, u64* out, size_t og,
+                                                                const u64* in, size_t ig) {
+    extern __shared__ u64 sB[];          // [ntb][KS][8][64]
+    __shared__ u64 s_q[kMaxConvDst], s_mu[kMaxConvDst], s_c48[kMaxConvDst], s_c48s[kMaxConvDst],
+        s_dmod[kMaxConvDst];
+    __shared__ int s_bits[kMaxConvDst], s_row[kMaxConvDst];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int quad = lane >> 4, col = lane & 15;
+    const int g = blockIdx.y;
+    const int N = T.N;
+    const int m = C.m, ntb = C.ntb;
+    for (int e = threadIdx.x; e < ntb * KS * 8 * 64; e += blockDim.x) sB[e] = C.bfrag[e];
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        const PrimeInfo P = T.prime[C.dst_prime[t]];
+        s_q[t] = P.q;
+        s_mu[t] = P.mu;
+        s_bits[t] = P.bits;
+        s_c48[t] = C.c48[t];
+        s_c48s[t] = C.c48s[t];
+        s_dmod[t] = C.dmod[t];
+        s_row[t] = C.dst_row[t];
+    }
+    __syncthreads();
+    for (int tile = 0; tile < kConvTiles; tile++) {
+        const int base = ((blockIdx.x * 4 + wave) * kConvTiles + tile) * 16;
+        if (base >= N) break;   // whole wave
+        // A operand: coefficient base + col, sources 4 ks + quad
+        long afr[KS];
+        int neg = 0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) {
+            const int s = 4 * ks + quad;
+            u64 x = 0;
+            if (s < C.k) {
+                const u64 v = in[(size_t)g * ig + (size_t)C.src_row[s] * N + base + col];
+                const u64 d = T.prime[C.src_prime[s]].q;
+                x = mul_shoup(v, C.inv_hat[s], C.inv_hat_s[s], d);
+                if (C.centered && x > (d - 1) / 2) neg++;
+            }
+            afr[ks] = (long)((x + kDigitBias) ^ kDigitBias);
+        }
+        int nneg[4] = {0, 0, 0, 0};
+        if (C.centered) {
+            neg += __shfl_xor(neg, 16);
+            neg += __shfl_xor(neg, 32);
+#pragma unroll
+            for (int r = 0; r < 4; r++) nneg[r] = __shfl(neg, 4 * quad + r);
+        }
+        for (int tb = 0; tb < ntb; tb++) {
+            v4i acc[8];
+#pragma unroll
+            for (int b = 0; b < 8; b++) acc[b] = v4i{0, 0, 0, 0};
+            const u64* bt = sB + (size_t)tb * KS * 8 * 64;
+#pragma unroll
+            for (int ks = 0; ks < KS; ks++)
+#pragma unroll
+                for (int b = 0; b < 8; b++)
+                    acc[b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(afr[ks], (long)bt[(ks * 8 + b) * 64 + lane],
+                                                                   acc[b], 0, 0, 0);
+            const int t = tb * 16 + col;
+            if (t >= m) continue;
+            PrimeInfo P;
+            P.q = s_q[t];
+            P.mu = s_mu[t];
+            P.bits = s_bits[t];
+            const u64 c48 = s_c48[t], c48s = s_c48s[t];
+            u64* o = out + (size_t)g * og + (size_t)s_row[t] * N + base + 4 * quad;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int p0 = acc[0][r] + acc[1][r] * 256;
+                const int p1 = acc[2][r] + acc[3][r] * 256;
+                const int p2 = acc[4][r] + acc[5][r] * 256;
+                const int p3 = acc[6][r] + acc[7][r] * 256;
+                const int64_t X = (int64_t)p0 + (int64_t)p1 * 65536 + (int64_t)p2 * 4294967296ll;
+                u64 rx = reduce64(X < 0 ? (u64)(-X) : (u64)X, P);
+                if (X < 0 && rx) rx = P.q - rx;
+                const u64 p3m = p3 < 0 ? P.q - (u64)(-(int64_t)p3) : (u64)p3;
+                u64 res = add_mod(rx, mul_shoup(p3m, c48, c48s, P.q), P.q);
+                for (int k = 0; k < nneg[r]; k++) res = sub_mod(res, s_dmod[t], P.q);
+                o[r] = res;
+            }
+        }
+    }
+}
+
+template <int KS>
+static void launch_base_convert_mfma(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in,
+                                     size_t ig, int ngroups, hipStream_t st) {
+    if (C.nks == KS) {
+        const int per_block = 4 * kConvTiles * 16;
+        const size_t lds = (size_t)C.ntb * KS * 8 * 64 * sizeof(u64);
+        hipLaunchKernelGGL(base_convert_mfma_kernel<KS>, dim3((T.N + per_block - 1) / per_block, ngroups),
+                           dim3(256), lds, st, T, C, out, og, in, ig);
+    } else if constexpr (KS < kMaxConvSrc / 4) {
+        launch_base_convert_mfma<KS + 1>(T, C, out, og, in, ig, ngroups, st);
+    }
+}
+
 template <int K>
 static void launch_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in,
                                 size_t ig, int ngroups, hipStream_t st) {
@@ -814,12 +960,248 @@ static void launch_base_convert(const DevTables& T, const ConvTables& C, u64* ou
         launch_base_convert<K + 1>(T, C, out, og, in, ig, ngroups, st);
 }
 
+static bool conv_planes_fit(const DevTables& T, const ConvTables& C) {
+    return C.bfrag && T.N % 16 == 0 && (size_t)C.ntb * C.nks * 8 * 64 * sizeof(u64) <= (size_t)kConvPlaneLds;
+}
+
+// variant 0: VALU kernel; 1: matrix-core kernel (when its tables exist)
+static void conv_launch(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in, size_t ig,
+                        int ngroups, int variant, hipStream_t st) {
+    if (variant == 1 && conv_planes_fit(T, C))
+        launch_base_convert_mfma<1>(T, C, out, og, in, ig, ngroups, st);
+    else
+        launch_base_convert<1>(T, C, out, og, in, ig, ngroups, st);
+}
+
+// ------------------------------------------------------------- autotuner
+// Interchangeable implementations of one operation (identical results) are
+// timed on scratch data of the launch's shape the first time the shape is
+// met while tuning is enabled, outside graph capture; the fastest is kept
+// for the process (and can be saved and loaded).  A candidate whose output
+// differs from the default's in any word is rejected.
+namespace {
+struct TuneEntry {
+    int choice = 0;
+    std::vector<std::string> names;
+    std::vector<double> us;      // best time per candidate (microseconds), < 0: rejected
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+int g_tune_on = -1;
+
+bool tuning_on() {
+    if (g_tune_on < 0) {
+        const char* e = std::getenv("HS_TUNE");
+        g_tune_on = (e && std::string(e) == "1") ? 1 : 0;
+    }
+    return g_tune_on == 1;
+}
+
+__global__ void tune_fill_kernel(u64* p, size_t n, u64 seed) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u64 z = (i + 1) * 0x9E3779B97F4A7C15ull + seed;    // SplitMix64 finaliser
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    p[i] = (z ^ (z >> 31)) & ((1ull << 39) - 1);        // below every prime
+}
+
+__global__ void tune_diff_kernel(const u64* a, const u64* b, size_t n, unsigned* bad) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && a[i] != b[i]) atomicAdd(bad, 1u);
+}
+
+void tune_fill(u64* p, size_t n, u64 seed, hipStream_t st) {
+    if (n) hipLaunchKernelGGL(tune_fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, seed);
+}
+
+// Times `launch(c, in, out)` for every candidate; in-place candidates
+// (out == in) get the input restored before each run.
+int tune_run(const std::string& key, const std::vector<std::string>& names, const std::vector<bool>& ok,
+             size_t in_words, size_t out_words, bool inplace, hipStream_t st,
+             const std::function<void(int, const u64*, u64*)>& launch) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
+    if (hipStreamSynchronize(st) != hipSuccess) return 0;
+    u64 *in = nullptr, *pristine = nullptr, *out = nullptr, *ref = nullptr;
+    unsigned* bad = nullptr;
+    auto cleanup = [&] {
+        (void)hipStreamSynchronize(st);
+        for (void* p : {(void*)in, (void*)pristine, (void*)out, (void*)ref, (void*)bad})
+            if (p) (void)hipFree(p);
+    };
+    const size_t ow = inplace ? in_words : out_words;
+    if (hipMalloc(&in, in_words * 8) != hipSuccess || hipMalloc(&ref, ow * 8) != hipSuccess ||
+        hipMalloc(&bad, sizeof(unsigned)) != hipSuccess ||
+        (inplace ? hipMalloc(&pristine, in_words * 8) : hipMalloc(&out, out_words * 8)) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return 0;    // no room to tune: keep the default
+    }
+    tune_fill(in, in_words, 0x5eed, st);
+    if (inplace) (void)hipMemcpyAsync(pristine, in, in_words * 8, hipMemcpyDeviceToDevice, st);
+    u64* dst = inplace ? in : out;
+    auto prepare = [&] {
+        if (inplace) (void)hipMemcpyAsync(in, pristine, in_words * 8, hipMemcpyDeviceToDevice, st);
+        else tune_fill(out, out_words, 0, st);
+    };
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    TuneEntry E;
+    E.names = names;
+    E.us.assign(names.size(), -1.0);
+    for (size_t c = 0; c < names.size(); c++) {
+        if (!ok[c]) continue;
+        double best = 1e30;
+        for (int rep = 0; rep < 4; rep++) {
+            prepare();
+            (void)hipEventRecord(e0, st);
+            launch((int)c, in, dst);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) best = std::min(best, 1e3 * ms);    // the first run warms caches
+        }
+        if (c == 0) {
+            (void)hipMemcpyAsync(ref, dst, ow * 8, hipMemcpyDeviceToDevice, st);
+        } else {
+            unsigned nb = 0;
+            (void)hipMemsetAsync(bad, 0, sizeof(unsigned), st);
+            hipLaunchKernelGGL(tune_diff_kernel, dim3((unsigned)((ow + 255) / 256)), dim3(256), 0, st, dst, ref, ow,
+                               bad);
+            (void)hipMemcpyAsync(&nb, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+            (void)hipStreamSynchronize(st);
+            if (nb) continue;    // not interchangeable: rejected
+        }
+        E.us[c] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cleanup();
+    for (size_t c = 0; c < names.size(); c++)
+        if (E.us[c] >= 0 && (E.us[E.choice] < 0 || E.us[c] < E.us[E.choice])) E.choice = (int)c;
+    if (std::getenv("HS_TRACE")) {
+        std::fprintf(stderr, "[hs] tune %s:", key.c_str());
+        for (size_t c = 0; c < names.size(); c++) std::fprintf(stderr, " %s=%.1fus", names[c].c_str(), E.us[c]);
+        std::fprintf(stderr, " -> %s\n", names[E.choice].c_str());
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = E;
+    return E.choice;
+}
+
+// decided variant for `key`, or -1 when the shape has not been tuned
+int tune_lookup(const std::string& key) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? -1 : it->second.choice;
+}
+
+int pow2_bucket(int x) {
+    int b = 1;
+    while (b < x) b <<= 1;
+    return b;
+}
+}  // namespace
+
+int tune_conv(const DevTables& T, const ConvTables& C, size_t og, size_t ig, int ngroups, hipStream_t st) {
+    const std::string key = "conv N=" + std::to_string(T.N) + " k=" + std::to_string(C.k) + " m=" +
+                            std::to_string(C.m) + " groups=" + std::to_string(pow2_bucket(ngroups)) +
+                            (C.centered ? " centred" : "");
+    const int v = tune_lookup(key);
+    if (v >= 0 || !tuning_on()) return v < 0 ? 0 : v;
+    const int gq = pow2_bucket(ngroups);
+    return tune_run(key, {"valu", "mfma"}, {true, conv_planes_fit(T, C)}, (size_t)gq * ig, (size_t)gq * og, false,
+                    st, [&](int c, const u64* in, u64* out) { conv_launch(T, C, out, og, in, ig, gq, c, st); });
+}
+
+int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st) {
+    const int gq = pow2_bucket(x.ngroups);
+    const std::string key = "ntt N=" + std::to_string(T.N) + " rows=" + std::to_string(x.rpg) + " groups=" +
+                            std::to_string(gq) + (inverse ? " inverse" : " forward");
+    const int v = tune_lookup(key);
+    if (v >= 0 || !tuning_on()) return v < 0 ? 0 : v;
+    const size_t words = (size_t)gq * x.rpg * T.N;
+    return tune_run(key, {"prime-major", "storage-order", "prime-major/batched", "storage-order/batched"},
+                    {true, true, gq > kNttGroupBatch, gq > kNttGroupBatch}, words, 0, true, st,
+                    [&](int c, const u64*, u64* buf) {
+                        Rows r = x;
+                        r.base = buf;
+                        r.gstride = (size_t)x.rpg * T.N;
+                        r.ngroups = gq;
+                        ntt16_launch(T, r, r, inverse, c, st);
+                    });
+}
+
+void tune_enable(bool on) { g_tune_on = on ? 1 : 0; }
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+// one entry per line: {"key": "...", "choice": "...", "us": {"name": t, ...}}
+std::string tune_dump() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::string s;
+    char buf[64];
+    for (auto& kv : g_tune) {
+        s += "{\"key\": \"" + kv.first + "\", \"choice\": \"" + kv.second.names[kv.second.choice] + "\", \"us\": {";
+        for (size_t c = 0; c < kv.second.names.size(); c++) {
+            std::snprintf(buf, sizeof(buf), "%.2f", kv.second.us[c]);
+            s += (c ? ", \"" : "\"") + kv.second.names[c] + "\": " + buf;
+        }
+        s += "}}\n";
+    }
+    return s;
+}
+
+// reads lines written by tune_dump; returns the number of entries taken
+int tune_load(const std::string& text) {
+    int n = 0;
+    size_t pos = 0;
+    while (pos < text.size()) {
+        size_t eol = text.find('\n', pos);
+        if (eol == std::string::npos) eol = text.size();
+        const std::string line = text.substr(pos, eol - pos);
+        pos = eol + 1;
+        auto field = [&](const std::string& name) -> std::string {
+            const std::string tag = "\"" + name + "\": \"";
+            size_t a = line.find(tag);
+            if (a == std::string::npos) return "";
+            a += tag.size();
+            size_t b = line.find('"', a);
+            return b == std::string::npos ? "" : line.substr(a, b - a);
+        };
+        const std::string key = field("key"), choice = field("choice");
+        if (key.empty() || choice.empty()) continue;
+        std::vector<std::string> names;
+        if (key.rfind("conv", 0) == 0) names = {"valu", "mfma"};
+        else if (key.rfind("ntt", 0) == 0)
+            names = {"prime-major", "storage-order", "prime-major/batched", "storage-order/batched"};
+        TuneEntry E;
+        E.names = names;
+        E.us.assign(names.size(), -1.0);
+        E.choice = -1;
+        for (size_t c = 0; c < names.size(); c++)
+            if (names[c] == choice) E.choice = (int)c;
+        if (E.choice < 0) continue;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = E;
+        n++;
+    }
+    return n;
+}
+
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride, const u64* in,
                     size_t in_gstride, int ngroups, void* stream) {
     if (ngroups == 0 || C.m == 0) return;
     if (C.k < 1 || C.k > kMaxConvSrc || C.m > kMaxConvDst) return;  // tables are checked when built
+    const int variant = tune_conv(T, C, out_gstride, in_gstride, ngroups, (hipStream_t)stream);
     ProfScope ps(T.prof, PK_CONV, 8.0 * T.N * ngroups * (double)(C.k + C.m), stream);
-    launch_base_convert<1>(T, C, out, out_gstride, in, in_gstride, ngroups, (hipStream_t)stream);
+    conv_launch(T, C, out, out_gstride, in, in_gstride, ngroups, variant, (hipStream_t)stream);
 }
 
 // centred lift: v = x if x <= (q_s - 1)/2 else x - q_s, reduced mod each row's prime

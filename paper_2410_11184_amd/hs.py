@@ -123,6 +123,11 @@ def lib():
                                    ctypes.c_double, ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_plan_run": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp)],
         "hs_softmax_plan_info": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+        "hs_tune_enable": [S],
+        "hs_tune_clear": [],
+        "hs_tune_report": [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "hs_tune_save": [ctypes.c_char_p],
+        "hs_tune_load": [ctypes.c_char_p, ctypes.POINTER(S)],
         "hs_pack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double, _vp,
                             ctypes.POINTER(ctypes.c_size_t)],
         "hs_unpack_softmax": [_f64p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_size_t, _f64p],
@@ -199,6 +204,36 @@ class Ciphertext:
         _check(lib().hs_ct_export(self.ctx.h, self.h, out, out.size, ctypes.byref(used)))
         lv, nc, _ = self.info
         return out.reshape(nc, lv + 1, -1)
+
+
+def tune_enable(on=True):
+    """hs_tune_enable: time interchangeable kernels on the first launch of each shape."""
+    _check(lib().hs_tune_enable(1 if on else 0))
+
+
+def tune_clear():
+    """hs_tune_clear: forget every decision (default kernels again)."""
+    _check(lib().hs_tune_clear())
+
+
+def tune_report():
+    """Autotuner decisions: list of dicts {key, choice, us}."""
+    import json
+    used = ctypes.c_size_t()
+    _check(lib().hs_tune_report(None, 0, ctypes.byref(used)))
+    buf = ctypes.create_string_buffer(used.value)
+    _check(lib().hs_tune_report(buf, used.value, ctypes.byref(used)))
+    return [json.loads(l) for l in buf.value.decode().splitlines() if l.strip()]
+
+
+def tune_save(path):
+    _check(lib().hs_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    n = ctypes.c_int()
+    _check(lib().hs_tune_load(str(path).encode(), ctypes.byref(n)))
+    return n.value
 
 
 class SoftmaxPlan:

@@ -57,3 +57,25 @@ def test_last_error_is_thread_local_string():
     st = L.hs_pack_softmax(np.zeros(4), 1, 3, 8, 1.0, None, ctypes.byref(ctypes.c_size_t()))
     assert st == -2
     assert b"power of two" in L.hs_last_error()
+
+
+def test_tune_decisions_round_trip(tmp_path):
+    # host-only: decisions are text; unknown kernels or choices are skipped
+    from paper_2410_11184_amd import hs
+    hs.tune_clear()
+    f = tmp_path / "decisions.json"
+    f.write_text('{"key": "conv N=4096 k=2 m=24 groups=8", "choice": "mfma", "us": {}}\n'
+                 '{"key": "ntt N=65536 rows=13 groups=64 forward", "choice": "storage-order", "us": {}}\n'
+                 '{"key": "ntt N=65536 rows=13 groups=64 inverse", "choice": "no-such-variant"}\n'
+                 '{"key": "other N=1", "choice": "valu"}\n')
+    assert hs.tune_load(f) == 2
+    got = {r["key"]: r["choice"] for r in hs.tune_report()}
+    assert got == {"conv N=4096 k=2 m=24 groups=8": "mfma", "ntt N=65536 rows=13 groups=64 forward": "storage-order"}
+    g = tmp_path / "saved.json"
+    hs.tune_save(g)
+    hs.tune_clear()
+    assert hs.tune_report() == []
+    assert hs.tune_load(g) == 2
+    hs.tune_clear()
+    with pytest.raises(hs.HSError):
+        hs.tune_load(tmp_path / "missing.json")
