@@ -465,7 +465,8 @@ CtHandle::~CtHandle() {
 
 // ------------------------------------------------- base-conversion tables
 static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vector<int>& src_row,
-                         const std::vector<int>& dst, const std::vector<int>& dst_row, bool centered) {
+                         const std::vector<int>& dst, const std::vector<int>& dst_row, bool centered,
+                         const std::vector<int>& own_row = {}) {
     const int k = (int)src.size(), m = (int)dst.size();
     // the conversion kernel holds k sources in registers and m targets in LDS
     HS_REQUIRE(k >= 1 && k <= 16 && m <= kMaxRows, E_PARAM, "base conversion shape out of range");
@@ -501,6 +502,11 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
     cd.t.dst_prime = (const int*)put(dst.data(), m * 4);
     cd.t.src_row = (const int*)put(src_row.data(), k * 4);
     cd.t.dst_row = (const int*)put(dst_row.data(), m * 4);
+    cd.t.own_row = nullptr;
+    if (!own_row.empty()) {
+        HS_REQUIRE((int)own_row.size() == k, E_PARAM, "one own row per source");
+        cd.t.own_row = (const int*)put(own_row.data(), k * 4);
+    }
     std::vector<u64> dmod(m);
     for (int t = 0; t < m; t++) {
         const u64 qt = c.primes[dst[t]];
@@ -579,7 +585,8 @@ const ConvDev& Context::modup_tables(int level, int j) {
         drow.push_back(level + 1 + k);
     }
     HS_REQUIRE((int)src.size() <= 16, E_PARAM, "digit too large");
-    return modup.emplace(key, make_conv(*this, src, srow, dst, drow, false)).first->second;
+    // the digit's own rows go to the same rows of the extended layout unchanged
+    return modup.emplace(key, make_conv(*this, src, srow, dst, drow, false, srow)).first->second;
 }
 
 // ModDown at level l: sources are P (rows l+1.. of the extended layout),

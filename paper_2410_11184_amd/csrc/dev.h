@@ -78,6 +78,7 @@ struct ConvTables {
     const int* dst_prime;   // [m]
     const int* src_row;     // [k] row offsets (within the input group)
     const int* dst_row;     // [m] row offsets (within the output group)
+    const int* own_row;     // [k] output row that receives source s unchanged, or -1 (null: none)
     const u64* dmod;        // [m]  D mod q_t (centred conversion only)
     const u64* r64;         // [m]  2^64 mod q_t
     int k;

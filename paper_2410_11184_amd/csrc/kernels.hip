@@ -778,7 +778,8 @@ void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* p
 
 // --------------------------------------------------------- base conversion
 // One thread per coefficient, K (the number of source primes) a template
-// argument so the lifted sources stay in registers; the conversion constants
+// argument so the lifted sources stay in registers (a source row may also be
+// copied unchanged to an output row: ModUp's own digit rows); the conversion constants
 // (K x m products [D/d_s]_t and the target primes) are staged in LDS once per
 // workgroup and read as broadcasts inside the product loop.
 constexpr int kMaxConvSrc = 16;
@@ -811,6 +812,7 @@ __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTabl
 #pragma unroll
     for (int s = 0; s < K; s++) {
         const u64 x = in[(size_t)g * ig + (size_t)C.src_row[s] * N + i];
+        if (C.own_row && C.own_row[s] >= 0) out[(size_t)g * og + (size_t)C.own_row[s] * N + i] = x;
         const u64 d = T.prime[C.src_prime[s]].q;
         xh[s] = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
         // centred: xh - d_s contributes xh * hat - D
@@ -887,6 +889,7 @@ __global__ void __launch_bounds__(256) base_convert_mfma_kernel(DevTables T, Con
             u64 x = 0;
             if (s < C.k) {
                 const u64 v = in[(size_t)g * ig + (size_t)C.src_row[s] * N + base + col];
+                if (C.own_row && C.own_row[s] >= 0) out[(size_t)g * og + (size_t)C.own_row[s] * N + base + col] = v;
                 const u64 d = T.prime[C.src_prime[s]].q;
                 x = mul_shoup(v, C.inv_hat[s], C.inv_hat_s[s], d);
                 if (C.centered && x > (d - 1) / 2) neg++;

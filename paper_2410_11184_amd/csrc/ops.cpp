@@ -128,8 +128,7 @@ Ct op_rescale(Context& c, const Ct& a) {
     u64* lifted = c.alloc_words((size_t)np_ * l * N);
     Rows in_last{a.d + (size_t)l * N, np_, 1, (size_t)(l + 1) * N, 1, l, c.nq};
     Rows r_last{last, np_, 1, N, 1, l, c.nq};
-    k_copy_rows(c.T, r_last, in_last, c.stream);
-    k_ntt(c.T, r_last, true, c.stream);
+    k_ntt_from(c.T, r_last, in_last, true, c.stream);
     Rows r_lift{lifted, np_, l, (size_t)l * N, l, 0, c.nq};
     k_lift_centered(c.T, r_lift, last, N, l, c.stream);
     k_ntt(c.T, r_lift, false, c.stream);
@@ -226,13 +225,11 @@ static u64* ks_modup(Context& c, const Rows& d, int level) {
     u64* ext = c.alloc_words((size_t)m * beta * E * N);
     const size_t xg = (size_t)beta * E * N;
     for (int j = 0; j < beta; j++) {
-        const int lo = j * c.prm.digit, hi = std::min((j + 1) * c.prm.digit, nql);
+        // every row of digit j's extension: the conversion writes the other
+        // primes and copies the digit's own rows
         u64* xj = ext + (size_t)j * E * N;
         const ConvDev& cv = c.modup_tables(l, j);
         k_base_convert(c.T, cv.t, xj, xg, dc, (size_t)nql * N, m, c.stream);
-        Rows own_out{xj + (size_t)lo * N, m, hi - lo, xg, hi - lo, lo, c.nq};
-        Rows own_in{dc + (size_t)lo * N, m, hi - lo, (size_t)nql * N, hi - lo, lo, c.nq};
-        k_copy_rows(c.T, own_out, own_in, c.stream);
     }
     c.free_words(dc);
     // one launch for every row of every digit (the digit's own rows come
@@ -398,8 +395,7 @@ Ct op_mod_raise(Context& c, const Ct& a, int level) {
     k_copy_rows(c.T, r0, c.ct_rows(a), c.stream);
     u64* coef = c.alloc_words((size_t)np_ * N);
     Rows rc{coef, np_, 1, N, 1, 0, c.nq};
-    k_copy_rows(c.T, rc, c.ct_rows(a), c.stream);
-    k_ntt(c.T, rc, true, c.stream);
+    k_ntt_from(c.T, rc, c.ct_rows(a), true, c.stream);
     Rows up{o.d + N, np_, level, (size_t)(level + 1) * N, level, 1, c.nq};
     k_lift_centered(c.T, up, coef, N, 0, c.stream);
     k_ntt(c.T, up, false, c.stream);
