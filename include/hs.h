@@ -260,9 +260,10 @@ void hs_softmax_plan_destroy(hs_softmax_plan* plan);
 
 /* Autotuner (not in the paper: an implementation choice).  Some operations
  * have interchangeable kernels that give identical results: the base
- * conversion of hybrid key switching (exact 128-bit VALU sums, or int8 byte
- * planes on the matrix cores) and the N = 2^16 NTT (row order, launch
- * batching over row groups).  While tuning is enabled (or HS_TUNE=1 in the
+ * conversion of hybrid key switching (exact 128-bit VALU sums with the
+ * targets on 1, 2 or 4 threads per coefficient, or int8 byte planes on the
+ * matrix cores) and the N = 2^16 NTT (row order, launch batching over row
+ * groups).  While tuning is enabled (or HS_TUNE=1 in the
  * environment), the first launch of each shape (N, sources, targets, row
  * groups rounded up to a power of two) times every candidate on scratch
  * data, rejects any whose output differs from the default kernel's, and keeps

@@ -515,9 +515,16 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
         dmod[t] = g;
     }
     cd.t.dmod = (const u64*)put(dmod.data(), m * 8);
-    std::vector<u64> r64(m);
-    for (int t = 0; t < m; t++) r64[t] = (u64)(((u128)1 << 64) % c.primes[dst[t]]);
+    std::vector<u64> r64(m), r64s(m), ones(m);
+    for (int t = 0; t < m; t++) {
+        const u64 qt = c.primes[dst[t]];
+        r64[t] = (u64)(((u128)1 << 64) % qt);
+        r64s[t] = shoup_h(r64[t], qt);
+        ones[t] = shoup_h(1, qt);
+    }
     cd.t.r64 = (const u64*)put(r64.data(), m * 8);
+    cd.t.r64s = (const u64*)put(r64s.data(), m * 8);
+    cd.t.ones = (const u64*)put(ones.data(), m * 8);
     cd.t.k = k;
     cd.t.m = m;
     cd.t.centered = centered ? 1 : 0;

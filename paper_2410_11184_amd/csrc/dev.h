@@ -81,6 +81,8 @@ struct ConvTables {
     const int* own_row;     // [k] output row that receives source s unchanged, or -1 (null: none)
     const u64* dmod;        // [m]  D mod q_t (centred conversion only)
     const u64* r64;         // [m]  2^64 mod q_t
+    const u64* r64s;        // [m]  Shoup companion of r64
+    const u64* ones;        // [m]  floor(2^64 / q_t): Shoup companion of 1
     int k;
     int m;
     int centered;           // 1: [x_i inv_hat_i] taken in (-d_i/2, d_i/2]

@@ -785,20 +785,59 @@ void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* p
 constexpr int kMaxConvSrc = 16;
 constexpr int kMaxConvDst = 64;
 
+// Products without carries: x_s = x1 2^32 + x0 (x1 < 2^30) and the constant
+// [D/d_s]_t = h2 2^42 + h1 2^21 + h0 (21-bit limbs), so each of the six
+// partial sums S_ij = sum_s x_i h_j stays below 2^57 for K <= 16 and is one
+// v_mad_u64_u32 per product; the exact 128-bit sum is then
+// sum_ij S_ij 2^(32 i + 21 j).  Targets below 2^42 have h2 = 0 and skip two.
+template <int K, bool WIDE>
+__device__ __forceinline__ unsigned __int128 conv_sum(const u32 (&x0)[K], const u32 (&x1)[K], const u64* hl,
+                                                      const u32* h2, int m, int t) {
+    u64 s00 = 0, s01 = 0, s02 = 0, s10 = 0, s11 = 0, s12 = 0;
+#pragma unroll
+    for (int s = 0; s < K; s++) {
+        const u64 h = hl[s * m + t];
+        const u32 a = (u32)h, b = (u32)(h >> 32);
+        s00 += (u64)x0[s] * a;
+        s01 += (u64)x0[s] * b;
+        s10 += (u64)x1[s] * a;
+        s11 += (u64)x1[s] * b;
+        if (WIDE) {
+            const u32 c = h2[s * m + t];
+            s02 += (u64)x0[s] * c;
+            s12 += (u64)x1[s] * c;
+        }
+    }
+    unsigned __int128 v = s00;
+    v += (unsigned __int128)s01 << 21;
+    v += (unsigned __int128)s10 << 32;
+    v += (unsigned __int128)s11 << 53;
+    if (WIDE) {
+        v += (unsigned __int128)s02 << 42;
+        v += (unsigned __int128)s12 << 74;
+    }
+    return v;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t og,
                                                            const u64* in, size_t ig) {
-    __shared__ u64 s_hat[K * kMaxConvDst];
-    __shared__ u64 s_q[kMaxConvDst], s_mu[kMaxConvDst], s_r64[kMaxConvDst], s_dmod[kMaxConvDst];
-    __shared__ int s_bits[kMaxConvDst], s_row[kMaxConvDst];
+    __shared__ u64 s_hl[K * kMaxConvDst];        // (h1 << 32) | h0
+    __shared__ u32 s_h2[K * kMaxConvDst];
+    __shared__ u64 s_q[kMaxConvDst], s_r64[kMaxConvDst], s_r64s[kMaxConvDst], s_one[kMaxConvDst],
+        s_dmod[kMaxConvDst];
+    __shared__ int s_row[kMaxConvDst];
     const int m = C.m;
-    for (int e = threadIdx.x; e < K * m; e += blockDim.x) s_hat[e] = C.hat[e];
+    for (int e = threadIdx.x; e < K * m; e += blockDim.x) {
+        const u64 h = C.hat[e];
+        s_hl[e] = ((h >> 21) & 0x1FFFFF) << 32 | (h & 0x1FFFFF);
+        s_h2[e] = (u32)(h >> 42);
+    }
     for (int t = threadIdx.x; t < m; t += blockDim.x) {
-        const PrimeInfo P = T.prime[C.dst_prime[t]];
-        s_q[t] = P.q;
-        s_mu[t] = P.mu;
-        s_bits[t] = P.bits;
+        s_q[t] = T.prime[C.dst_prime[t]].q;
         s_r64[t] = C.r64[t];
+        s_r64s[t] = C.r64s[t];
+        s_one[t] = C.ones[t];
         s_dmod[t] = C.dmod[t];
         s_row[t] = C.dst_row[t];
     }
@@ -807,33 +846,36 @@ __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTabl
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = T.N;
     if (i >= N) return;
-    u64 xh[K];
+    // blockIdx.z of gridDim.z takes one slice of the targets (more waves for
+    // launches over few row groups)
+    const int t0 = (m * (int)blockIdx.z) / (int)gridDim.z, t1 = (m * ((int)blockIdx.z + 1)) / (int)gridDim.z;
+    u32 x0[K], x1[K];
     int nneg = 0;
 #pragma unroll
     for (int s = 0; s < K; s++) {
         const u64 x = in[(size_t)g * ig + (size_t)C.src_row[s] * N + i];
-        if (C.own_row && C.own_row[s] >= 0) out[(size_t)g * og + (size_t)C.own_row[s] * N + i] = x;
+        if (C.own_row && C.own_row[s] >= 0 && blockIdx.z == 0)
+            out[(size_t)g * og + (size_t)C.own_row[s] * N + i] = x;
         const u64 d = T.prime[C.src_prime[s]].q;
-        xh[s] = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
+        const u64 xh = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
         // centred: xh - d_s contributes xh * hat - D
-        if (C.centered && xh[s] > (d - 1) / 2) nneg++;
+        if (C.centered && xh > (d - 1) / 2) nneg++;
+        x0[s] = (u32)xh;
+        x1[s] = (u32)(xh >> 32);
     }
     u64* o = out + (size_t)g * og + i;
-#pragma unroll 2
-    for (int t = 0; t < m; t++) {
-        // exact sum of K <= 16 products below 2^122, then one reduction of
-        // its two 64-bit words: (hi mod q) 2^64 + lo
-        unsigned __int128 wide = 0;
-#pragma unroll
-        for (int s = 0; s < K; s++) wide += (unsigned __int128)xh[s] * s_hat[s * m + t];
-        PrimeInfo P;
-        P.q = s_q[t];
-        P.mu = s_mu[t];
-        P.bits = s_bits[t];
-        u64 acc = reduce_wide(wide, P, s_r64[t]);
+    for (int t = t0; t < t1; t++) {
+        const u64 q = s_q[t];
+        // the branch is uniform: every lane works on target t
+        const unsigned __int128 v = q >> 42 ? conv_sum<K, true>(x0, x1, s_hl, s_h2, m, t)
+                                            : conv_sum<K, false>(x0, x1, s_hl, s_h2, m, t);
+        // v mod q = (hi 2^64 mod q) + (lo mod q): two Shoup reductions
+        const u64 hi = (u64)(v >> 64), lo = (u64)v;
+        const u64 rl = lo - __umul64hi(lo, s_one[t]) * q;
+        u64 acc = add_mod(mul_shoup(hi, s_r64[t], s_r64s[t], q), rl >= q ? rl - q : rl, q);
         if (nneg) {
             const u64 dm = s_dmod[t];
-            for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, P.q);
+            for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, q);
         }
         o[(size_t)s_row[t] * N] = acc;
     }
@@ -955,25 +997,27 @@ static void launch_base_convert_mfma(const DevTables& T, const ConvTables& C, u6
 
 template <int K>
 static void launch_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in,
-                                size_t ig, int ngroups, hipStream_t st) {
+                                size_t ig, int ngroups, int split, hipStream_t st) {
     if (C.k == K)
-        hipLaunchKernelGGL(base_convert_kernel<K>, dim3((T.N + 255) / 256, ngroups), dim3(256), 0, st, T, C, out,
-                           og, in, ig);
+        hipLaunchKernelGGL(base_convert_kernel<K>, dim3((T.N + 255) / 256, ngroups, split), dim3(256), 0, st, T, C,
+                           out, og, in, ig);
     else if constexpr (K < kMaxConvSrc)
-        launch_base_convert<K + 1>(T, C, out, og, in, ig, ngroups, st);
+        launch_base_convert<K + 1>(T, C, out, og, in, ig, ngroups, split, st);
 }
 
 static bool conv_planes_fit(const DevTables& T, const ConvTables& C) {
     return C.bfrag && T.N % 16 == 0 && (size_t)C.ntb * C.nks * 8 * 64 * sizeof(u64) <= (size_t)kConvPlaneLds;
 }
 
-// variant 0: VALU kernel; 1: matrix-core kernel (when its tables exist)
+// variant 0: VALU kernel; 1: matrix-core kernel (when its tables exist);
+// 2, 3: VALU kernel with the targets split over 2 or 4 threads per coefficient
+static const char* const kConvVariants[] = {"valu", "mfma", "valu/split2", "valu/split4"};
 static void conv_launch(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in, size_t ig,
                         int ngroups, int variant, hipStream_t st) {
     if (variant == 1 && conv_planes_fit(T, C))
         launch_base_convert_mfma<1>(T, C, out, og, in, ig, ngroups, st);
     else
-        launch_base_convert<1>(T, C, out, og, in, ig, ngroups, st);
+        launch_base_convert<1>(T, C, out, og, in, ig, ngroups, variant == 2 ? 2 : variant == 3 ? 4 : 1, st);
 }
 
 // ------------------------------------------------------------- autotuner
@@ -1116,8 +1160,9 @@ int tune_conv(const DevTables& T, const ConvTables& C, size_t og, size_t ig, int
     const int v = tune_lookup(key);
     if (v >= 0 || !tuning_on()) return v < 0 ? 0 : v;
     const int gq = pow2_bucket(ngroups);
-    return tune_run(key, {"valu", "mfma"}, {true, conv_planes_fit(T, C)}, (size_t)gq * ig, (size_t)gq * og, false,
-                    st, [&](int c, const u64* in, u64* out) { conv_launch(T, C, out, og, in, ig, gq, c, st); });
+    return tune_run(key, {kConvVariants, kConvVariants + 4}, {true, conv_planes_fit(T, C), C.m >= 4, C.m >= 8},
+                    (size_t)gq * ig, (size_t)gq * og, false, st,
+                    [&](int c, const u64* in, u64* out) { conv_launch(T, C, out, og, in, ig, gq, c, st); });
 }
 
 int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st) {
@@ -1181,7 +1226,7 @@ int tune_load(const std::string& text) {
         const std::string key = field("key"), choice = field("choice");
         if (key.empty() || choice.empty()) continue;
         std::vector<std::string> names;
-        if (key.rfind("conv", 0) == 0) names = {"valu", "mfma"};
+        if (key.rfind("conv", 0) == 0) names = {kConvVariants, kConvVariants + 4};
         else if (key.rfind("ntt", 0) == 0)
             names = {"prime-major", "storage-order", "prime-major/batched", "storage-order/batched"};
         TuneEntry E;

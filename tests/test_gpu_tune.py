@@ -3,8 +3,9 @@
 The metric's batched Softmax job (64 ciphertexts, N = 2^16) is run with the
 default kernels, then with tuning enabled (each launch shape times its
 candidates on scratch data), then with every decision forced to a
-non-default candidate (matrix-core base conversion, other NTT row orders and
-batched launches): all three give the same output ciphertexts bit for bit."""
+non-default candidate (matrix-core base conversion, conversion targets split
+over threads, other NTT row orders and batched launches): all three give the
+same output ciphertexts bit for bit."""
 import json
 
 import numpy as np
@@ -38,13 +39,15 @@ def test_tuned_and_forced_variants_match_defaults(tmp_path):
         kinds = {r["key"].split()[0] for r in rep}
         assert kinds == {"conv", "ntt"}
         print("tuned:", json.dumps(rep[:3]), "... %d entries" % len(rep))
-        # force the slowest-ranked valid non-default candidate of every shape
+        # force a valid non-default candidate on every shape, cycling through
+        # them so that each one is exercised
         forced = []
-        for r in rep:
+        for i, r in enumerate(rep):
             alts = [name for name, t in r["us"].items() if t >= 0 and name not in ("valu", "prime-major")]
-            forced.append({"key": r["key"], "choice": alts[-1] if alts else r["choice"]})
-        assert any(f["choice"] == "mfma" for f in forced)
-        assert any(f["choice"].endswith("batched") for f in forced)
+            forced.append({"key": r["key"], "choice": alts[i % len(alts)] if alts else r["choice"]})
+        chosen = {f["choice"] for f in forced}
+        for name in ("mfma", "valu/split2", "valu/split4", "storage-order/batched"):
+            assert name in chosen, name
         path = tmp_path / "forced.json"
         path.write_text("".join(json.dumps(f) + "\n" for f in forced))
         hs.tune_enable(False)
