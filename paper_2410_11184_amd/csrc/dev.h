@@ -104,6 +104,23 @@ void tune_clear();                       // forget every decision (defaults agai
 std::string tune_dump();                 // one JSON object per line
 int tune_load(const std::string& text);  // entries taken
 
+// Epilogue of a forward NTT of rows x (groups G = 0..ngroups-1, rows r of a
+// group use primes q_off + r): instead of NTT(x), write
+//   out_j[G / split][r] = (d_j[G / split][r] +) (a[G][r] - NTT(x)[G][r]) c[r]
+// with j = G mod split (split = 1 or 2: the two components of ModDown); the
+// addend is taken where d_j is not null.
+struct NttEpilogue {
+    int split = 1;
+    u64* out[2] = {nullptr, nullptr};
+    size_t out_gs[2] = {0, 0};
+    const u64* a = nullptr;
+    size_t a_gs = 0;
+    const u64* d[2] = {nullptr, nullptr};
+    size_t d_gs[2] = {0, 0};
+    int g0 = 0;                  // group offset of a partial launch
+    RowConsts c;
+};
+
 // ------------------------------------------------------------- launches
 // All launches are asynchronous on `stream` (a hipStream_t).
 void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream);
@@ -111,6 +128,8 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream);
 double k_mul_rate(void* stream);
 // x = NTT(src) (or its inverse); src has x's shape and may be x itself
 void k_ntt_from(const DevTables& T, const Rows& x, const Rows& src, bool inverse, void* stream);
+// forward NTT of x followed by the epilogue (x is left unspecified)
+void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream);
 void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
 void k_sub(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
 void k_neg(const DevTables& T, const Rows& out, const Rows& a, void* stream);

@@ -475,7 +475,9 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
     }
 }
 
-__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order) {
+template <bool EPI>
+__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+                                                       NttEpilogue Ep) {
     __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row(x, blockIdx.y, order);
     const int pi = prime_of(x, row % x.rpg);
@@ -502,8 +504,25 @@ __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) s[l * 17 + lo] = E[lo];
         __syncthreads();
+        if constexpr (!EPI) {
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = reduce4q(s[hi * 17 + l], q);
+            for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = reduce4q(s[hi * 17 + l], q);
+        } else {
+            // (d +) (a - NTT(x)) c for this row, written to its destination
+            const int G = Ep.g0 + row / x.rpg, r = row % x.rpg;
+            const int j = G % Ep.split, gj = G / Ep.split;
+            const size_t off = (size_t)r * 65536 + (size_t)R * 256;
+            const u64* pa = Ep.a + (size_t)G * Ep.a_gs + off;
+            u64* po = Ep.out[j] + (size_t)gj * Ep.out_gs[j] + off;
+            const u64 c = Ep.c.c[r], cs = Ep.c.cs[r];
+#pragma unroll
+            for (int hi = 0; hi < 16; hi++) {
+                const int k = hi * 16 + l;
+                u64 v = mul_shoup(sub_mod(pa[k], reduce4q(s[hi * 17 + l], q), q), c, cs, q);
+                if (Ep.d[j]) v = add_mod(Ep.d[j][(size_t)gj * Ep.d_gs[j] + off + k], v, q);
+                po[k] = v;
+            }
+        }
     } else {
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) s[hi * 17 + l] = E[hi];
@@ -531,21 +550,53 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) { k_nt
 // variant & 2 splits the launch into batches of kNttGroupBatch row groups.
 constexpr int kNttGroupBatch = 8;
 static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, bool inverse, int variant,
-                         hipStream_t st) {
+                         hipStream_t st, const NttEpilogue* epi = nullptr) {
     const int order = variant & 1;
     const int gb = (variant & 2) ? kNttGroupBatch : x.ngroups;
+    NttEpilogue e;
+    if (epi) e = *epi;
     for (int g0 = 0; g0 < x.ngroups; g0 += gb) {
         Rows xs = x, ss = src;
         xs.base = x.base + (size_t)g0 * x.gstride;
         ss.base = src.base + (size_t)g0 * src.gstride;
         xs.ngroups = ss.ngroups = std::min(gb, x.ngroups - g0);
+        e.g0 = g0;
         const dim3 g(16, xs.ngroups * xs.rpg);
         if (!inverse) {
             hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order);
-            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, xs, xs, 0, order);
+            if (epi)
+                hipLaunchKernelGGL(ntt16_p2_kernel<true>, g, dim3(256), 0, st, T, xs, xs, 0, order, e);
+            else
+                hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, xs, 0, order, e);
         } else {
-            hipLaunchKernelGGL(ntt16_p2_kernel, g, dim3(256), 0, st, T, xs, ss, 1, order);
+            hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, ss, 1, order, e);
             hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order);
+        }
+    }
+}
+
+void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream) {
+    const int nrows = x.ngroups * x.rpg;
+    if (nrows == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    if (T.logN == 16) {
+        const int variant = tune_ntt16(T, x, false, st);
+        ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
+        ntt16_launch(T, x, x, false, variant, st, &e);
+        return;
+    }
+    // other ring sizes: the transform, then the epilogue as its own kernels
+    k_ntt(T, x, false, stream);
+    for (int j = 0; j < e.split; j++) {
+        const int ng = (x.ngroups - j + e.split - 1) / e.split;
+        Rows ro{e.out[j], ng, x.rpg, e.out_gs[j], x.nq, x.q_off, x.p_base};
+        Rows ra{const_cast<u64*>(e.a) + (size_t)j * e.a_gs, ng, x.rpg, e.a_gs * e.split, x.nq, x.q_off, x.p_base};
+        Rows rb{x.base + (size_t)j * x.gstride, ng, x.rpg, x.gstride * e.split, x.nq, x.q_off, x.p_base};
+        if (e.d[j]) {
+            Rows rd{const_cast<u64*>(e.d[j]), ng, x.rpg, e.d_gs[j], x.nq, x.q_off, x.p_base};
+            k_add_sub_mul_const(T, ro, rd, ra, rb, e.c, stream);
+        } else {
+            k_sub_mul_const(T, ro, ra, rb, e.c, stream);
         }
     }
 }

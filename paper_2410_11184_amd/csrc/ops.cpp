@@ -131,14 +131,17 @@ Ct op_rescale(Context& c, const Ct& a) {
     k_ntt_from(c.T, r_last, in_last, true, c.stream);
     Rows r_lift{lifted, np_, l, (size_t)l * N, l, 0, c.nq};
     k_lift_centered(c.T, r_lift, last, N, l, c.stream);
-    k_ntt(c.T, r_lift, false, c.stream);
     Ct o = ct_alloc(c, a.m, a.ncomp, l - 1);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = invmod_h(c.primes[l] % c.primes[i], c.primes[i]);
-    RowConsts rc = c.shoup_consts(inv, 0);
-    Rows out{o.d, np_, l, (size_t)l * N, l, 0, c.nq};
-    Rows ain{a.d, np_, l, (size_t)(l + 1) * N, l, 0, c.nq};
-    k_sub_mul_const(c.T, out, ain, r_lift, rc, c.stream);
+    // out = (a - NTT(lifted)) q_l^-1, fused into the transform's last pass
+    NttEpilogue e;
+    e.c = c.shoup_consts(inv, 0);
+    e.out[0] = o.d;
+    e.out_gs[0] = (size_t)l * N;
+    e.a = a.d;
+    e.a_gs = (size_t)(l + 1) * N;
+    k_ntt_epilogue(c.T, r_lift, e, c.stream);
     o.scale = a.scale / (double)c.primes[l];
     c.free_words(last);
     c.free_words(lifted);
@@ -258,19 +261,26 @@ static void ks_finish(Context& c, const u64* ext, int m, int level, const u64* k
     const ConvDev& md = c.moddown_tables(l);
     k_base_convert(c.T, md.t, conv, (size_t)nql * N, acc, (size_t)E * N, 2 * m, c.stream);
     Rows rconv{conv, 2 * m, nql, (size_t)nql * N, nql, 0, c.nq};
-    k_ntt(c.T, rconv, false, c.stream);
     std::vector<u64> pinv(nql);
     for (int i = 0; i < nql; i++) pinv[i] = invmod_h(c.P_mod[i], c.primes[i]);
-    RowConsts rc = c.shoup_consts(pinv, 0);
+    // out_k = (add_k +) (acc_k - NTT(conv_k)) P^-1, fused into the transform's
+    // last pass; group G of conv is component G mod 2 of ciphertext G / 2
+    NttEpilogue e;
+    e.c = c.shoup_consts(pinv, 0);
+    e.split = 2;
+    e.a = acc;
+    e.a_gs = (size_t)E * N;
     for (int k = 0; k < 2; k++) {
-        u64* outk = k == 0 ? out0 : out1;
-        Rows ro{outk, m, nql, out_gstride, nql, 0, c.nq};
-        Rows ra{acc + (size_t)k * E * N, m, nql, (size_t)2 * E * N, nql, 0, c.nq};
-        Rows rb{conv + (size_t)k * nql * N, m, nql, (size_t)2 * nql * N, nql, 0, c.nq};
+        e.out[k] = k == 0 ? out0 : out1;
+        e.out_gs[k] = out_gstride;
         const Rows* add = k == 0 ? add0 : add1;
-        if (add) k_add_sub_mul_const(c.T, ro, *add, ra, rb, rc, c.stream);
-        else k_sub_mul_const(c.T, ro, ra, rb, rc, c.stream);
+        if (add) {
+            HS_REQUIRE(add->ngroups == m && add->rpg == nql, E_ARG, "key switch: addend shape");
+            e.d[k] = add->base;
+            e.d_gs[k] = add->gstride;
+        }
     }
+    k_ntt_epilogue(c.T, rconv, e, c.stream);
     c.free_words(acc);
     c.free_words(conv);
 }
