@@ -239,6 +239,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured schedule")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time version-B jobs of 1, 2, 4, ..., 64 ciphertexts")
+    ap.add_argument("--sm-many", action="store_true",
+                    help="also time version SM on the same 64 ciphertexts (bootstraps the main ciphertexts)")
     ap.add_argument("--tune", action="store_true",
                     help="time interchangeable kernels during the warm-up and save the decisions")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -373,6 +377,45 @@ def main():
     roofline.update({"launches": d["launches"], "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "hbm_algorithmic_GBps": hbm_achieved, "hbm_frac": hbm_achieved / PEAK_HBM_GBS})
 
+    sweep = None
+    if args.sweep:
+        # version-B jobs of m = 1 .. 64 ciphertexts (Section 4.2 packing, n = 256,
+        # U[-128, 0]), each captured and replayed like the metric's job
+        sweep = []
+        for mm in (1, 2, 4, 8, 16, 32, 64):
+            Lm = mm * p["slots"] // n
+            xm = synthetic.logits_uniform(Lm, n, M, seed=7000 + mm)
+            cm = encrypt_logits(ctx, xm, M, seed=7100 + mm)
+            pm = ctx.softmax_plan(cm, n, M, variant=variant)
+            pm.run(cm)
+            ctx.sync()
+            t0 = time.perf_counter()
+            om = pm.run(cm)
+            ctx.sync()
+            tm = time.perf_counter() - t0
+            bm = S.precision_bits(S.softmax(xm), decrypt_outputs(ctx, om, n))
+            sweep.append({"ciphertexts": mm, "calls": Lm, "ms_per_job": 1e3 * tm, "calls_per_s": Lm / tm,
+                          "bootstraps": ctx.softmax_stats()["bootstraps"], "worst_bits": bm["worst"]})
+            _log("sweep m=%d: %.1f ms, %.1f calls/s, worst %.2f bits" % (mm, 1e3 * tm, Lm / tm, bm["worst"]))
+            del om, cm
+            pm.close()
+
+    sm_many = None
+    if args.sm_many:
+        # trade study: the same 64 ciphertexts through version SM (main
+        # ciphertexts bootstrapped when their levels run out), eager, one job
+        t0 = time.perf_counter()
+        osm = ctx.softmax(cts, n, M, variant=0)
+        ctx.sync()
+        tsm = time.perf_counter() - t0
+        st_sm = ctx.softmax_stats()
+        bsm = S.precision_bits(S.softmax(x), decrypt_outputs(ctx, osm, n))
+        del osm
+        sm_many = dict(calls_per_s=L / tsm, s_per_job=tsm, precision_worst_bits=bsm["worst"],
+                       bootstraps=st_sm["bootstraps"], k=st_sm["k"], schedule="eager")
+        _log("SM many-ciphertext: %.2fs per job, %.1f calls/s, %d bootstraps, worst %.2f bits" %
+             (tsm, L / tsm, st_sm["bootstraps"], bsm["worst"]))
+
     plain = None
     if not args.no_plain:
         wp = synthetic.WORKLOADS["fgb16_sm"]
@@ -430,6 +473,8 @@ def main():
         "precision_bits": bits,
         "plain": plain,
         "speedup_vs_plain": (value / plain["calls_per_s"]) if plain else None,
+        "sm_many_ciphertext": sm_many,
+        "smb_scaling": sweep,
         # not the metric: the client side (pack, encode, PCIe upload, encrypt) and decryption
         "client_encrypt_s": client_encrypt_s,
         "calls_per_s_including_client_encrypt": L / (ms_step * 1e-3 + client_encrypt_s),

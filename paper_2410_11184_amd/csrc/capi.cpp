@@ -196,6 +196,14 @@ hs_status hs_key_export(hs_ctx* ctx, int key_id, uint64_t* out, size_t cap, size
         if (!out || cap == 0) return;
         HS_REQUIRE(cap >= w, hs::E_ARG, "buffer too small");
         c.download(out, c.keys.at(key_id), w * 8);
+        // the device copy holds the Q rows times P^-1 mod q_i: restore them
+        const size_t rw = (size_t)(c.nq + c.np) * c.N;
+        for (int blk = 0; blk < 2 * c.dnum; blk++)
+            for (int i = 0; i < c.nq; i++) {
+                const uint64_t q = c.primes[i], pm = c.P_mod[i];
+                uint64_t* row = out + blk * rw + (size_t)i * c.N;
+                for (int x = 0; x < c.N; x++) row[x] = hs::mulmod_h(row[x], pm, q);
+            }
     });
 }
 

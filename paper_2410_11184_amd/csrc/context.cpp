@@ -466,7 +466,7 @@ CtHandle::~CtHandle() {
 // ------------------------------------------------- base-conversion tables
 static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vector<int>& src_row,
                          const std::vector<int>& dst, const std::vector<int>& dst_row, bool centered,
-                         const std::vector<int>& own_row = {}) {
+                         const std::vector<int>& own_row = {}, const std::vector<u64>& post = {}) {
     const int k = (int)src.size(), m = (int)dst.size();
     // the conversion kernel holds k sources in registers and m targets in LDS
     HS_REQUIRE(k >= 1 && k <= 16 && m <= kMaxRows, E_PARAM, "base conversion shape out of range");
@@ -483,6 +483,7 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
             u64 g = 1;
             for (int j = 0; j < k; j++)
                 if (j != i) g = mulmod_h(g, c.primes[src[j]] % qt, qt);
+            if (!post.empty()) g = mulmod_h(g, post[t], qt);   // output times post[t]
             hat[(size_t)i * m + t] = g;
             hat_s[(size_t)i * m + t] = shoup_h(g, qt);
         }
@@ -512,6 +513,7 @@ static ConvDev make_conv(Context& c, const std::vector<int>& src, const std::vec
         const u64 qt = c.primes[dst[t]];
         u64 g = 1;
         for (int j = 0; j < k; j++) g = mulmod_h(g, c.primes[src[j]] % qt, qt);
+        if (!post.empty()) g = mulmod_h(g, post[t], qt);
         dmod[t] = g;
     }
     cd.t.dmod = (const u64*)put(dmod.data(), m * 8);
@@ -612,7 +614,10 @@ const ConvDev& Context::moddown_tables(int level) {
         drow.push_back(i);
     }
     HS_REQUIRE((int)src.size() <= 16, E_PARAM, "too many special primes");
-    return moddown.emplace(level, make_conv(*this, src, srow, dst, drow, true)).first->second;
+    // outputs come out times P^-1 (the key's Q rows carry the same factor)
+    std::vector<u64> pinv(level + 1);
+    for (int i = 0; i <= level; i++) pinv[i] = invmod_h(P_mod[i], primes[i]);
+    return moddown.emplace(level, make_conv(*this, src, srow, dst, drow, true, {}, pinv)).first->second;
 }
 
 // X -> X^g in the bit-reversed NTT domain: out[i] = in[perm[i]] with
@@ -784,6 +789,13 @@ static u64* make_switch_key(Context& c, int key_id, const u64* s_target) {
         k_mul_row_const(c.T, t2, st, rc, c.stream);
         k_add(c.T, dst, dst, t2, c.stream);
     }
+    // stored with the Q rows times P^-1 mod q_i: the inner product then lands
+    // divided by P on Q, and ModDown only subtracts (the P rows, which feed
+    // the ModDown conversion, are kept as they are); hs_key_export undoes it
+    std::vector<u64> pinv(c.nq);
+    for (int i = 0; i < c.nq; i++) pinv[i] = invmod_h(c.P_mod[i], c.primes[i]);
+    Rows rq{key, 2 * c.dnum, c.nq, rows_words, c.nq, 0, c.nq};
+    k_mul_row_const(c.T, rq, rq, c.shoup_consts(pinv, 0), c.stream);
     c.sync();
     c.free_words(tmp);
     return key;

@@ -106,11 +106,12 @@ int tune_load(const std::string& text);  // entries taken
 
 // Epilogue of a forward NTT of rows x (groups G = 0..ngroups-1, rows r of a
 // group use primes q_off + r): instead of NTT(x), write
-//   out_j[G / split][r] = (d_j[G / split][r] +) (a[G][r] - NTT(x)[G][r]) c[r]
+//   out_j[G / split][r] = (d_j[G / split][r] +) (a[G][r] - NTT(x)[G][r]) (c[r])
 // with j = G mod split (split = 1 or 2: the two components of ModDown); the
-// addend is taken where d_j is not null.
+// addend is taken where d_j is not null, the factor c where mul is set.
 struct NttEpilogue {
     int split = 1;
+    bool mul = true;
     u64* out[2] = {nullptr, nullptr};
     size_t out_gs[2] = {0, 0};
     const u64* a = nullptr;

@@ -518,7 +518,8 @@ __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows
 #pragma unroll
             for (int hi = 0; hi < 16; hi++) {
                 const int k = hi * 16 + l;
-                u64 v = mul_shoup(sub_mod(pa[k], reduce4q(s[hi * 17 + l], q), q), c, cs, q);
+                u64 v = sub_mod(pa[k], reduce4q(s[hi * 17 + l], q), q);
+                if (Ep.mul) v = mul_shoup(v, c, cs, q);
                 if (Ep.d[j]) v = add_mod(Ep.d[j][(size_t)gj * Ep.d_gs[j] + off + k], v, q);
                 po[k] = v;
             }
@@ -592,11 +593,13 @@ void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, voi
         Rows ro{e.out[j], ng, x.rpg, e.out_gs[j], x.nq, x.q_off, x.p_base};
         Rows ra{const_cast<u64*>(e.a) + (size_t)j * e.a_gs, ng, x.rpg, e.a_gs * e.split, x.nq, x.q_off, x.p_base};
         Rows rb{x.base + (size_t)j * x.gstride, ng, x.rpg, x.gstride * e.split, x.nq, x.q_off, x.p_base};
-        if (e.d[j]) {
-            Rows rd{const_cast<u64*>(e.d[j]), ng, x.rpg, e.d_gs[j], x.nq, x.q_off, x.p_base};
-            k_add_sub_mul_const(T, ro, rd, ra, rb, e.c, stream);
+        Rows rd{const_cast<u64*>(e.d[j]), ng, x.rpg, e.d_gs[j], x.nq, x.q_off, x.p_base};
+        if (e.mul) {
+            if (e.d[j]) k_add_sub_mul_const(T, ro, rd, ra, rb, e.c, stream);
+            else k_sub_mul_const(T, ro, ra, rb, e.c, stream);
         } else {
-            k_sub_mul_const(T, ro, ra, rb, e.c, stream);
+            k_sub(T, ro, ra, rb, stream);
+            if (e.d[j]) k_add(T, ro, rd, ro, stream);
         }
     }
 }

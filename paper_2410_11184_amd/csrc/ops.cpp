@@ -261,12 +261,12 @@ static void ks_finish(Context& c, const u64* ext, int m, int level, const u64* k
     const ConvDev& md = c.moddown_tables(l);
     k_base_convert(c.T, md.t, conv, (size_t)nql * N, acc, (size_t)E * N, 2 * m, c.stream);
     Rows rconv{conv, 2 * m, nql, (size_t)nql * N, nql, 0, c.nq};
-    std::vector<u64> pinv(nql);
-    for (int i = 0; i < nql; i++) pinv[i] = invmod_h(c.P_mod[i], c.primes[i]);
     // out_k = (add_k +) (acc_k - NTT(conv_k)) P^-1, fused into the transform's
-    // last pass; group G of conv is component G mod 2 of ciphertext G / 2
+    // last pass; both acc's Q rows (through the key) and the conversion's
+    // outputs (through its constants) already carry the factor P^-1.  Group G
+    // of conv is component G mod 2 of ciphertext G / 2
     NttEpilogue e;
-    e.c = c.shoup_consts(pinv, 0);
+    e.mul = false;
     e.split = 2;
     e.a = acc;
     e.a_gs = (size_t)E * N;
