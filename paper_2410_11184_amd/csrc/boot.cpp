@@ -311,44 +311,63 @@ static void ensure_keys(Context& c, BootCtx& B) {
 // (skipped when do_rescale is false: the caller rescales later)
 static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x, bool do_rescale = true) {
     HS_REQUIRE(x.level == lv.level, E_LEVEL, "linear transform: unexpected input level");
-    std::map<int, Ct> baby;
+    const size_t cw = x.ct_words(c.N) * x.m;   // words of one rotation of x
+    // baby steps: every nonzero rotation of x in one hoisted batch
     std::set<int> need;
     for (auto& kv : lv.by_giant)
-        for (int b : kv.second) need.insert(b);
-    {
-        // baby steps: rotations of one ciphertext, sharing one ModUp
-        std::vector<int> bs(need.begin(), need.end()), rs;
-        for (int b : bs) rs.push_back(b * lv.unit);
-        std::vector<Ct> rot = op_rotate_hoisted(c, x, rs);
-        for (size_t i = 0; i < bs.size(); i++) baby[bs[i]] = rot[i];
+        for (int b : kv.second)
+            if (b != 0) need.insert(b);
+    std::map<int, int> slot;
+    Ct babies;
+    if (!need.empty()) {
+        std::vector<int> rs;
+        for (int b : need) {
+            slot[b] = (int)rs.size();
+            rs.push_back(b * lv.unit);
+        }
+        babies = op_rotate_hoisted_batch(c, x, rs);
     }
-    Ct acc;
-    bool have = false;
+    auto baby = [&](int b) -> const u64* { return b == 0 ? x.d : babies.d + (size_t)slot.at(b) * cw; };
+    // sums over the babies of baby_b * diag_(g,b) (one fused launch per giant
+    // step): giant 0 straight into the accumulator, the others into one batch
+    // that takes all its giant-step rotations in one batched key switch
+    Ct acc = ct_alloc(c, x.m, 2, x.level);
+    acc.scale = x.scale * lv.pt_scale;
+    std::vector<int> giants;
+    for (auto& kv : lv.by_giant)
+        if (kv.first != 0) giants.push_back(kv.first);
+    Ct inner;
+    if (!giants.empty()) {
+        inner = ct_alloc(c, (int)giants.size() * x.m, 2, x.level);
+        inner.scale = acc.scale;
+    }
+    bool have0 = false;
+    int gi = 0;
     for (auto& kv : lv.by_giant) {
-        const int g = kv.first;
-        // sum over the babies of baby_b * diag_(g,b), one fused launch
-        Ct inner = ct_alloc(c, x.m, 2, x.level);
-        inner.scale = x.scale * lv.pt_scale;
         std::vector<const u64*> as, ps;
         for (int b : kv.second) {
-            as.push_back(baby.at(b).d);
-            ps.push_back(lv.pt.at({g, b}));
+            as.push_back(baby(b));
+            ps.push_back(lv.pt.at({kv.first, b}));
         }
-        k_mul_plain_acc(c.T, inner.d, as.data(), ps.data(), (int)as.size(), x.m * 2, x.level + 1, c.stream);
-        if (g != 0) {
-            Ct r = op_rotate(c, inner, g * lv.n1 * lv.unit);
-            ct_free(c, inner);
-            inner = r;
-        }
-        if (!have) {
-            acc = inner;
-            have = true;
-        } else {
-            op_add_inplace(c, acc, inner);
-            ct_free(c, inner);
-        }
+        u64* dst = kv.first == 0 ? acc.d : inner.d + (size_t)(gi++) * cw;
+        if (kv.first == 0) have0 = true;
+        k_mul_plain_acc(c.T, dst, as.data(), ps.data(), (int)as.size(), x.m * 2, x.level + 1, c.stream);
     }
-    for (auto& kv : baby) ct_free(c, kv.second);
+    if (babies.d) ct_free(c, babies);
+    if (!giants.empty()) {
+        std::vector<int> gal;
+        for (int g : giants) gal.push_back(galois_rot(g * lv.n1 * lv.unit, c.N));
+        Ct rot = op_galois_batch(c, inner, gal, x.m);
+        ct_free(c, inner);
+        const Rows ra = c.ct_rows(acc);
+        for (size_t i = 0; i < giants.size(); i++) {
+            Rows rr = ra;
+            rr.base = rot.d + i * cw;
+            if (i == 0 && !have0) k_copy_rows(c.T, ra, rr, c.stream);
+            else k_add(c.T, ra, ra, rr, c.stream);
+        }
+        ct_free(c, rot);
+    }
     if (!do_rescale) return acc;
     Ct out = op_rescale(c, acc);
     ct_free(c, acc);

@@ -158,6 +158,21 @@ void k_tensor(const DevTables& T, const Rows& d, const Rows& a, const Rows& b, s
 void k_square_sum(const DevTables& T, u64* d, size_t d_comp, const Rows& a, size_t a_comp,
                   void* stream);
 void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* perm, void* stream);
+// several automorphisms in one launch: output group G reads input group
+// G mod in.ngroups through perm[G / per]
+constexpr int kMaxKeys = 32;
+struct PermList {
+    const int* perm[kMaxKeys];
+    int n;
+    int per;
+};
+void k_permute_multi(const DevTables& T, const Rows& out, const Rows& in, const PermList& perms, void* stream);
+// keys of a batched key switch: ciphertext g uses key[g / per]
+struct KeyList {
+    const u64* key[kMaxKeys];
+    int n;
+    int per;
+};
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride,
                     const u64* in, size_t in_gstride, int ngroups, void* stream);
 // centred lift of one row (prime src_prime, coefficient domain) of each
@@ -166,8 +181,8 @@ void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t 
                      int src_prime, void* stream);
 // hybrid key-switching inner product: for each ciphertext g and extended row
 // r: acc0 = sum_j ext[g][j][r] * key[j][0][kr(r)], acc1 likewise with key[j][1]
-void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta,
-                 int ext_rows, int nq_level, int key_rows, int key_nq, int alpha, void* stream);
+void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const KeyList& keys, int beta, int ext_rows,
+                 int nq_level, int key_rows, int key_nq, void* stream);
 void k_sample_uniform(const DevTables& T, const Rows& out, u64 seed, u64 domain_base, void* stream);
 // kind: 0 uniform ternary, 2 gaussian (cdt table in device memory)
 void k_sample_small(int64_t* out, int N, u64 seed, u64 domain, int kind, const u64* cdt, int ncdt,

@@ -258,7 +258,11 @@ Ct op_apply_galois(Context& c, const Ct& a, int g);
 Ct op_rotate(Context& c, const Ct& a, int r);
 Ct op_conjugate(Context& c, const Ct& a);
 // rotations of a by every r in rots with one shared ModUp (values as op_rotate)
-std::vector<Ct> op_rotate_hoisted(Context& c, const Ct& a, const std::vector<int>& rots);
+// rotations of a by every r in rots (none a multiple of the slot count) with
+// one ModUp: one batch of rots.size() * a.m ciphertexts, rotation-major
+Ct op_rotate_hoisted_batch(Context& c, const Ct& a, const std::vector<int>& rots);
+// block i of `per` ciphertexts of a through Galois element gal[i]
+Ct op_galois_batch(Context& c, const Ct& a, const std::vector<int>& gal, int per);
 Ct op_mod_raise(Context& c, const Ct& a, int level);
 Ct op_mul_monomial(Context& c, const Ct& a, int k);
 void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1,

@@ -830,6 +830,24 @@ void k_permute(const DevTables& T, const Rows& out, const Rows& in, const int* p
     hipLaunchKernelGGL(permute_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, in, perm, T.N);
 }
 
+__global__ void permute_multi_kernel(Rows out, Rows in, PermList perms, int N) {
+    const int row = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int G = row / out.rpg, r = row - G * out.rpg;
+    const int* perm = perms.perm[G / perms.per];
+    const u64* src = in.base + (size_t)(G % in.ngroups) * in.gstride + (size_t)r * N;
+    row_ptr(out, row, N)[i] = src[perm[i]];
+}
+
+void k_permute_multi(const DevTables& T, const Rows& out, const Rows& in, const PermList& perms, void* stream) {
+    if (out.ngroups * out.rpg == 0) return;
+    if (perms.per < 1 || (out.ngroups + perms.per - 1) / perms.per > perms.n || in.rpg < out.rpg) return;
+    ProfScope ps(T.prof, PK_PERM, 16.0 * T.N * out.ngroups * out.rpg, stream);
+    hipLaunchKernelGGL(permute_multi_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, in, perms,
+                       T.N);
+}
+
 // --------------------------------------------------------- base conversion
 // One thread per coefficient, K (the number of source primes) a template
 // argument so the lifted sources stay in registers (a source row may also be
@@ -1342,22 +1360,25 @@ void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t 
 constexpr int kMaxDigits = 16;
 
 template <int B>
-__global__ void __launch_bounds__(256) key_inner_kernel(DevTables T, u64* acc, const u64* ext, const u64* key,
-                                                        int ncts, int E, int nql, int key_rows, int key_nq) {
+__global__ void __launch_bounds__(256) key_inner_kernel(DevTables T, u64* acc, const u64* ext, KeyList keys,
+                                                        int E, int nql, int key_rows, int key_nq) {
     const int r = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = T.N;
     if (i >= N) return;
     const int kr = r < nql ? r : key_nq + (r - nql);
     const PrimeInfo P = T.prime[kr];
+    const u64 r64 = T.r64[kr];
+    // each key is read once and applied to its block of ciphertexts
+    for (int kk = 0; kk < keys.n; kk++) {
+    const u64* key = keys.key[kk];
     u64 kb[B], ka[B];
 #pragma unroll
     for (int j = 0; j < B; j++) {
         kb[j] = key[((size_t)(2 * j) * key_rows + kr) * N + i];
         ka[j] = key[((size_t)(2 * j + 1) * key_rows + kr) * N + i];
     }
-    const u64 r64 = T.r64[kr];
-    for (int g = 0; g < ncts; g++) {
+    for (int g = kk * keys.per; g < (kk + 1) * keys.per; g++) {
         // exact sums of B <= 16 products below 2^122, reduced once
         unsigned __int128 s0 = 0, s1 = 0;
 #pragma unroll
@@ -1369,25 +1390,27 @@ __global__ void __launch_bounds__(256) key_inner_kernel(DevTables T, u64* acc, c
         acc[(((size_t)g * 2 + 0) * E + r) * N + i] = reduce_wide(s0, P, r64);
         acc[(((size_t)g * 2 + 1) * E + r) * N + i] = reduce_wide(s1, P, r64);
     }
+    }
 }
 
 template <int B>
-static void launch_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta,
-                             int E, int nql, int key_rows, int key_nq, hipStream_t st) {
+static void launch_key_inner(const DevTables& T, u64* acc, const u64* ext, const KeyList& keys, int beta, int E,
+                             int nql, int key_rows, int key_nq, hipStream_t st) {
     if (beta == B)
-        hipLaunchKernelGGL(key_inner_kernel<B>, dim3((T.N + 255) / 256, E), dim3(256), 0, st, T, acc, ext, key,
-                           ncts, E, nql, key_rows, key_nq);
+        hipLaunchKernelGGL(key_inner_kernel<B>, dim3((T.N + 255) / 256, E), dim3(256), 0, st, T, acc, ext, keys, E,
+                           nql, key_rows, key_nq);
     else if constexpr (B < kMaxDigits)
-        launch_key_inner<B + 1>(T, acc, ext, key, ncts, beta, E, nql, key_rows, key_nq, st);
+        launch_key_inner<B + 1>(T, acc, ext, keys, beta, E, nql, key_rows, key_nq, st);
 }
 
-void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const u64* key, int ncts, int beta, int ext_rows,
-                 int nq_level, int key_rows, int key_nq, int alpha, void* stream) {
-    (void)alpha;
+void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const KeyList& keys, int beta, int ext_rows,
+                 int nq_level, int key_rows, int key_nq, void* stream) {
     if (beta < 1 || beta > kMaxDigits) return;  // the digit count is checked when the context is built
-    // algorithmic bytes: the key once per launch, ext read and acc written per ciphertext
-    ProfScope ps(T.prof, PK_KEYIP, 8.0 * T.N * ext_rows * (2.0 * beta + ncts * (beta + 2.0)), stream);
-    launch_key_inner<1>(T, acc, ext, key, ncts, beta, ext_rows, nq_level, key_rows, key_nq, (hipStream_t)stream);
+    if (keys.n < 1 || keys.n > kMaxKeys || keys.per < 1) return;
+    // algorithmic bytes: each key once per launch, ext read and acc written per ciphertext
+    const double ncts = (double)keys.n * keys.per;
+    ProfScope ps(T.prof, PK_KEYIP, 8.0 * T.N * ext_rows * (2.0 * beta * keys.n + ncts * (beta + 2.0)), stream);
+    launch_key_inner<1>(T, acc, ext, keys, beta, ext_rows, nq_level, key_rows, key_nq, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------- sampling

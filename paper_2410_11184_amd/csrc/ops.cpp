@@ -244,7 +244,7 @@ static u64* ks_modup(Context& c, const Rows& d, int level) {
 
 // Inner product of the lifted digits with the key, then ModDown (centred
 // conversion of the P part, times P^-1); out_k = (add_k +) result_k.
-static void ks_finish(Context& c, const u64* ext, int m, int level, const u64* key, u64* out0, u64* out1,
+static void ks_finish(Context& c, const u64* ext, int m, int level, const KeyList& keys, u64* out0, u64* out1,
                       size_t out_gstride, const Rows* add0, const Rows* add1) {
     const int l = level;
     const int nql = l + 1;
@@ -253,7 +253,8 @@ static void ks_finish(Context& c, const u64* ext, int m, int level, const u64* k
     const size_t N = c.N;
     // inner product with the key: acc [m][2][E][N]
     u64* acc = c.alloc_words((size_t)m * 2 * E * N);
-    k_key_inner(c.T, acc, ext, key, m, beta, E, nql, c.nq + c.np, c.nq, c.np, c.stream);
+    HS_REQUIRE(keys.n * keys.per == m, E_ARG, "key switch: key list does not cover the batch");
+    k_key_inner(c.T, acc, ext, keys, beta, E, nql, c.nq + c.np, c.nq, c.stream);
     // ModDown
     Rows accp{acc + (size_t)nql * N, 2 * m, c.np, (size_t)E * N, 0, 0, c.nq};
     k_ntt(c.T, accp, true, c.stream);
@@ -288,7 +289,11 @@ static void ks_finish(Context& c, const u64* ext, int m, int level, const u64* k
 void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1, size_t out_gstride,
                 const Rows* add0, const Rows* add1) {
     u64* ext = ks_modup(c, d, level);
-    ks_finish(c, ext, d.ngroups, level, key, out0, out1, out_gstride, add0, add1);
+    KeyList kl;
+    kl.key[0] = key;
+    kl.n = 1;
+    kl.per = d.ngroups;
+    ks_finish(c, ext, d.ngroups, level, kl, out0, out1, out_gstride, add0, add1);
     c.free_words(ext);
 }
 
@@ -346,52 +351,80 @@ Ct op_rotate(Context& c, const Ct& a, int r) {
 
 Ct op_conjugate(Context& c, const Ct& a) { return op_apply_galois(c, a, 2 * c.N - 1); }
 
-// Rotations of one ciphertext sharing a single ModUp (hoisting): the
+// Rotations of one ciphertext batch sharing a single ModUp (hoisting): the
 // automorphism is a slot permutation in the NTT domain, the same for every
 // prime, so it commutes with the lifted digits, which are a valid lift of the
 // rotated digits.  The results decrypt like op_rotate's; their words differ
-// (another valid lift), so this is used where only the values matter.
-std::vector<Ct> op_rotate_hoisted(Context& c, const Ct& a, const std::vector<int>& rots) {
+// (another valid lift), so this is used where only the values matter.  All R
+// rotations go through one permutation launch, one inner product (a key per
+// rotation) and one ModDown; the result holds R a.m ciphertexts,
+// rotation-major.  No r may be a multiple of the slot count.
+Ct op_rotate_hoisted_batch(Context& c, const Ct& a, const std::vector<int>& rots) {
     HS_REQUIRE(a.ncomp == 2, E_ARG, "automorphism: degree-1 input expected");
-    std::vector<Ct> out;
+    const int R = (int)rots.size();
+    HS_REQUIRE(R >= 1 && R <= kMaxKeys, E_ARG, "hoisted rotations: 1 to 32 per batch");
     const int half = c.N / 2;
-    bool any = false;
-    for (int r : rots) any |= ((r % half) + half) % half != 0;
-    u64* ext = nullptr;
-    u64* extg = nullptr;
     const int nql = a.level + 1;
     const int E = nql + c.np;
     const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
-    const size_t ew = (size_t)a.m * beta * E * c.N;
-    if (any) {
-        ext = ks_modup(c, c.comp_rows(a, 1), a.level);
-        extg = c.alloc_words(ew);
-    }
-    for (int r : rots) {
-        if (((r % half) + half) % half == 0) {
-            out.push_back(ct_copy(c, a));
-            continue;
-        }
-        const int g = galois_rot(r, c.N);
+    const size_t N = c.N;
+    KeyList kl;
+    PermList pl;
+    kl.n = pl.n = R;
+    for (int i = 0; i < R; i++) {
+        HS_REQUIRE(((rots[i] % half) + half) % half != 0, E_ARG, "hoisted rotations: zero rotation");
+        const int g = galois_rot(rots[i], c.N);
         HS_REQUIRE(has_key(c, g), E_KEY, "Galois key missing");
-        const int* perm = c.perm(g);
-        Rows re_in{ext, a.m * beta, E, (size_t)E * c.N, E, 0, c.nq};
-        Rows re_out{extg, a.m * beta, E, (size_t)E * c.N, E, 0, c.nq};
-        k_permute(c.T, re_out, re_in, perm, c.stream);
-        Ct b0 = ct_alloc(c, a.m, 1, a.level);
-        k_permute(c.T, c.ct_rows(b0), c.comp_rows(a, 0), perm, c.stream);
-        Ct o = ct_alloc(c, a.m, 2, a.level);
-        o.scale = a.scale;
-        Rows rb0 = c.comp_rows(b0, 0);
-        ks_finish(c, extg, a.m, a.level, c.keys.at(g), o.d, o.d + o.comp_words(c.N), o.ct_words(c.N), &rb0, nullptr);
-        ct_free(c, b0);
-        out.push_back(o);
+        kl.key[i] = c.keys.at(g);
+        pl.perm[i] = c.perm(g);
     }
-    if (ext) {
-        c.free_words(ext);
-        c.free_words(extg);
+    u64* ext = ks_modup(c, c.comp_rows(a, 1), a.level);            // [m][beta][E][N]
+    u64* extg = c.alloc_words((size_t)R * a.m * beta * E * N);      // [R][m][beta][E][N]
+    pl.per = a.m * beta;
+    k_permute_multi(c.T, Rows{extg, R * a.m * beta, E, (size_t)E * N, E, 0, c.nq},
+                    Rows{ext, a.m * beta, E, (size_t)E * N, E, 0, c.nq}, pl, c.stream);
+    c.free_words(ext);
+    Ct b0 = ct_alloc(c, R * a.m, 1, a.level);                       // rotated first components
+    pl.per = a.m;
+    k_permute_multi(c.T, c.ct_rows(b0), c.comp_rows(a, 0), pl, c.stream);
+    Ct o = ct_alloc(c, R * a.m, 2, a.level);
+    o.scale = a.scale;
+    kl.per = a.m;
+    Rows rb0 = c.comp_rows(b0, 0);
+    ks_finish(c, extg, R * a.m, a.level, kl, o.d, o.d + o.comp_words(N), o.ct_words(N), &rb0, nullptr);
+    ct_free(c, b0);
+    c.free_words(extg);
+    return o;
+}
+
+// Automorphisms of a batch: block i (per ciphertexts) by Galois element
+// gal[i], each exactly as op_apply_galois, with one permutation, ModUp,
+// inner product and ModDown for the whole batch.
+Ct op_galois_batch(Context& c, const Ct& a, const std::vector<int>& gal, int per) {
+    HS_REQUIRE(a.ncomp == 2, E_ARG, "automorphism: degree-1 input expected");
+    const int G = (int)gal.size();
+    HS_REQUIRE(G >= 1 && G <= kMaxKeys && per >= 1 && a.m == G * per, E_ARG, "automorphism batch: bad shape");
+    KeyList kl;
+    PermList pl;
+    kl.n = pl.n = G;
+    kl.per = pl.per = per;
+    for (int i = 0; i < G; i++) {
+        const int g = ((gal[i] % (2 * c.N)) + 2 * c.N) % (2 * c.N);
+        HS_REQUIRE(has_key(c, g), E_KEY, "Galois key missing");
+        kl.key[i] = c.keys.at(g);
+        pl.perm[i] = c.perm(g);
     }
-    return out;
+    const size_t N = c.N;
+    Ct b = ct_alloc(c, a.m, 2, a.level);
+    for (int k = 0; k < 2; k++) k_permute_multi(c.T, c.comp_rows(b, k), c.comp_rows(a, k), pl, c.stream);
+    u64* ext = ks_modup(c, c.comp_rows(b, 1), a.level);
+    Ct o = ct_alloc(c, a.m, 2, a.level);
+    o.scale = a.scale;
+    Rows b0 = c.comp_rows(b, 0);
+    ks_finish(c, ext, a.m, a.level, kl, o.d, o.d + o.comp_words(N), o.ct_words(N), &b0, nullptr);
+    c.free_words(ext);
+    ct_free(c, b);
+    return o;
 }
 
 Ct op_mod_raise(Context& c, const Ct& a, int level) {
