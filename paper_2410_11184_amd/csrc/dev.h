@@ -129,6 +129,16 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream);
 double k_mul_rate(void* stream);
 // x = NTT(src) (or its inverse); src has x's shape and may be x itself
 void k_ntt_from(const DevTables& T, const Rows& x, const Rows& src, bool inverse, void* stream);
+// Rows of a ModUp extension that the N = 2^16 forward transform leaves out:
+// group G (ciphertext-major, digit G mod per) skips rows [lo, hi) with
+// lo = (G mod per) digit, hi = min(lo + digit, nql) (the digit's own rows,
+// already in the NTT domain).  per = 0: no rows are skipped.
+struct NttSkip {
+    int per = 0;
+    int digit = 0;
+    int nql = 0;
+};
+void k_ntt_skip(const DevTables& T, const Rows& x, const NttSkip& skip, void* stream);
 // forward NTT of x followed by the epilogue (x is left unspecified)
 void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream);
 void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
@@ -173,8 +183,11 @@ struct KeyList {
     int n;
     int per;
 };
+// own rows (ConvTables::own_row) are copied from own_in (group stride
+// own_gstride, same row indices as in) when it is given, else from in
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride,
-                    const u64* in, size_t in_gstride, int ngroups, void* stream);
+                    const u64* in, size_t in_gstride, int ngroups, void* stream, const u64* own_in = nullptr,
+                    size_t own_gstride = 0);
 // centred lift of one row (prime src_prime, coefficient domain) of each
 // group to the rows of `out` (coefficient domain)
 void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t in_gstride,

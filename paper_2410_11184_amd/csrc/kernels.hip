@@ -95,7 +95,7 @@ struct ProfScope {
 };
 
 // autotuner decisions (defined with the tuner below)
-int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st);
+int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st, const NttSkip* skip = nullptr);
 int tune_conv(const DevTables& T, const ConvTables& C, size_t og, size_t ig, int ngroups, hipStream_t st);
 
 // ------------------------------------------------------------- arithmetic
@@ -357,9 +357,19 @@ __device__ __forceinline__ int ntt_row_prime_major(const Rows& x, int y) {
     return g * x.rpg + y / x.ngroups;
 }
 
-// row visited by workgroup row y: prime-major (order 0) or in storage order (1)
-__device__ __forceinline__ int ntt_row(const Rows& x, int y, int order) {
-    return order ? y : ntt_row_prime_major(x, y);
+// row visited by workgroup row y: prime-major (order 0) or in storage order
+// (1); with a skip, y enumerates only the transformed rows (vrows per group,
+// rows of groups with fewer get -1) and g0 is the launch's first group
+__device__ __forceinline__ int ntt_row(const Rows& x, int y, int order, const NttSkip& sk, int g0) {
+    if (!sk.per) return order ? y : ntt_row_prime_major(x, y);
+    const int own_min = sk.nql - ((sk.nql - 1) / sk.digit) * sk.digit;
+    const int V = x.rpg - own_min;
+    const int g = order ? y / V : y % x.ngroups;
+    const int rv = order ? y % V : y / x.ngroups;
+    const int lo = ((g0 + g) % sk.per) * sk.digit;
+    const int own = min(lo + sk.digit, sk.nql) - lo;
+    const int r = rv < lo ? rv : rv + own;
+    return r < x.rpg ? g * x.rpg + r : -1;
 }
 
 // Lazy (Harvey) butterflies: a*w - floor(a*ws/2^64)*q lies in [0, 2q) for
@@ -432,9 +442,11 @@ __device__ __forceinline__ u64 reduce4q(u64 x, u64 q) {
 // pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
 #define NTT16_LDS (16 * 272)
 
-__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order) {
+__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+                                                       NttSkip sk, int g0) {
     __shared__ u64 sm[NTT16_LDS];
-    const int row = ntt_row(x, blockIdx.y, order);
+    const int row = ntt_row(x, blockIdx.y, order, sk, g0);
+    if (row < 0) return;   // whole workgroup
     u64* p = row_ptr(x, row, 65536) + blockIdx.x * 16;
     const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * 16;
     const int pi = prime_of(x, row % x.rpg);
@@ -477,9 +489,10 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
 
 template <bool EPI>
 __global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
-                                                       NttEpilogue Ep) {
+                                                       NttEpilogue Ep, NttSkip sk) {
     __shared__ u64 sm[NTT16_LDS];
-    const int row = ntt_row(x, blockIdx.y, order);
+    const int row = ntt_row(x, blockIdx.y, order, sk, Ep.g0);
+    if (row < 0) return;   // whole workgroup
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
     const int t = threadIdx.x, w = t >> 4, l = t & 15;
@@ -551,9 +564,10 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) { k_nt
 // variant & 2 splits the launch into batches of kNttGroupBatch row groups.
 constexpr int kNttGroupBatch = 8;
 static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, bool inverse, int variant,
-                         hipStream_t st, const NttEpilogue* epi = nullptr) {
+                         hipStream_t st, const NttEpilogue* epi = nullptr, const NttSkip& sk = NttSkip()) {
     const int order = variant & 1;
     const int gb = (variant & 2) ? kNttGroupBatch : x.ngroups;
+    const int vrows = sk.per ? x.rpg - (sk.nql - ((sk.nql - 1) / sk.digit) * sk.digit) : x.rpg;
     NttEpilogue e;
     if (epi) e = *epi;
     for (int g0 = 0; g0 < x.ngroups; g0 += gb) {
@@ -562,18 +576,31 @@ static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, boo
         ss.base = src.base + (size_t)g0 * src.gstride;
         xs.ngroups = ss.ngroups = std::min(gb, x.ngroups - g0);
         e.g0 = g0;
-        const dim3 g(16, xs.ngroups * xs.rpg);
+        const dim3 g(16, xs.ngroups * vrows);
         if (!inverse) {
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0);
             if (epi)
-                hipLaunchKernelGGL(ntt16_p2_kernel<true>, g, dim3(256), 0, st, T, xs, xs, 0, order, e);
+                hipLaunchKernelGGL(ntt16_p2_kernel<true>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
             else
-                hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, xs, 0, order, e);
+                hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
         } else {
-            hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, ss, 1, order, e);
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order);
+            hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, ss, 1, order, e, sk);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0);
         }
     }
+}
+
+void k_ntt_skip(const DevTables& T, const Rows& x, const NttSkip& skip, void* stream) {
+    if (x.ngroups * x.rpg == 0) return;
+    if (T.logN != 16 || !skip.per) {
+        k_ntt(T, x, false, stream);
+        return;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int variant = tune_ntt16(T, x, false, st, &skip);
+    const int rows = x.ngroups * x.rpg - (x.ngroups / skip.per) * skip.nql;   // transformed rows
+    ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * rows, stream);
+    ntt16_launch(T, x, x, false, variant, st, nullptr, skip);
 }
 
 void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream) {
@@ -893,7 +920,8 @@ __device__ __forceinline__ unsigned __int128 conv_sum(const u32 (&x0)[K], const 
 
 template <int K>
 __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTables C, u64* out, size_t og,
-                                                           const u64* in, size_t ig) {
+                                                           const u64* in, size_t ig, const u64* own_in,
+                                                           size_t own_ig) {
     __shared__ u64 s_hl[K * kMaxConvDst];        // (h1 << 32) | h0
     __shared__ u32 s_h2[K * kMaxConvDst];
     __shared__ u64 s_q[kMaxConvDst], s_r64[kMaxConvDst], s_r64s[kMaxConvDst], s_one[kMaxConvDst],
@@ -927,7 +955,8 @@ __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTabl
     for (int s = 0; s < K; s++) {
         const u64 x = in[(size_t)g * ig + (size_t)C.src_row[s] * N + i];
         if (C.own_row && C.own_row[s] >= 0 && blockIdx.z == 0)
-            out[(size_t)g * og + (size_t)C.own_row[s] * N + i] = x;
+            out[(size_t)g * og + (size_t)C.own_row[s] * N + i] =
+                own_in ? own_in[(size_t)g * own_ig + (size_t)C.src_row[s] * N + i] : x;
         const u64 d = T.prime[C.src_prime[s]].q;
         const u64 xh = mul_shoup(x, C.inv_hat[s], C.inv_hat_s[s], d);
         // centred: xh - d_s contributes xh * hat - D
@@ -969,7 +998,8 @@ constexpr int kConvPlaneLds = 56 * 1024; // bytes of B operands one workgroup st
 
 template <int KS>
 __global__ void __launch_bounds__(256) base_convert_mfma_kernel(DevTables T, ConvTables C, u64* out, size_t og,
-                                                                const u64* in, size_t ig) {
+                                                                const u64* in, size_t ig, const u64* own_in,
+                                                                size_t own_ig) {
     extern __shared__ u64 sB[];          // [ntb][KS][8][64]
     __shared__ u64 s_q[kMaxConvDst], s_mu[kMaxConvDst], s_c48[kMaxConvDst], s_c48s[kMaxConvDst],
         s_dmod[kMaxConvDst];
@@ -1003,7 +1033,9 @@ __global__ void __launch_bounds__(256) base_convert_mfma_kernel(DevTables T, Con
             u64 x = 0;
             if (s < C.k) {
                 const u64 v = in[(size_t)g * ig + (size_t)C.src_row[s] * N + base + col];
-                if (C.own_row && C.own_row[s] >= 0) out[(size_t)g * og + (size_t)C.own_row[s] * N + base + col] = v;
+                if (C.own_row && C.own_row[s] >= 0)
+                    out[(size_t)g * og + (size_t)C.own_row[s] * N + base + col] =
+                        own_in ? own_in[(size_t)g * own_ig + (size_t)C.src_row[s] * N + base + col] : v;
                 const u64 d = T.prime[C.src_prime[s]].q;
                 x = mul_shoup(v, C.inv_hat[s], C.inv_hat_s[s], d);
                 if (C.centered && x > (d - 1) / 2) neg++;
@@ -1056,25 +1088,26 @@ __global__ void __launch_bounds__(256) base_convert_mfma_kernel(DevTables T, Con
 
 template <int KS>
 static void launch_base_convert_mfma(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in,
-                                     size_t ig, int ngroups, hipStream_t st) {
+                                     size_t ig, int ngroups, const u64* own_in, size_t own_ig, hipStream_t st) {
     if (C.nks == KS) {
         const int per_block = 4 * kConvTiles * 16;
         const size_t lds = (size_t)C.ntb * KS * 8 * 64 * sizeof(u64);
         hipLaunchKernelGGL(base_convert_mfma_kernel<KS>, dim3((T.N + per_block - 1) / per_block, ngroups),
-                           dim3(256), lds, st, T, C, out, og, in, ig);
+                           dim3(256), lds, st, T, C, out, og, in, ig, own_in, own_ig);
     } else if constexpr (KS < kMaxConvSrc / 4) {
-        launch_base_convert_mfma<KS + 1>(T, C, out, og, in, ig, ngroups, st);
+        launch_base_convert_mfma<KS + 1>(T, C, out, og, in, ig, ngroups, own_in, own_ig, st);
     }
 }
 
 template <int K>
 static void launch_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in,
-                                size_t ig, int ngroups, int split, hipStream_t st) {
+                                size_t ig, int ngroups, int split, const u64* own_in, size_t own_ig,
+                                hipStream_t st) {
     if (C.k == K)
         hipLaunchKernelGGL(base_convert_kernel<K>, dim3((T.N + 255) / 256, ngroups, split), dim3(256), 0, st, T, C,
-                           out, og, in, ig);
+                           out, og, in, ig, own_in, own_ig);
     else if constexpr (K < kMaxConvSrc)
-        launch_base_convert<K + 1>(T, C, out, og, in, ig, ngroups, split, st);
+        launch_base_convert<K + 1>(T, C, out, og, in, ig, ngroups, split, own_in, own_ig, st);
 }
 
 static bool conv_planes_fit(const DevTables& T, const ConvTables& C) {
@@ -1085,11 +1118,12 @@ static bool conv_planes_fit(const DevTables& T, const ConvTables& C) {
 // 2, 3: VALU kernel with the targets split over 2 or 4 threads per coefficient
 static const char* const kConvVariants[] = {"valu", "mfma", "valu/split2", "valu/split4"};
 static void conv_launch(const DevTables& T, const ConvTables& C, u64* out, size_t og, const u64* in, size_t ig,
-                        int ngroups, int variant, hipStream_t st) {
+                        int ngroups, int variant, hipStream_t st, const u64* own_in = nullptr, size_t own_ig = 0) {
     if (variant == 1 && conv_planes_fit(T, C))
-        launch_base_convert_mfma<1>(T, C, out, og, in, ig, ngroups, st);
+        launch_base_convert_mfma<1>(T, C, out, og, in, ig, ngroups, own_in, own_ig, st);
     else
-        launch_base_convert<1>(T, C, out, og, in, ig, ngroups, variant == 2 ? 2 : variant == 3 ? 4 : 1, st);
+        launch_base_convert<1>(T, C, out, og, in, ig, ngroups, variant == 2 ? 2 : variant == 3 ? 4 : 1, own_in,
+                               own_ig, st);
 }
 
 // ------------------------------------------------------------- autotuner
@@ -1237,10 +1271,13 @@ int tune_conv(const DevTables& T, const ConvTables& C, size_t og, size_t ig, int
                     [&](int c, const u64* in, u64* out) { conv_launch(T, C, out, og, in, ig, gq, c, st); });
 }
 
-int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st) {
-    const int gq = pow2_bucket(x.ngroups);
+int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st, const NttSkip* skip) {
+    // a skipping launch tunes over whole groups of its digit pattern
+    const int gq = skip && skip->per ? ((pow2_bucket(x.ngroups) + skip->per - 1) / skip->per) * skip->per
+                                     : pow2_bucket(x.ngroups);
     const std::string key = "ntt N=" + std::to_string(T.N) + " rows=" + std::to_string(x.rpg) + " groups=" +
-                            std::to_string(gq) + (inverse ? " inverse" : " forward");
+                            std::to_string(gq) + (inverse ? " inverse" : " forward") +
+                            (skip && skip->per ? " skip-own-digit" : "");
     const int v = tune_lookup(key);
     if (v >= 0 || !tuning_on()) return v < 0 ? 0 : v;
     const size_t words = (size_t)gq * x.rpg * T.N;
@@ -1251,7 +1288,7 @@ int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st) 
                         r.base = buf;
                         r.gstride = (size_t)x.rpg * T.N;
                         r.ngroups = gq;
-                        ntt16_launch(T, r, r, inverse, c, st);
+                        ntt16_launch(T, r, r, inverse, c, st, nullptr, skip ? *skip : NttSkip());
                     });
 }
 
@@ -1316,12 +1353,12 @@ int tune_load(const std::string& text) {
 }
 
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride, const u64* in,
-                    size_t in_gstride, int ngroups, void* stream) {
+                    size_t in_gstride, int ngroups, void* stream, const u64* own_in, size_t own_gstride) {
     if (ngroups == 0 || C.m == 0) return;
     if (C.k < 1 || C.k > kMaxConvSrc || C.m > kMaxConvDst) return;  // tables are checked when built
     const int variant = tune_conv(T, C, out_gstride, in_gstride, ngroups, (hipStream_t)stream);
     ProfScope ps(T.prof, PK_CONV, 8.0 * T.N * ngroups * (double)(C.k + C.m), stream);
-    conv_launch(T, C, out, out_gstride, in, in_gstride, ngroups, variant, (hipStream_t)stream);
+    conv_launch(T, C, out, out_gstride, in, in_gstride, ngroups, variant, (hipStream_t)stream, own_in, own_gstride);
 }
 
 // centred lift: v = x if x <= (q_s - 1)/2 else x - q_s, reduced mod each row's prime

@@ -227,18 +227,27 @@ static u64* ks_modup(Context& c, const Rows& d, int level) {
     k_ntt_from(c.T, rdc, d, true, c.stream);
     u64* ext = c.alloc_words((size_t)m * beta * E * N);
     const size_t xg = (size_t)beta * E * N;
+    // at N = 2^16 the digit's own rows are taken from d (already in the NTT
+    // domain) and the one forward launch skips them; elsewhere they are
+    // copied in the coefficient domain and transformed with the others
+    const bool skip = c.logN == 16;
     for (int j = 0; j < beta; j++) {
         // every row of digit j's extension: the conversion writes the other
         // primes and copies the digit's own rows
         u64* xj = ext + (size_t)j * E * N;
         const ConvDev& cv = c.modup_tables(l, j);
-        k_base_convert(c.T, cv.t, xj, xg, dc, (size_t)nql * N, m, c.stream);
+        k_base_convert(c.T, cv.t, xj, xg, dc, (size_t)nql * N, m, c.stream, skip ? d.base : nullptr, d.gstride);
     }
     c.free_words(dc);
-    // one launch for every row of every digit (the digit's own rows come
-    // back to d's values; a launch per row range would under-fill the GPU
-    // for single ciphertexts)
-    k_ntt(c.T, Rows{ext, m * beta, E, (size_t)E * N, nql, 0, c.nq}, false, c.stream);
+    // one launch for every row of every digit (a launch per row range would
+    // under-fill the GPU for single ciphertexts)
+    NttSkip sk;
+    if (skip) {
+        sk.per = beta;
+        sk.digit = c.prm.digit;
+        sk.nql = nql;
+    }
+    k_ntt_skip(c.T, Rows{ext, m * beta, E, (size_t)E * N, nql, 0, c.nq}, sk, c.stream);
     return ext;
 }
 
