@@ -166,6 +166,17 @@ hs_status hs_rescale(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
 hs_status hs_mult_relin(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, int rescale, hs_ct** out);
 /* Rot (Section 2.2): left rotation of the slots by r (needs its key). */
 hs_status hs_rotate(hs_ctx* ctx, const hs_ct* a, int32_t r, hs_ct** out);
+/* Rot by several offsets of one ciphertext sharing one ModUp (hoisting; the
+ * linear transforms of the bootstrap, Section 5.1, use it): out[i] decrypts
+ * to Rot(a, rots[i]).  The words differ from hs_rotate's (another valid lift
+ * of the rotated digits).  1 <= n <= 32, no rots[i] a multiple of the slot
+ * count (HS_E_ARG), every key present (HS_E_KEY); writes n new handles. */
+hs_status hs_rotate_hoisted(hs_ctx* ctx, const hs_ct* a, const int32_t* rots, size_t n, hs_ct** out);
+/* Rot of n ciphertexts of one level and scale, a[i] by rots[i], as one batched
+ * key switch (one ModUp, inner product with a key per ciphertext, ModDown);
+ * out[i] equals hs_rotate(a[i], rots[i]) word for word.  1 <= n <= 32;
+ * errors as hs_rotate_hoisted, HS_E_LEVEL / HS_E_SCALE for mixed inputs. */
+hs_status hs_rotate_batch(hs_ctx* ctx, const hs_ct* const* a, const int32_t* rots, size_t n, hs_ct** out);
 /* Complex conjugation of every slot (needs the conjugation key). */
 hs_status hs_conjugate(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
 /* Multiply by NTT-domain plaintext residues pt[(a.level+1) * N] whose scale

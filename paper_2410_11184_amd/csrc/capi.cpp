@@ -433,6 +433,58 @@ hs_status hs_rotate(hs_ctx* ctx, const hs_ct* a, int32_t r, hs_ct** out) {
     });
 }
 
+hs_status hs_rotate_hoisted(hs_ctx* ctx, const hs_ct* a, const int32_t* rots, size_t n, hs_ct** out) {
+    if (out)
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(rots);
+        NEED(out);
+        HS_REQUIRE(n >= 1 && n <= (size_t)hs::kMaxKeys, hs::E_ARG, "1 to 32 rotations");
+        hs::Context& c = *ctx->c;
+        const std::vector<int> rs(rots, rots + n);
+        hs::Ct b = hs::op_rotate_hoisted_batch(c, a->ct, rs);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(&c, hs::ct_slice(c, b, (int)(i * a->ct.m), a->ct.m));
+        hs::ct_free(c, b);
+    });
+}
+
+hs_status hs_rotate_batch(hs_ctx* ctx, const hs_ct* const* a, const int32_t* rots, size_t n, hs_ct** out) {
+    if (out)
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(rots);
+        NEED(out);
+        HS_REQUIRE(n >= 1 && n <= (size_t)hs::kMaxKeys, hs::E_ARG, "1 to 32 ciphertexts");
+        hs::Context& c = *ctx->c;
+        std::vector<const hs::Ct*> parts;
+        std::vector<int> gal;
+        const int half = c.N / 2;
+        for (size_t i = 0; i < n; i++) {
+            NEED(a[i]);
+            HS_REQUIRE(a[i]->ct.m == 1, hs::E_ARG, "one ciphertext per handle");
+            HS_REQUIRE(a[i]->ct.scale == a[0]->ct.scale, hs::E_SCALE, "inputs must share one scale");
+            HS_REQUIRE(((rots[i] % half) + half) % half != 0, hs::E_ARG, "zero rotation");
+            parts.push_back(&a[i]->ct);
+            gal.push_back(hs::galois_rot(rots[i], c.N));
+        }
+        hs::Ct in = hs::ct_gather(c, parts);   // checks the levels
+        hs::Ct b;
+        try {
+            b = hs::op_galois_batch(c, in, gal, 1);
+        } catch (...) {
+            hs::ct_free(c, in);
+            throw;
+        }
+        hs::ct_free(c, in);
+        for (size_t i = 0; i < n; i++) out[i] = wrap(&c, hs::ct_slice(c, b, (int)i, 1));
+        hs::ct_free(c, b);
+    });
+}
+
 UNARY_OP(hs_conjugate, hs::op_conjugate(c, a->ct))
 
 hs_status hs_mul_plain_rows(hs_ctx* ctx, const hs_ct* a, const uint64_t* pt, double pt_scale, int rescale,

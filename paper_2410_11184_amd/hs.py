@@ -95,6 +95,9 @@ def lib():
         "hs_rescale": [_vp, _vp, ctypes.POINTER(_vp)],
         "hs_mult_relin": [_vp, _vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_rotate": [_vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
+        "hs_rotate_hoisted": [_vp, _vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, ctypes.POINTER(_vp)],
+        "hs_rotate_batch": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
+                            ctypes.POINTER(_vp)],
         "hs_conjugate": [_vp, _vp, ctypes.POINTER(_vp)],
         "hs_mul_plain_rows": [_vp, _vp, _u64p, ctypes.c_double, S, ctypes.POINTER(_vp)],
         "hs_mul_int": [_vp, _vp, ctypes.c_int64, ctypes.POINTER(_vp)],
@@ -404,6 +407,23 @@ class Context:
 
     def rotate(self, a, r):
         return self._op("hs_rotate", a.h, r)
+
+    def rotate_hoisted(self, a, rots):
+        """hs_rotate_hoisted: rotations of `a` by every r in rots, one ModUp."""
+        n = len(rots)
+        rs = (ctypes.c_int32 * n)(*rots)
+        out = (_vp * n)()
+        _check(lib().hs_rotate_hoisted(self.h, a.h, rs, n, out))
+        return [Ciphertext(self, _vp(out[i])) for i in range(n)]
+
+    def rotate_batch(self, cts, rots):
+        """hs_rotate_batch: cts[i] rotated by rots[i], one batched key switch."""
+        n = len(cts)
+        arr = (_vp * n)(*[c.h for c in cts])
+        rs = (ctypes.c_int32 * n)(*rots)
+        out = (_vp * n)()
+        _check(lib().hs_rotate_batch(self.h, arr, rs, n, out))
+        return [Ciphertext(self, _vp(out[i])) for i in range(n)]
 
     def conjugate(self, a):
         return self._op("hs_conjugate", a.h)

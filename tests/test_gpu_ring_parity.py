@@ -139,6 +139,32 @@ def test_conjugate(pair, cts):
     assert np.max(np.abs(g.decrypt(out) - np.conj(za))) < 2 ** -18
 
 
+def test_rotate_batch_matches_the_oracle(pair, cts):
+    # several ciphertexts, each with its own rotation, in one key switch
+    g, o = pair
+    ga, gb, oa, ob, za, zb = cts
+    outs = g.rotate_batch([ga, gb, ga, gb], [1, -3, 1000, 128])
+    for out, (oc, r) in zip(outs, [(oa, 1), (ob, -3), (oa, 1000), (ob, 128)]):
+        _same(out, o.rotate(oc, r))
+
+
+def test_rotate_hoisted_values(pair, cts):
+    # one ModUp for all rotations: another valid lift, same values
+    from paper_2410_11184_amd import hs
+    g, o = pair
+    ga, _, _, _, za, _ = cts
+    rots = [1, -3, 128, 1000]
+    for out, r in zip(g.rotate_hoisted(ga, rots), rots):
+        assert out.level == ga.level and out.scale == ga.scale
+        assert np.max(np.abs(g.decrypt(out) - np.roll(za, -r))) < 2 ** -18
+    with pytest.raises(hs.HSError) as e:
+        g.rotate_hoisted(ga, [1, g.slots])
+    assert e.value.name == "HS_E_ARG"
+    with pytest.raises(hs.HSError) as e:
+        g.rotate_hoisted(ga, [5])
+    assert e.value.name == "HS_E_KEY"
+
+
 def test_constants_and_plain(pair, cts):
     g, o = pair
     ga, _, oa, _, za, _ = cts
