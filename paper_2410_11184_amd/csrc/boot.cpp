@@ -535,13 +535,9 @@ Ct bootstrap_stage(Context& c, const Ct& x, double bound, int stop, int mask_L) 
     Ct z;
     {
         const double Dp = Db * std::pow(kfac, -std::ldexp(1.0, -(bp.double_angle + 1)));
-        std::vector<Ct> pq = eval_cheb_many(c, u, {&B.pcos, &B.psin}, Dp);
+        // cos + i sin as one polynomial with complex coefficients
+        z = eval_cheb_complex(c, u, B.pcos, B.psin, Dp);
         ct_free(c, u);
-        Ct is = op_mul_monomial(c, pq[1], c.N / 2);
-        z = op_add(c, pq[0], is);
-        ct_free(c, is);
-        ct_free(c, pq[0]);
-        ct_free(c, pq[1]);
     }
     if (stop == 4) {
         Ct r = ct_slice(c, z, 0, m);

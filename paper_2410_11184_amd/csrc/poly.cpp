@@ -15,6 +15,7 @@
 //    Depth: ceil(log2(d+1)) + 1 (the +1 is the leaf's constant products).
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <functional>
 #include <map>
 
@@ -67,9 +68,11 @@ int cheb_depth(int degree) { return ceil_log2(degree + 1) + 1; }
 // ---------------------------------------------------------------- evaluator
 namespace {
 
+using cplx = std::complex<double>;
+
 struct Val {
     bool is_const = false;
-    double cval = 0;
+    cplx cval = 0;
     Ct ct;
 };
 
@@ -151,8 +154,42 @@ struct Evaluator {
         }
     }
 
-    // sum_j coef[j] T_j at (scale S, level lv); one rescale
-    Val leaf(const std::vector<double>& coef, double S, int lv) {
+    // round(value S q_(lv+1) / tj.scale) as residues of the primes 0..lv+1
+    std::vector<u64> const_residues(double value, double S, int lv, double tscale) {
+        const double K = std::rint(value * S * (double)c.primes[lv + 1] / tscale);
+        std::vector<u64> res(lv + 2);
+        const bool neg = K < 0;
+        const double a = std::fabs(K);
+        for (int i = 0; i <= lv + 1; i++) {
+            const u64 q = c.primes[i];
+            u64 m;
+            if (a < 9.2e18) {
+                m = (u64)a % q;
+            } else {
+                int e;
+                const double mant = std::frexp(a, &e);
+                const u64 mi = (u64)std::ldexp(mant, 53);
+                m = mulmod_h(mi % q, powmod_h(2, (u64)(e - 53), q), q);
+            }
+            res[i] = (neg && m) ? q - m : m;
+        }
+        return res;
+    }
+
+    static void accumulate(Context& c, Ct& acc, bool& have, Ct& t) {
+        if (!have) {
+            acc = t;
+            have = true;
+        } else {
+            op_add_inplace(c, acc, t);
+            ct_free(c, t);
+        }
+    }
+
+    // sum_j coef[j] T_j at (scale S, level lv); one rescale.  Imaginary
+    // parts are summed apart and multiplied by X^(N/2), which multiplies
+    // every slot by i exactly (no level, no noise).
+    Val leaf(const std::vector<cplx>& coef, double S, int lv) {
         int deg = (int)coef.size() - 1;
         while (deg > 0 && coef[deg] == 0.0) deg--;
         Val v;
@@ -162,74 +199,73 @@ struct Evaluator {
             return v;
         }
         const double ql = (double)c.primes[lv + 1];
-        Ct acc;
-        bool have = false;
+        Ct acc, acci;
+        bool have = false, havei = false;
         for (int j = 1; j <= deg; j++) {
             if (coef[j] == 0.0) continue;
             build_T(j);
             const Ct& tj = T.at(j);
             HS_REQUIRE(tj.level >= lv + 1, E_LEVEL, "polynomial evaluation: level budget exhausted");
-            Ct d = ct_drop(c, tj, lv + 1);
-            if (mask) {
-                Ct md = mul_mask(d, coef[j], S * ql / tj.scale);
-                ct_free(c, d);
-                md.scale = S * ql;
-                if (!have) {
-                    acc = md;
-                    have = true;
-                } else {
-                    op_add_inplace(c, acc, md);
-                    ct_free(c, md);
+            for (int part = 0; part < 2; part++) {
+                const double value = part == 0 ? coef[j].real() : coef[j].imag();
+                if (value == 0.0) continue;
+                Ct d = ct_drop(c, tj, lv + 1);
+                if (mask) {
+                    HS_REQUIRE(part == 0, E_ARG, "masked evaluation takes real coefficients");
+                    Ct md = mul_mask(d, value, S * ql / tj.scale);
+                    ct_free(c, d);
+                    md.scale = S * ql;
+                    accumulate(c, acc, have, md);
+                    continue;
                 }
-                continue;
-            }
-            const double K = std::rint(coef[j] * S * ql / tj.scale);
-            std::vector<u64> res(lv + 2);
-            {
-                const bool neg = K < 0;
-                const double a = std::fabs(K);
-                for (int i = 0; i <= lv + 1; i++) {
-                    const u64 q = c.primes[i];
-                    u64 m;
-                    if (a < 9.2e18) {
-                        m = (u64)a % q;
-                    } else {
-                        int e;
-                        const double mant = std::frexp(a, &e);
-                        const u64 mi = (u64)std::ldexp(mant, 53);
-                        m = mulmod_h(mi % q, powmod_h(2, (u64)(e - 53), q), q);
-                    }
-                    res[i] = (neg && m) ? q - m : m;
-                }
-            }
-            op_mul_residues_inplace(c, d, res);
-            d.scale = S * ql;
-            if (!have) {
-                acc = d;
-                have = true;
-            } else {
-                op_add_inplace(c, acc, d);
-                ct_free(c, d);
+                op_mul_residues_inplace(c, d, const_residues(value, S, lv, tj.scale));
+                d.scale = S * ql;
+                if (part == 0) accumulate(c, acc, have, d);
+                else accumulate(c, acci, havei, d);
             }
         }
-        if (mask) add_mask_const(acc, coef[0]);
-        else op_add_const_inplace(c, acc, coef[0]);
+        if (havei) {
+            Ct t = op_mul_monomial(c, acci, c.N / 2);
+            ct_free(c, acci);
+            accumulate(c, acc, have, t);
+        }
+        HS_REQUIRE(coef[0].imag() == 0.0, E_ARG, "polynomial evaluation: imaginary constant term");
+        if (mask) add_mask_const(acc, coef[0].real());
+        else op_add_const_inplace(c, acc, coef[0].real());
         v.ct = op_rescale(c, acc);
         ct_free(c, acc);
         v.ct.scale = S;
         return v;
     }
 
-    Val eval(const std::vector<double>& coef, double S, int lv) {
+    // g * cv at scale S (one rescale): real and imaginary parts apart
+    Ct mul_const_complex(const Ct& g, cplx cv, double S) {
+        Ct r;
+        bool have = false;
+        if (cv.real() != 0.0) {
+            Ct t = op_mul_const(c, g, cv.real(), S);
+            accumulate(c, r, have, t);
+        }
+        if (cv.imag() != 0.0) {
+            Ct t = op_mul_const(c, g, cv.imag(), S);
+            Ct ti = op_mul_monomial(c, t, c.N / 2);
+            ct_free(c, t);
+            accumulate(c, r, have, ti);
+        }
+        HS_REQUIRE(have, E_ARG, "polynomial evaluation: zero leading part");
+        return r;
+    }
+
+    Val eval(const std::vector<cplx>& coef, double S, int lv) {
         int deg = (int)coef.size() - 1;
         while (deg > 0 && coef[deg] == 0.0) deg--;
-        if (deg < B) return leaf(std::vector<double>(coef.begin(), coef.begin() + deg + 1), S, lv);
+        if (deg < B) return leaf(std::vector<cplx>(coef.begin(), coef.begin() + deg + 1), S, lv);
         int n = B;
         while (2 * n <= deg) n *= 2;
         // p = q_lo + q_hi T_n
-        std::vector<double> hi(deg - n + 1), lo(n);
+        std::vector<cplx> hi(deg - n + 1), lo(n);
         hi[0] = coef[n];
-        for (int k = 1; k <= deg - n; k++) hi[k] = 2 * coef[n + k];
+        for (int k = 1; k <= deg - n; k++) hi[k] = 2.0 * coef[n + k];
         for (int j = 0; j < n; j++) lo[j] = coef[j];
         for (int k = 1; k <= deg - n; k++) lo[n - k] -= coef[n + k];
         build_T(n);
@@ -240,12 +276,13 @@ struct Evaluator {
         Val out;
         Ct g = ct_drop(c, G, lv + 1);
         if (vh.is_const && mask) {
-            Ct t = mul_mask(g, vh.cval, S * ql / g.scale);
+            HS_REQUIRE(vh.cval.imag() == 0.0, E_ARG, "masked evaluation takes real coefficients");
+            Ct t = mul_mask(g, vh.cval.real(), S * ql / g.scale);
             out.ct = op_rescale(c, t);
             ct_free(c, t);
             out.ct.scale = S;
         } else if (vh.is_const) {
-            out.ct = op_mul_const(c, g, vh.cval, S);
+            out.ct = mul_const_complex(g, vh.cval, S);
         } else {
             Ct d = op_tensor(c, vh.ct, g);
             Ct r = op_relin(c, d);
@@ -257,10 +294,10 @@ struct Evaluator {
         }
         ct_free(c, g);
         Val vl = eval(lo, S, lv);
-        if (vl.is_const && mask) {
-            add_mask_const(out.ct, vl.cval);
-        } else if (vl.is_const) {
-            op_add_const_inplace(c, out.ct, vl.cval);
+        if (vl.is_const) {
+            HS_REQUIRE(vl.cval.imag() == 0.0, E_ARG, "polynomial evaluation: imaginary constant term");
+            if (mask) add_mask_const(out.ct, vl.cval.real());
+            else op_add_const_inplace(c, out.ct, vl.cval.real());
         } else {
             op_add_inplace(c, out.ct, vl.ct);
             ct_free(c, vl.ct);
@@ -287,11 +324,31 @@ std::vector<Ct> eval_cheb_many(Context& c, const Ct& x, const std::vector<const 
     ev.T[1] = ct_copy(c, x);
     std::vector<Ct> out;
     for (const ChebPoly* p : ps) {
-        Val v = ev.eval(p->c, target_scale, out_level);
+        Val v = ev.eval(std::vector<cplx>(p->c.begin(), p->c.end()), target_scale, out_level);
         HS_REQUIRE(!v.is_const, E_ARG, "constant polynomial");
         out.push_back(v.ct);
     }
     return out;
+}
+
+Ct eval_cheb_complex(Context& c, const Ct& x, const ChebPoly& re, const ChebPoly& im, double target_scale) {
+    HS_REQUIRE(re.a == -1.0 && re.b == 1.0 && im.a == -1.0 && im.b == 1.0, E_ARG,
+               "complex evaluation expects polynomials on [-1, 1]");
+    const size_t n = std::max(re.c.size(), im.c.size());
+    std::vector<cplx> coef(n, 0.0);
+    for (size_t j = 0; j < n; j++)
+        coef[j] = cplx(j < re.c.size() ? re.c[j] : 0.0, j < im.c.size() ? im.c[j] : 0.0);
+    const int d = (int)n - 1;
+    HS_REQUIRE(d >= 1, E_ARG, "polynomial degree must be >= 1");
+    const int t = ceil_log2(d + 1);
+    const int out_level = x.level - (t + 1);
+    HS_REQUIRE(out_level >= 0, E_LEVEL, "polynomial evaluation: level budget exhausted");
+    Evaluator ev(c);
+    ev.B = 1 << std::max(1, (t + 1) / 2);
+    ev.T[1] = ct_copy(c, x);
+    Val v = ev.eval(coef, target_scale, out_level);
+    HS_REQUIRE(!v.is_const, E_ARG, "constant polynomial");
+    return v.ct;
 }
 
 Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, const double* mask) {
@@ -319,7 +376,7 @@ Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, co
     ev.mask = mask;
     ev.B = 1 << std::max(1, (t + 1) / 2);
     ev.T[1] = u;
-    Val v = ev.eval(p.c, target_scale, out_level);
+    Val v = ev.eval(std::vector<cplx>(p.c.begin(), p.c.end()), target_scale, out_level);
     HS_REQUIRE(!v.is_const, E_ARG, "constant polynomial");
     return v.ct;
 }

@@ -24,5 +24,10 @@ Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, co
 // Several polynomials on [-1, 1] of one input, sharing the Chebyshev basis
 // T_j(x); every result sits at the same level and scale target_scale.
 std::vector<Ct> eval_cheb_many(Context& c, const Ct& x, const std::vector<const ChebPoly*>& ps, double target_scale);
+// re(x) + i im(x) for two polynomials on [-1, 1], as one polynomial with
+// complex coefficients (the imaginary parts through a product by X^(N/2),
+// which multiplies every slot by i): half the products of evaluating both.
+// Every constant term met must be real (HS_E_ARG otherwise).
+Ct eval_cheb_complex(Context& c, const Ct& x, const ChebPoly& re, const ChebPoly& im, double target_scale);
 
 }  // namespace hs
