@@ -487,8 +487,10 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
     }
 }
 
+// four waves per SIMD: the LDS tile (35 KB per workgroup) allows four
+// workgroups per CU, and 128 VGPRs (no spills) lets the registers follow
 template <bool EPI>
-__global__ void __launch_bounds__(256) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
                                                        NttEpilogue Ep, NttSkip sk) {
     __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row(x, blockIdx.y, order, sk, Ep.g0);
