@@ -308,29 +308,6 @@ struct Evaluator {
 
 }  // namespace
 
-std::vector<Ct> eval_cheb_many(Context& c, const Ct& x, const std::vector<const ChebPoly*>& ps, double target_scale) {
-    HS_REQUIRE(!ps.empty(), E_ARG, "no polynomial");
-    int d = 0;
-    for (const ChebPoly* p : ps) {
-        HS_REQUIRE(p->a == -1.0 && p->b == 1.0, E_ARG, "shared-basis evaluation expects polynomials on [-1, 1]");
-        d = std::max(d, (int)p->c.size() - 1);
-    }
-    HS_REQUIRE(d >= 1, E_ARG, "polynomial degree must be >= 1");
-    const int t = ceil_log2(d + 1);
-    const int out_level = x.level - (t + 1);
-    HS_REQUIRE(out_level >= 0, E_LEVEL, "polynomial evaluation: level budget exhausted");
-    Evaluator ev(c);
-    ev.B = 1 << std::max(1, (t + 1) / 2);
-    ev.T[1] = ct_copy(c, x);
-    std::vector<Ct> out;
-    for (const ChebPoly* p : ps) {
-        Val v = ev.eval(std::vector<cplx>(p->c.begin(), p->c.end()), target_scale, out_level);
-        HS_REQUIRE(!v.is_const, E_ARG, "constant polynomial");
-        out.push_back(v.ct);
-    }
-    return out;
-}
-
 Ct eval_cheb_complex(Context& c, const Ct& x, const ChebPoly& re, const ChebPoly& im, double target_scale) {
     HS_REQUIRE(re.a == -1.0 && re.b == 1.0 && im.a == -1.0 && im.b == 1.0, E_ARG,
                "complex evaluation expects polynomials on [-1, 1]");

@@ -21,9 +21,6 @@ int cheb_depth(int degree);   // levels used by eval_cheb (plus 1 if the affine 
 // laid out as encode_to lays out w), the result is p(x) * mask at no extra
 // level: every leaf constant becomes a masked plaintext.
 Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, const double* mask = nullptr);
-// Several polynomials on [-1, 1] of one input, sharing the Chebyshev basis
-// T_j(x); every result sits at the same level and scale target_scale.
-std::vector<Ct> eval_cheb_many(Context& c, const Ct& x, const std::vector<const ChebPoly*>& ps, double target_scale);
 // re(x) + i im(x) for two polynomials on [-1, 1], as one polynomial with
 // complex coefficients (the imaginary parts through a product by X^(N/2),
 // which multiplies every slot by i): half the products of evaluating both.
