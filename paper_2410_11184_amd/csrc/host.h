@@ -4,6 +4,7 @@
 #pragma once
 #include <cstdint>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -159,6 +160,12 @@ struct Context {
     std::map<int, u64*> monomials;                  // k -> NTT of X^k over all Q primes
     void* boot = nullptr;                           // bootstrapping tables (boot.cpp), built on first use
     std::map<int, double*> mask_coeffs;             // L -> coefficients of the slot mask [0, L)
+    // NTT-domain plaintexts rint(scale * mask) over rows 0..level, keyed by
+    // (mask, level, exact scale): a Softmax schedule meets the same ones in
+    // every job; kept up to kMaskCacheBytes
+    std::map<std::tuple<const double*, int, double>, u64*> mask_pts;
+    size_t mask_pts_bytes = 0;
+    static constexpr size_t kMaskCacheBytes = (size_t)4 << 30;
     std::vector<void*> owned;                       // device tables
     std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
 

@@ -86,29 +86,45 @@ struct Evaluator {
     // whole polynomial by the mask since mask^2 = mask.
     const double* mask = nullptr;
 
-    // NTT-domain rows 0..lv of rint(scale * mask), in a pool buffer
-    u64* mask_pt(double scale, int lv) {
-        u64* pt = c.alloc_words((size_t)(lv + 1) * c.N);
+    // NTT-domain rows 0..lv of rint(scale * mask): from the context's cache
+    // (built on first use, kept; *owned = false), else in a pool buffer the
+    // caller frees (*owned = true)
+    u64* mask_pt(double scale, int lv, bool* owned) {
+        const auto key = std::make_tuple(mask, lv, scale);
+        auto it = c.mask_pts.find(key);
+        *owned = false;
+        if (it != c.mask_pts.end()) return it->second;
+        const size_t bytes = sizeof(u64) * (size_t)(lv + 1) * c.N;
+        const bool keep = c.mask_pts_bytes + bytes <= Context::kMaskCacheBytes;
+        u64* pt = keep ? (u64*)c.persistent_alloc(bytes, "mask plaintext") : c.alloc_words((size_t)(lv + 1) * c.N);
         Rows r = c.rows(pt, 1, lv + 1, (size_t)(lv + 1) * c.N);
         k_encode_real(c.T, r, mask, 0, scale, c.stream);
         k_ntt(c.T, r, false, c.stream);
+        if (keep) {
+            c.mask_pts[key] = pt;
+            c.mask_pts_bytes += bytes;
+        } else {
+            *owned = true;
+        }
         return pt;
     }
 
     // a (level lv) * (value * mask) with the product at scale a.scale * pscale
     Ct mul_mask(const Ct& a, double value, double pscale) {
-        u64* pt = mask_pt(value * pscale, a.level);
+        bool owned;
+        u64* pt = mask_pt(value * pscale, a.level, &owned);
         Ct o = op_mul_plain(c, a, pt, pscale, false);
-        c.free_words(pt);
+        if (owned) c.free_words(pt);
         return o;
     }
 
     void add_mask_const(Ct& a, double value) {
-        u64* pt = mask_pt(value * a.scale, a.level);
+        bool owned;
+        u64* pt = mask_pt(value * a.scale, a.level, &owned);
         Rows r0 = c.comp_rows(a, 0);
         Rows rp{pt, a.m, a.level + 1, 0, a.level + 1, 0, c.nq};
         k_add(c.T, r0, r0, rp, c.stream);
-        c.free_words(pt);
+        if (owned) c.free_words(pt);
     }
 
     explicit Evaluator(Context& cc) : c(cc) {}
