@@ -151,6 +151,21 @@ void k_mul(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, vo
 constexpr int kMaxMacTerms = 16;
 void k_mul_plain_acc(const DevTables& T, u64* out, const u64* const* a, const u64* const* p, int nterms,
                      int groups, int rows, void* stream);
+// One leaf of a polynomial evaluation in one launch per 16 terms:
+// out[G][r] = sum_t a_t[G][r] * f_t(r) over rows r < rows of every group G
+// (a_t keeps arows rows per group: reading the first `rows` is the drop to
+// the output's level), f_t a plaintext row p[r] or, where p is null, the
+// integer (neg ? -1 : 1) mant 2^e reduced modulo q_r.
+struct LeafTerm {
+    const u64* a;
+    int arows;
+    const u64* p;
+    u64 mant;
+    int e;
+    int neg;
+};
+void k_leaf_mac(const DevTables& T, u64* out, int groups, int rows, const LeafTerm* terms, int nterms,
+                void* stream);
 void k_mul_add(const DevTables& T, const Rows& acc, const Rows& a, const Rows& b, void* stream);
 void k_mul_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream);
 void k_add_row_const(const DevTables& T, const Rows& out, const Rows& a, const RowConsts& c, void* stream);

@@ -165,7 +165,7 @@ struct Context {
     // every job; kept up to kMaskCacheBytes
     std::map<std::tuple<const double*, int, double>, u64*> mask_pts;
     size_t mask_pts_bytes = 0;
-    static constexpr size_t kMaskCacheBytes = (size_t)4 << 30;
+    static constexpr size_t kMaskCacheBytes = (size_t)8 << 30;
     std::vector<void*> owned;                       // device tables
     std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
 

@@ -771,6 +771,53 @@ void k_mul_plain_acc(const DevTables& T, u64* out, const u64* const* a, const u6
     }
 }
 
+struct LeafTerms {
+    LeafTerm t[kMaxMacTerms];
+    int n;
+};
+
+__global__ void leaf_mac_kernel(DevTables T, u64* out, LeafTerms L, int rows, int accumulate) {
+    __shared__ u64 sk[kMaxMacTerms];
+    const int R = blockIdx.y;
+    const int G = R / rows, r = R - G * rows;
+    const PrimeInfo P = T.prime[r];
+    // integer constants of the scalar terms, reduced modulo this row's prime
+    if (threadIdx.x < L.n && !L.t[threadIdx.x].p) {
+        const LeafTerm& lt = L.t[threadIdx.x];
+        u64 k = reduce64(lt.mant, P);
+        for (int s = 0; s < lt.e; s++) {
+            k <<= 1;
+            if (k >= P.q) k -= P.q;
+        }
+        sk[threadIdx.x] = (lt.neg && k) ? P.q - k : k;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = T.N;
+    if (i >= N) return;
+    const size_t o = (size_t)R * N + i;
+    unsigned __int128 w = accumulate ? out[o] : 0;
+    for (int t = 0; t < L.n; t++) {
+        const u64 av = L.t[t].a[((size_t)G * L.t[t].arows + r) * N + i];
+        const u64 f = L.t[t].p ? L.t[t].p[(size_t)r * N + i] : sk[t];
+        w += (unsigned __int128)av * f;
+    }
+    out[o] = reduce_wide(w, P, T.r64[r]);
+}
+
+void k_leaf_mac(const DevTables& T, u64* out, int groups, int rows, const LeafTerm* terms, int nterms,
+                void* stream) {
+    if (groups * rows == 0 || nterms == 0) return;
+    ProfScope ps(T.prof, PK_EW, 8.0 * T.N * groups * rows * (nterms + 1.0), stream);
+    for (int t0 = 0; t0 < nterms; t0 += kMaxMacTerms) {
+        LeafTerms L;
+        L.n = std::min(kMaxMacTerms, nterms - t0);
+        for (int t = 0; t < L.n; t++) L.t[t] = terms[t0 + t];
+        hipLaunchKernelGGL(leaf_mac_kernel, dim3((T.N + 255) / 256, groups * rows), dim3(256), 0,
+                           (hipStream_t)stream, T, out, L, rows, t0 > 0 ? 1 : 0);
+    }
+}
+
 void k_mul(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream) {
     EW_LAUNCH(mul_kernel, out, a, b);
 }

@@ -170,28 +170,6 @@ struct Evaluator {
         }
     }
 
-    // round(value S q_(lv+1) / tj.scale) as residues of the primes 0..lv+1
-    std::vector<u64> const_residues(double value, double S, int lv, double tscale) {
-        const double K = std::rint(value * S * (double)c.primes[lv + 1] / tscale);
-        std::vector<u64> res(lv + 2);
-        const bool neg = K < 0;
-        const double a = std::fabs(K);
-        for (int i = 0; i <= lv + 1; i++) {
-            const u64 q = c.primes[i];
-            u64 m;
-            if (a < 9.2e18) {
-                m = (u64)a % q;
-            } else {
-                int e;
-                const double mant = std::frexp(a, &e);
-                const u64 mi = (u64)std::ldexp(mant, 53);
-                m = mulmod_h(mi % q, powmod_h(2, (u64)(e - 53), q), q);
-            }
-            res[i] = (neg && m) ? q - m : m;
-        }
-        return res;
-    }
-
     static void accumulate(Context& c, Ct& acc, bool& have, Ct& t) {
         if (!have) {
             acc = t;
@@ -202,9 +180,11 @@ struct Evaluator {
         }
     }
 
-    // sum_j coef[j] T_j at (scale S, level lv); one rescale.  Imaginary
-    // parts are summed apart and multiplied by X^(N/2), which multiplies
-    // every slot by i exactly (no level, no noise).
+    // sum_j coef[j] T_j at (scale S, level lv); one rescale.  Every term
+    // T_j (read at level lv + 1) times its integer round(coef S q / scale_j),
+    // or times its masked plaintext, enters one multiply-accumulate launch;
+    // imaginary parts are summed apart and multiplied by X^(N/2), which
+    // multiplies every slot by i exactly (no level, no noise).
     Val leaf(const std::vector<cplx>& coef, double S, int lv) {
         int deg = (int)coef.size() - 1;
         while (deg > 0 && coef[deg] == 0.0) deg--;
@@ -215,35 +195,66 @@ struct Evaluator {
             return v;
         }
         const double ql = (double)c.primes[lv + 1];
-        Ct acc, acci;
-        bool have = false, havei = false;
+        std::vector<LeafTerm> terms[2];
+        std::vector<u64*> owned_pts;   // uncached mask plaintexts, freed after the launches
+        int m = 0;
         for (int j = 1; j <= deg; j++) {
             if (coef[j] == 0.0) continue;
             build_T(j);
             const Ct& tj = T.at(j);
             HS_REQUIRE(tj.level >= lv + 1, E_LEVEL, "polynomial evaluation: level budget exhausted");
+            m = tj.m;
             for (int part = 0; part < 2; part++) {
                 const double value = part == 0 ? coef[j].real() : coef[j].imag();
                 if (value == 0.0) continue;
-                Ct d = ct_drop(c, tj, lv + 1);
+                LeafTerm t{};
+                t.a = tj.d;
+                t.arows = tj.level + 1;
                 if (mask) {
                     HS_REQUIRE(part == 0, E_ARG, "masked evaluation takes real coefficients");
-                    Ct md = mul_mask(d, value, S * ql / tj.scale);
-                    ct_free(c, d);
-                    md.scale = S * ql;
-                    accumulate(c, acc, have, md);
-                    continue;
+                    bool owned;
+                    const double pscale = S * ql / tj.scale;
+                    u64* pt = mask_pt(value * pscale, lv + 1, &owned);
+                    if (owned) owned_pts.push_back(pt);
+                    t.p = pt;
+                } else {
+                    const double K = std::rint(value * S * ql / tj.scale);
+                    if (K == 0.0) continue;   // the term vanishes at this scale
+                    const double a = std::fabs(K);
+                    t.neg = K < 0;
+                    if (a < 9.2e18) {
+                        t.mant = (u64)a;
+                        t.e = 0;
+                    } else {
+                        int e;
+                        const double mant = std::frexp(a, &e);
+                        t.mant = (u64)std::ldexp(mant, 53);
+                        t.e = e - 53;
+                    }
                 }
-                op_mul_residues_inplace(c, d, const_residues(value, S, lv, tj.scale));
-                d.scale = S * ql;
-                if (part == 0) accumulate(c, acc, have, d);
-                else accumulate(c, acci, havei, d);
+                terms[part].push_back(t);
             }
         }
-        if (havei) {
-            Ct t = op_mul_monomial(c, acci, c.N / 2);
-            ct_free(c, acci);
-            accumulate(c, acc, have, t);
+        Ct acc;
+        bool have = false;
+        for (int part = 0; part < 2; part++) {
+            if (terms[part].empty()) continue;
+            Ct s = ct_alloc(c, m, 2, lv + 1);
+            s.scale = S * ql;
+            k_leaf_mac(c.T, s.d, 2 * m, lv + 2, terms[part].data(), (int)terms[part].size(), c.stream);
+            if (part == 1) {
+                Ct t = op_mul_monomial(c, s, c.N / 2);
+                ct_free(c, s);
+                s = t;
+            }
+            accumulate(c, acc, have, s);
+        }
+        for (u64* pt : owned_pts) c.free_words(pt);
+        if (!have) {
+            // every term rounded to zero
+            acc = ct_alloc(c, std::max(m, 1), 2, lv + 1);
+            acc.scale = S * ql;
+            k_zero_rows(c.T, c.ct_rows(acc), c.stream);
         }
         HS_REQUIRE(coef[0].imag() == 0.0, E_ARG, "polynomial evaluation: imaginary constant term");
         if (mask) add_mask_const(acc, coef[0].real());
