@@ -139,8 +139,18 @@ struct NttSkip {
     int nql = 0;
 };
 void k_ntt_skip(const DevTables& T, const Rows& x, const NttSkip& skip, void* stream);
-// forward NTT of x followed by the epilogue (x is left unspecified)
-void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream);
+// Input of a forward NTT taken as the centred lift of one coefficient-domain
+// row per group (base + G gs, prime src_prime) to each row's prime, instead
+// of x's own rows (rescale: the dropped row lifted to every other prime).
+struct NttLift {
+    const u64* base = nullptr;
+    size_t gs = 0;
+    int src_prime = 0;
+};
+// forward NTT of x (or of the lift, when given) followed by the epilogue
+// (x is left unspecified)
+void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream,
+                    const NttLift* lift = nullptr);
 void k_add(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
 void k_sub(const DevTables& T, const Rows& out, const Rows& a, const Rows& b, void* stream);
 void k_neg(const DevTables& T, const Rows& out, const Rows& a, void* stream);

@@ -442,8 +442,16 @@ __device__ __forceinline__ u64 reduce4q(u64 x, u64 q) {
 // pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
 #define NTT16_LDS (16 * 272)
 
+// centred lift of x (mod q_s) to the prime of P: x if x <= (q_s - 1) / 2,
+// else x - q_s, reduced
+__device__ __forceinline__ u64 lift_centred(u64 x, u64 qs, const PrimeInfo& P) {
+    if (x <= (qs - 1) / 2) return reduce64(x, P);
+    const u64 mag = reduce64(qs - x, P);
+    return mag ? P.q - mag : 0;
+}
+
 __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
-                                                       NttSkip sk, int g0) {
+                                                       NttSkip sk, int g0, NttLift lf) {
     __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row(x, blockIdx.y, order, sk, g0);
     if (row < 0) return;   // whole workgroup
@@ -456,8 +464,16 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
     if (!inverse) {
         const ulonglong2* tw = (const ulonglong2*)T.tw2 + (size_t)pi * 65536;
         // thread (lo = hl, c): hi = 0..15, stages 0..3
+        if (lf.base) {
+            const PrimeInfo P = T.prime[pi];
+            const u64 qs = T.prime[lf.src_prime].q;
+            const u64* pl = lf.base + (size_t)(row / x.rpg) * lf.gs + blockIdx.x * 16;
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) E[hi] = ps[(size_t)(hi * 16 + hl) * 256 + c];
+            for (int hi = 0; hi < 16; hi++) E[hi] = lift_centred(pl[(size_t)(hi * 16 + hl) * 256 + c], qs, P);
+        } else {
+#pragma unroll
+            for (int hi = 0; hi < 16; hi++) E[hi] = ps[(size_t)(hi * 16 + hl) * 256 + c];
+        }
         fwd16(E, tw, 1, q);
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) sm[hi * 272 + hl * 16 + c] = E[hi];
@@ -566,7 +582,8 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) { k_nt
 // variant & 2 splits the launch into batches of kNttGroupBatch row groups.
 constexpr int kNttGroupBatch = 8;
 static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, bool inverse, int variant,
-                         hipStream_t st, const NttEpilogue* epi = nullptr, const NttSkip& sk = NttSkip()) {
+                         hipStream_t st, const NttEpilogue* epi = nullptr, const NttSkip& sk = NttSkip(),
+                         const NttLift* lift = nullptr) {
     const int order = variant & 1;
     const int gb = (variant & 2) ? kNttGroupBatch : x.ngroups;
     const int vrows = sk.per ? x.rpg - (sk.nql - ((sk.nql - 1) / sk.digit) * sk.digit) : x.rpg;
@@ -578,16 +595,21 @@ static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, boo
         ss.base = src.base + (size_t)g0 * src.gstride;
         xs.ngroups = ss.ngroups = std::min(gb, x.ngroups - g0);
         e.g0 = g0;
+        NttLift lf;
+        if (lift) {
+            lf = *lift;
+            lf.base = lift->base + (size_t)g0 * lift->gs;
+        }
         const dim3 g(16, xs.ngroups * vrows);
         if (!inverse) {
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0, lf);
             if (epi)
                 hipLaunchKernelGGL(ntt16_p2_kernel<true>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
             else
                 hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
         } else {
             hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, ss, 1, order, e, sk);
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
         }
     }
 }
@@ -605,17 +627,18 @@ void k_ntt_skip(const DevTables& T, const Rows& x, const NttSkip& skip, void* st
     ntt16_launch(T, x, x, false, variant, st, nullptr, skip);
 }
 
-void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream) {
+void k_ntt_epilogue(const DevTables& T, const Rows& x, const NttEpilogue& e, void* stream, const NttLift* lift) {
     const int nrows = x.ngroups * x.rpg;
     if (nrows == 0) return;
     hipStream_t st = (hipStream_t)stream;
     if (T.logN == 16) {
         const int variant = tune_ntt16(T, x, false, st);
         ProfScope ps(T.prof, PK_NTT, 16.0 * T.N * nrows, stream);
-        ntt16_launch(T, x, x, false, variant, st, &e);
+        ntt16_launch(T, x, x, false, variant, st, &e, NttSkip(), lift);
         return;
     }
-    // other ring sizes: the transform, then the epilogue as its own kernels
+    // other ring sizes: the lift, the transform, then the epilogue as their own kernels
+    if (lift) k_lift_centered(T, x, lift->base, lift->gs, lift->src_prime, stream);
     k_ntt(T, x, false, stream);
     for (int j = 0; j < e.split; j++) {
         const int ng = (x.ngroups - j + e.split - 1) / e.split;
@@ -1419,16 +1442,7 @@ __global__ void lift_centered_kernel(DevTables T, Rows out, const u64* in, size_
     const int g = row / out.rpg;
     const int r = row - g * out.rpg;
     const PrimeInfo P = T.prime[prime_of(out, r)];
-    const u64 qs = T.prime[src_prime].q;
-    const u64 x = in[(size_t)g * ig + i];
-    u64 v;
-    if (x <= (qs - 1) / 2) {
-        v = reduce64(x, P);
-    } else {
-        const u64 mag = reduce64(qs - x, P);
-        v = mag ? P.q - mag : 0;
-    }
-    row_ptr(out, row, N)[i] = v;
+    row_ptr(out, row, N)[i] = lift_centred(in[(size_t)g * ig + i], T.prime[src_prime].q, P);
 }
 
 void k_lift_centered(const DevTables& T, const Rows& out, const u64* in, size_t in_gstride, int src_prime,

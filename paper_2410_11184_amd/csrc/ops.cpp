@@ -130,7 +130,6 @@ Ct op_rescale(Context& c, const Ct& a) {
     Rows r_last{last, np_, 1, N, 1, l, c.nq};
     k_ntt_from(c.T, r_last, in_last, true, c.stream);
     Rows r_lift{lifted, np_, l, (size_t)l * N, l, 0, c.nq};
-    k_lift_centered(c.T, r_lift, last, N, l, c.stream);
     Ct o = ct_alloc(c, a.m, a.ncomp, l - 1);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = invmod_h(c.primes[l] % c.primes[i], c.primes[i]);
@@ -141,7 +140,12 @@ Ct op_rescale(Context& c, const Ct& a) {
     e.out_gs[0] = (size_t)l * N;
     e.a = a.d;
     e.a_gs = (size_t)(l + 1) * N;
-    k_ntt_epilogue(c.T, r_lift, e, c.stream);
+    // the transform reads the dropped row, lifted (centred) to each prime
+    NttLift lf;
+    lf.base = last;
+    lf.gs = N;
+    lf.src_prime = l;
+    k_ntt_epilogue(c.T, r_lift, e, c.stream, &lf);
     o.scale = a.scale / (double)c.primes[l];
     c.free_words(last);
     c.free_words(lifted);
