@@ -125,7 +125,9 @@ hs_status hs_keygen(hs_ctx* ctx, uint64_t seed);
  * and the conjugation key when conj != 0. */
 hs_status hs_add_rotation_keys(hs_ctx* ctx, const int32_t* steps, size_t n_steps, int conj);
 /* Key material export for testing: key id 0 = relinearisation, otherwise a
- * Galois element.  Layout [dnum][2 (b, a)][n_q + n_p][N]. */
+ * Galois element.  Layout [dnum][2 (b, a)][n_q + n_p][N], NTT domain, in the
+ * specified form (the device copy keeps its Q rows multiplied by P^-1 mod q_i,
+ * which lets ModDown skip a product; the export multiplies them back). */
 hs_status hs_key_export(hs_ctx* ctx, int key_id, uint64_t* out, size_t cap, size_t* used);
 /* Secret coefficients (int64, N values) and public key ([2][n_q][N]); for
  * the client side and for tests. */
