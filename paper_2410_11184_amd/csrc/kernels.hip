@@ -1040,17 +1040,15 @@ __global__ void __launch_bounds__(256) base_convert_kernel(DevTables T, ConvTabl
     for (int t = t0; t < t1; t++) {
         const u64 q = s_q[t];
         // the branch is uniform: every lane works on target t
-        const unsigned __int128 v = q >> 42 ? conv_sum<K, true>(x0, x1, s_hl, s_h2, m, t)
-                                            : conv_sum<K, false>(x0, x1, s_hl, s_h2, m, t);
+        unsigned __int128 v = q >> 42 ? conv_sum<K, true>(x0, x1, s_hl, s_h2, m, t)
+                                      : conv_sum<K, false>(x0, x1, s_hl, s_h2, m, t);
+        // centred sources: - nneg D = + nneg (q - D mod q) modulo q, added
+        // to the exact sum (nneg <= K, so it stays below 2^127)
+        if (nneg) v += (unsigned __int128)(u64)nneg * (q - s_dmod[t]);
         // v mod q = (hi 2^64 mod q) + (lo mod q): two Shoup reductions
         const u64 hi = (u64)(v >> 64), lo = (u64)v;
         const u64 rl = lo - __umul64hi(lo, s_one[t]) * q;
-        u64 acc = add_mod(mul_shoup(hi, s_r64[t], s_r64s[t], q), rl >= q ? rl - q : rl, q);
-        if (nneg) {
-            const u64 dm = s_dmod[t];
-            for (int r = 0; r < nneg; r++) acc = sub_mod(acc, dm, q);
-        }
-        o[(size_t)s_row[t] * N] = acc;
+        o[(size_t)s_row[t] * N] = add_mod(mul_shoup(hi, s_r64[t], s_r64s[t], q), rl >= q ? rl - q : rl, q);
     }
 }
 
