@@ -246,6 +246,8 @@ def main():
                     help="also time version SM on the same 64 ciphertexts (bootstraps the main ciphertexts)")
     ap.add_argument("--tune", action="store_true",
                     help="time interchangeable kernels during the warm-up and save the decisions")
+    ap.add_argument("--tune-file", default="tune_decisions.json",
+                    help="where --tune writes its decisions (the committed ones are %s)" % TUNE_FILE)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -253,8 +255,9 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the path on a single MI355X; "
-              "multi-GPU sharding is design-only (see the repository documentation).", file=sys.stderr)
+        print("bench.py measures one GPU: the path runs on a single MI355X; sharding across GPUs "
+              "(one ciphertext share per GPU, one sum all-reduce per iteration) is not implemented.",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "fgb16_uneven":
@@ -302,8 +305,9 @@ def main():
         _log("warmup %d: %.3fs %s" % (i, time.perf_counter() - t0, ctx.softmax_stats()))
     if args.tune:
         hs.tune_enable(False)
-        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-        hs.tune_save(os.path.join(ROOT, "gpurun_out", "tune_gfx950.json"))
+        d = os.path.dirname(os.path.abspath(args.tune_file))
+        os.makedirs(d, exist_ok=True)
+        hs.tune_save(args.tune_file)
     rep = hs.tune_report()
     tuning = {"source": tune_src, "shapes": len(rep),
               "choices": {c: sum(1 for r in rep if r["choice"] == c) for c in sorted({r["choice"] for r in rep})}}
