@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured schedule")
+    ap.add_argument("--lockstep", type=int, default=0,
+                    help="also time J jobs of the metric's shape in one lockstep schedule")
     ap.add_argument("--sweep", action="store_true",
                     help="also time version-B jobs of 1, 2, 4, ..., 64 ciphertexts")
     ap.add_argument("--sm-many", action="store_true",
@@ -405,6 +407,28 @@ def main():
             del om, cm
             pm.close()
 
+    lockstep = None
+    if args.lockstep > 1:
+        # J independent jobs of the same shape (each 64 ciphertexts, 8192
+        # Softmax) in one lockstep schedule: their auxiliary ciphertexts share
+        # every bootstrap; captured and replayed like the single job
+        J = args.lockstep
+        xs_l = [synthetic.logits_uniform(L, n, M, seed=8000 + j) for j in range(J)]
+        cl = [c for j, xl in enumerate(xs_l) for c in encrypt_logits(ctx, xl, M, seed=8100 + 100 * j)]
+        pl = ctx.softmax_plan(cl, n, M, variant=variant, jobs=J)
+        pl.run(cl)
+        ctx.sync()
+        t0 = time.perf_counter()
+        ol = pl.run(cl)
+        ctx.sync()
+        tl = time.perf_counter() - t0
+        worst = min(S.precision_bits(S.softmax(xs_l[j]), decrypt_outputs(ctx, ol[j * m:(j + 1) * m], n))["worst"]
+                    for j in range(J))
+        lockstep = dict(jobs=J, calls=J * L, ms=1e3 * tl, calls_per_s=J * L / tl, worst_bits=worst)
+        _log("lockstep %d jobs: %.1f ms, %.1f calls/s, worst %.2f bits" % (J, 1e3 * tl, J * L / tl, worst))
+        del ol, cl
+        pl.close()
+
     sm_many = None
     if args.sm_many:
         # trade study: the same 64 ciphertexts through version SM (main
@@ -492,6 +516,7 @@ def main():
         "plain": plain,
         "speedup_vs_plain": (value / plain["calls_per_s"]) if plain else None,
         "sm_many_ciphertext": sm_many,
+        "lockstep_jobs": lockstep,
         "smb_scaling": sweep,
         # not the metric: the client side (pack, encode, PCIe upload, encrypt) and decryption
         "client_encrypt_s": client_encrypt_s,
