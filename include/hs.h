@@ -109,7 +109,11 @@ hs_status hs_sync(hs_ctx* ctx);
 hs_status hs_stream_create(int device, void** stream);
 hs_status hs_stream_destroy(void* stream);
 /* Device memory of the context's arena: bytes held by live objects (keys,
- * tables, ciphertexts) and bytes reserved from the device (8 GiB chunks). */
+ * tables, ciphertexts) and bytes reserved from the device (8 GiB chunks).
+ * Not counted: tables the context keeps outside the arena until it is
+ * destroyed (conversion constants, bootstrap plaintexts, and the masked
+ * normalisation plaintexts of the Softmax schedules it has run, at most
+ * 8 GiB, reused by later calls of the same shape). */
 hs_status hs_ctx_memory(const hs_ctx* ctx, size_t* in_use, size_t* reserved);
 /* Return the arena's wholly unused chunks to the device (e.g. after a large
  * batch, so another context on the same GPU can use the memory); waits for
