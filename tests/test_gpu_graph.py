@@ -92,3 +92,19 @@ def test_plan_rejects_other_shapes(toy):
     with pytest.raises(ValueError):
         plan.run(cts[:1])
     plan.close()
+
+
+def test_plan_refuses_capture_while_profiling(toy):
+    # the launch profiler records events around launches: none may enter a graph
+    from paper_2410_11184_amd import hs
+    from paper_2410_11184_amd.softmax import encrypt_logits
+    x = synthetic.logits_uniform(2 * toy.slots // 16, 16, 8.0, seed=940)
+    cts = encrypt_logits(toy, x, 8.0, seed=2)
+    toy.prof_enable(True)
+    try:
+        with pytest.raises(hs.HSError) as e:
+            toy.softmax_plan(cts, 16, 8.0, variant=1, **TOY)
+        assert e.value.name == "HS_E_STATE"
+    finally:
+        toy.prof_enable(False)
+        toy.prof_collect()
