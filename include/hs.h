@@ -67,9 +67,9 @@ typedef struct hs_softmax_plan hs_softmax_plan;
 typedef struct hs_params {
     int log_n;            /* ring degree N = 2^log_n, 3 <= log_n <= 17        */
     int n_q;              /* number of Q primes                                */
-    const int* q_bits;    /* [n_q] target bit sizes (20..61)                   */
+    const int* q_bits;    /* [n_q] target bit sizes (32..61; HS_E_PARAM else)  */
     int n_p;              /* number of special primes                          */
-    const int* p_bits;    /* [n_p]                                             */
+    const int* p_bits;    /* [n_p] (32..61)                                    */
     int digit;            /* primes per key-switching digit                    */
     int hamming;          /* secret Hamming weight; 0 = uniform ternary        */
     double sigma;         /* discrete Gaussian parameter of the errors         */
@@ -123,7 +123,11 @@ hs_status hs_ctx_trim(hs_ctx* ctx, size_t* released);
 
 /* KeyGen (Section 2.2): secret, public and relinearisation keys from one
  * 64-bit seed.  Every draw is Philox4x32-10 (Salmon et al., SC11) with
- * key = seed and counter = (coefficient index, 64-bit domain tag). */
+ * key = seed and counter = (coefficient index, 64-bit domain tag).  Replaces
+ * every key of the context (rotation keys included).  HS_E_STATE while a
+ * captured Softmax schedule (hs_softmax_plan_create) of this context is
+ * alive: its graph holds the device addresses of the current keys, so
+ * destroy the plans first. */
 hs_status hs_keygen(hs_ctx* ctx, uint64_t seed);
 /* Rotation keys for the given left-rotation steps (any sign, modulo N/2),
  * and the conjugation key when conj != 0. */
@@ -268,7 +272,9 @@ hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n);
  * hs_softmax_jobs on the same inputs).  Synchronous; updates
  * hs_softmax_stats.  Replays of one plan must not overlap (one host thread).
  * hs_softmax_plan_info: graph node count and arena bytes (either may be NULL).
- * hs_softmax_plan_destroy: waits for the plan's stream and frees everything. */
+ * hs_softmax_plan_destroy: waits for the plan's stream and frees everything.
+ * While a plan is alive, hs_keygen on its context returns HS_E_STATE (the
+ * graph replays with the keys it was recorded with). */
 hs_status hs_softmax_plan_create(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t njobs, uint32_t n, double M,
                                  const hs_softmax_opts* opts, hs_softmax_plan** out);
 hs_status hs_softmax_plan_run(hs_softmax_plan* plan, hs_ct* const* in, size_t m, hs_ct** out);

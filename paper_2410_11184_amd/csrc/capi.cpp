@@ -169,6 +169,8 @@ hs_status hs_sync(hs_ctx* ctx) {
 hs_status hs_keygen(hs_ctx* ctx, uint64_t seed) {
     return guard([&] {
         NEED(ctx);
+        HS_REQUIRE(ctx->c->live_plans == 0, hs::E_STATE,
+                   "keygen: captured Softmax schedules hold the current keys; destroy them first");
         hs::keygen(*ctx->c, seed);
     });
 }
@@ -670,7 +672,9 @@ struct hs_softmax_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double stats[3] = {0, 0, 0};
+    bool counted = false;           // included in the context's live_plans
     ~hs_softmax_plan() {
+        if (counted) ctx->c->live_plans--;
         if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -755,6 +759,8 @@ hs_status hs_softmax_plan_create(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t
         P->stats[0] = st.k;
         P->stats[1] = st.bootstraps;
         P->stats[2] = st.levels_left;
+        c.live_plans++;
+        P->counted = true;
         *out = P.release();
     });
 }

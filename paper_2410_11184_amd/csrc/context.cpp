@@ -18,6 +18,8 @@
 
 namespace hs {
 
+void launch_error(const char* what) { throw Error(E_ARG, what); }
+
 static void check_hip(hipError_t e, const char* what) {
     if (e != hipSuccess) throw Error(E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -79,7 +81,6 @@ static std::vector<u64> find_primes(int logN, const std::vector<int>& bits) {
     std::map<int, long long> cursor;
     std::vector<u64> out;
     for (int b : bits) {
-        HS_REQUIRE(b >= 20 && b <= 61, E_PARAM, "prime sizes must be in [20, 61] bits");
         long long j = cursor[b];
         while (true) {
             long long k = j / 2 + 1;
@@ -302,6 +303,10 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     HS_REQUIRE((int)(p.q_bits.size() + p.p_bits.size()) <= kMaxRows, E_PARAM, "too many primes");
     HS_REQUIRE(p.digit >= 1 && p.digit <= 16, E_PARAM, "digit size out of range");
     HS_REQUIRE(p.user_top >= 0 && p.user_top < (int)p.q_bits.size(), E_PARAM, "user_top out of range");
+    // the device reductions (Barrett with mu = floor(2^(2b) / q), b = bit
+    // length of q) reduce full 64-bit words, which needs 2b >= 64
+    for (int b : p.q_bits) HS_REQUIRE(b >= 32 && b <= 61, E_PARAM, "prime sizes must be in [32, 61] bits");
+    for (int b : p.p_bits) HS_REQUIRE(b >= 32 && b <= 61, E_PARAM, "prime sizes must be in [32, 61] bits");
     check_hip(hipSetDevice(dev), "hipSetDevice");
     stream = st;
     logN = p.logN;

@@ -123,7 +123,11 @@ struct NttEpilogue {
 };
 
 // ------------------------------------------------------------- launches
-// All launches are asynchronous on `stream` (a hipStream_t).
+// All launches are asynchronous on `stream` (a hipStream_t).  A launch
+// wrapper given arguments its kernel cannot serve raises the library's
+// argument error (HS_E_ARG) through launch_error instead of returning with
+// the output unwritten.
+[[noreturn]] void launch_error(const char* what);
 void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream);
 // measured v_mad_u64_u32 rate of the device (10^12 lane operations / s)
 double k_mul_rate(void* stream);

@@ -142,6 +142,9 @@ struct Context {
     // schedule's own arena while it is being recorded
     Pool* cur = &pool;
     bool capturing = false;      // host-device copies and syncs are refused while set
+    // captured Softmax schedules alive on this context: their graphs hold the
+    // device addresses of the keys, so key generation is refused meanwhile
+    int live_plans = 0;
     std::vector<PrimeInfo> pinfo;
     u64 P_mod[kMaxRows];         // P mod q_i for Q primes
     // key material

@@ -941,7 +941,9 @@ __global__ void permute_multi_kernel(Rows out, Rows in, PermList perms, int N) {
 
 void k_permute_multi(const DevTables& T, const Rows& out, const Rows& in, const PermList& perms, void* stream) {
     if (out.ngroups * out.rpg == 0) return;
-    if (perms.per < 1 || (out.ngroups + perms.per - 1) / perms.per > perms.n || in.rpg < out.rpg) return;
+    if (perms.per < 1 || perms.n > kMaxKeys || (out.ngroups + perms.per - 1) / perms.per > perms.n ||
+        in.rpg < out.rpg)
+        launch_error("permutation batch: the permutation list does not cover the output groups");
     ProfScope ps(T.prof, PK_PERM, 16.0 * T.N * out.ngroups * out.rpg, stream);
     hipLaunchKernelGGL(permute_multi_kernel, ew_grid(T, out), dim3(256), 0, (hipStream_t)stream, out, in, perms,
                        T.N);
@@ -1425,7 +1427,8 @@ int tune_load(const std::string& text) {
 void k_base_convert(const DevTables& T, const ConvTables& C, u64* out, size_t out_gstride, const u64* in,
                     size_t in_gstride, int ngroups, void* stream, const u64* own_in, size_t own_gstride) {
     if (ngroups == 0 || C.m == 0) return;
-    if (C.k < 1 || C.k > kMaxConvSrc || C.m > kMaxConvDst) return;  // tables are checked when built
+    if (C.k < 1 || C.k > kMaxConvSrc || C.m > kMaxConvDst)
+        launch_error("base conversion: source or target count out of range");
     const int variant = tune_conv(T, C, out_gstride, in_gstride, ngroups, (hipStream_t)stream);
     ProfScope ps(T.prof, PK_CONV, 8.0 * T.N * ngroups * (double)(C.k + C.m), stream);
     conv_launch(T, C, out, out_gstride, in, in_gstride, ngroups, variant, (hipStream_t)stream, own_in, own_gstride);
@@ -1503,8 +1506,8 @@ static void launch_key_inner(const DevTables& T, u64* acc, const u64* ext, const
 
 void k_key_inner(const DevTables& T, u64* acc, const u64* ext, const KeyList& keys, int beta, int ext_rows,
                  int nq_level, int key_rows, int key_nq, void* stream) {
-    if (beta < 1 || beta > kMaxDigits) return;  // the digit count is checked when the context is built
-    if (keys.n < 1 || keys.n > kMaxKeys || keys.per < 1) return;
+    if (beta < 1 || beta > kMaxDigits) launch_error("key inner product: digit count out of range");
+    if (keys.n < 1 || keys.n > kMaxKeys || keys.per < 1) launch_error("key inner product: bad key list");
     // algorithmic bytes: each key once per launch, ext read and acc written per ciphertext
     const double ncts = (double)keys.n * keys.per;
     ProfScope ps(T.prof, PK_KEYIP, 8.0 * T.N * ext_rows * (2.0 * beta * keys.n + ncts * (beta + 2.0)), stream);

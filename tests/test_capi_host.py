@@ -79,3 +79,16 @@ def test_tune_decisions_round_trip(tmp_path):
     hs.tune_clear()
     with pytest.raises(hs.HSError):
         hs.tune_load(tmp_path / "missing.json")
+
+
+def test_prime_sizes_below_32_bits_refused():
+    # the device reductions need primes of at least 32 bits; the check runs
+    # before any device call, so it holds on a machine without a GPU
+    from paper_2410_11184_amd import hs
+    import synthetic
+    p = dict(synthetic.preset("toy12"))
+    p["q_bits"] = [31] + p["q_bits"][1:]
+    with pytest.raises(hs.HSError) as e:
+        hs.Context(p)
+    assert e.value.name == "HS_E_PARAM"
+    assert "32, 61" in str(e.value)

@@ -108,3 +108,24 @@ def test_plan_refuses_capture_while_profiling(toy):
     finally:
         toy.prof_enable(False)
         toy.prof_collect()
+
+
+def test_keygen_refused_while_a_plan_lives():
+    # a plan's graph holds the device addresses of the keys it was recorded
+    # with: new keys are refused until the plan is destroyed (the call is
+    # refused up front, so no replay ever reads freed key memory)
+    from paper_2410_11184_amd import hs
+    from paper_2410_11184_amd.softmax import encrypt_logits
+    c = hs.Context(synthetic.preset("toy12"))
+    c.keygen(322)
+    x = synthetic.logits_uniform(2 * c.slots // 16, 16, 8.0, seed=950)
+    cts = encrypt_logits(c, x, 8.0, seed=3)
+    plan = c.softmax_plan(cts, 16, 8.0, variant=1, **TOY)
+    with pytest.raises(hs.HSError) as e:
+        c.keygen(323)
+    assert e.value.name == "HS_E_STATE"
+    g = plan.run(cts)                       # the plan still replays on its keys
+    e_out = c.softmax(cts, 16, 8.0, variant=1, **TOY)
+    assert all(np.array_equal(a.export(), b.export()) for a, b in zip(e_out, g))
+    plan.close()
+    c.keygen(323)                           # allowed once the plan is gone
