@@ -153,3 +153,37 @@ def test_key_switch_noise_is_small(ctx):
     err = max(abs(a - b) for a, b in zip(mr, mg))
     # ModDown rounding: |u0 + u1 s| <= (alpha + 1) (1 + ||s||_1) / 2
     assert err <= (len(ctx.p) + 1) * (1 + np.count_nonzero(ctx.s_coeff))
+
+
+def test_mod_down_is_rounded_division_by_P(ctx):
+    # ModDown of c over Q_l u P: (c - Conv_P->Q([c]_P)) P^-1 = round(c / P) - u
+    # with |u| < (alpha + 1) / 2 (the centred conversion's multiple of P),
+    # checked by big-integer CRT on random polynomials over Q_l P
+    rng = np.random.default_rng(77)
+    level = 5
+    idx = list(range(level + 1)) + list(range(len(ctx.q), len(ctx.primes)))
+    Q = 1
+    for i in range(level + 1):
+        Q *= ctx.q[i]
+    QP = Q * ctx.P
+    C = [int.from_bytes(rng.bytes(64), "little") % QP for _ in range(ctx.N)]
+    limbs = [ctx.ntt(np.array([x % ctx.primes[t] for x in C], dtype=np.uint64), t) for t in idx]
+    out = ctx.mod_down(limbs, level)
+    got = ctx.crt([ctx.intt(out[i], i) for i in range(level + 1)], list(range(level + 1)))
+    alpha = len(ctx.p)
+    worst = 0
+    ds = []
+    for k in range(ctx.N):
+        cp = C[k] % ctx.P
+        if cp > ctx.P // 2:
+            cp -= ctx.P
+        r = (C[k] - cp) // ctx.P             # nearest integer to C / P
+        d = (got[k] - r) % Q
+        if d > Q // 2:
+            d -= Q
+        worst = max(worst, abs(d))
+        ds.append(d)
+    assert worst < (alpha + 1) / 2
+    # unbiased: a plain (non-centred) conversion would shift every
+    # coefficient by about -(alpha - 1) / 2 on average
+    assert abs(np.mean(ds)) < 5 * np.std(ds) / np.sqrt(len(ds)) + 0.02

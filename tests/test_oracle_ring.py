@@ -189,3 +189,80 @@ def test_samplers():
     L.or_draw_block(7, 4, 5, w)
     v = sum(int(w[i]) << (32 * i) for i in range(4))
     assert v % q == int(u[5])
+
+
+def _conv(fn, X, src, dst, N):
+    L = _lib.lib()
+    inp = np.array([[x % d for x in X] for d in src], dtype=np.uint64).reshape(-1)
+    out = np.empty(len(dst) * N, dtype=np.uint64)
+    getattr(L, fn)(inp, np.array(src, dtype=np.uint64), len(src), out, np.array(dst, dtype=np.uint64), len(dst), N)
+    return out.reshape(len(dst), N)
+
+
+def _lift_multiple(out, c, X, D, dst, umax):
+    """The integer u in [-umax, umax] with out[t][c] = (X + u D) mod t for every
+    target t (None when there is none: then no integer congruent to X mod D
+    with that bound explains the output)."""
+    hits = [u for u in range(-umax, umax + 1) if all(int(out[t][c]) == (X + u * D) % dst[t] for t in range(len(dst)))]
+    return hits[0] if len(hits) == 1 else None
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_centred_base_conversion_against_crt(k):
+    # The centred conversion (used by ModDown) takes each [x_i (D/d_i)^-1]_{d_i}
+    # in (-d_i/2, d_i/2]: its output is the residue of an integer X_c + u D
+    # (X_c the centred representative of X mod D) with |u| < (k + 1) / 2 and
+    # u of mean zero; the plain conversion gives X + u D with 0 <= u < k.
+    # Checked by big-integer CRT on every coefficient.
+    N = 256
+    q, p = find_primes(8, [40] * k, [60] * 3)
+    src, dst = q, p
+    D = 1
+    for d in src:
+        D *= d
+    rng = np.random.default_rng(30 + k)
+    X = [int.from_bytes(rng.bytes(40), "little") % D for _ in range(N)]
+    out_c = _conv("or_base_convert_centered", X, src, dst, N)
+    out_p = _conv("or_base_convert", X, src, dst, N)
+    uc, up = [], []
+    for c in range(N):
+        xc = X[c] - D if X[c] > D // 2 else X[c]
+        u = _lift_multiple(out_c, c, xc, D, dst, k + 1)
+        assert u is not None and abs(u) < (k + 1) / 2, (c, u)
+        uc.append(u)
+        u = _lift_multiple(out_p, c, X[c], D, dst, k + 1)
+        assert u is not None and 0 <= u < k, (c, u)
+        up.append(u)
+    # zero mean (the centred terms are symmetric): |mean| within 5 standard
+    # errors; the plain conversion's u has mean about (k - 1) / 2
+    sd = np.std(uc) / np.sqrt(N) + 1e-9
+    assert abs(np.mean(uc)) < 5 * sd + 0.05
+    assert np.mean(up) > (k - 1) / 2 - 0.5
+
+
+def test_centred_base_conversion_tie_rule():
+    # (-d/2, d/2] for odd d: the residue (d - 1) / 2 stays positive and
+    # (d + 1) / 2 becomes -(d - 1) / 2.  X is built from chosen lifted terms
+    # xh_i = [x_i (D/d_i)^-1]_{d_i}, so the exact integer the conversion must
+    # reproduce is sum_i xh_i' D / d_i with xh_i' the centred xh_i.
+    N = 4
+    src, dst = find_primes(4, [40, 40, 40], [60, 60])
+    D = 1
+    for d in src:
+        D *= d
+    choices = [((src[0] - 1) // 2, 5, 0), ((src[0] + 1) // 2, 7, 1), (1, (src[1] - 1) // 2, (src[2] + 1) // 2),
+               (src[0] - 1, src[1] - 1, src[2] - 1)]
+    X, want = [], []
+    for xh in choices:
+        x = 0
+        s = 0
+        for i, d in enumerate(src):
+            Di = D // d
+            x += xh[i] * Di          # x_i = xh_i (D/d_i) mod d_i
+            s += (xh[i] - d if xh[i] > (d - 1) // 2 else xh[i]) * Di
+        X.append(x % D)
+        want.append(s)
+    out = _conv("or_base_convert_centered", X, src, dst, N)
+    for c in range(N):
+        for t in range(len(dst)):
+            assert int(out[t][c]) == want[c] % dst[t], (c, t)
