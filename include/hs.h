@@ -344,6 +344,39 @@ hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct**
  * modulo prime index `prime` (host buffer, in place); for parity tests. */
 hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse);
 
+/* Raw ring operations on host rows, for parity tests of the primitives
+ * beneath key switching and rescaling (the paper relies on them through its
+ * CKKS library: Section 2.2, "Functionalities" and "Levels"; it specifies
+ * none of their internals).  Rows are N residues each, NTT domain unless
+ * stated, rows of prime q_i at index i; `in` holds in_words words and out
+ * receives *out_words words (out may be NULL or out_cap 0 to query the
+ * size).  HS_E_ARG when in_words does not match the operation, HS_E_LEVEL
+ * for a level outside 0..top.
+ *   HS_DBG_NTT / HS_DBG_INTT: rows q_0..q_level from coefficients / back.
+ *   HS_DBG_MODUP: one polynomial at `level` (level+1 rows) -> its hybrid
+ *     key-switching extension [beta][level+1+n_p][N], beta =
+ *     ceil((level+1)/digit): digit j (Q rows j*digit..) lifted to every
+ *     other prime of Q_level u P by the fast base conversion, NTT domain,
+ *     the digit's own rows unchanged.
+ *   HS_DBG_MODDOWN: one polynomial over Q_level u P ((level+1+n_p) rows,
+ *     q_0..q_level then p_0..) -> (c - Conv_P->Q([c]_P)) P^-1 mod q_i
+ *     (centred conversion), level+1 rows.
+ *   HS_DBG_AUTO: X -> X^arg (arg an odd Galois element, modulo 2N) on
+ *     level+1 rows.
+ *   HS_DBG_RESCALE: (c - r) q_level^-1 with r the centred residue of c mod
+ *     q_level; level+1 rows in, level rows out (level >= 1).
+ *   HS_DBG_TENSOR: two degree-1 ciphertexts (a0, a1, b0, b1: 4 (level+1)
+ *     rows) -> (a0 b0, a0 b1 + a1 b0, a1 b1): 3 (level+1) rows. */
+#define HS_DBG_NTT 0
+#define HS_DBG_INTT 1
+#define HS_DBG_MODUP 2
+#define HS_DBG_MODDOWN 3
+#define HS_DBG_AUTO 4
+#define HS_DBG_RESCALE 5
+#define HS_DBG_TENSOR 6
+hs_status hs_dbg_ring(hs_ctx* ctx, int op, int level, int arg, const uint64_t* in, size_t in_words,
+                      uint64_t* out, size_t out_cap, size_t* out_words);
+
 /* Measured throughput of v_mad_u64_u32 (32 x 32 + 64 -> 64 bit), the
  * instruction the 64-bit modular products are built from, in 10^12 lane
  * operations per second (eight independent chains per lane, about 1 ms on

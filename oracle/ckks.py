@@ -382,6 +382,24 @@ class Context:
         ext_idx = list(range(nq_l)) + p_idx
         acc0 = {t: np.zeros(self.N, dtype=np.uint64) for t in ext_idx}
         acc1 = {t: np.zeros(self.N, dtype=np.uint64) for t in ext_idx}
+        for j, ext in enumerate(self.mod_up(d, level)):
+            bj, aj = key[j]
+            for r, t in enumerate(ext_idx):
+                acc0[t] = self.add(acc0[t], self.mul(ext[r], bj[t], t), t)
+                acc1[t] = self.add(acc1[t], self.mul(ext[r], aj[t], t), t)
+        return self.mod_down([acc0[t] for t in ext_idx], level), \
+            self.mod_down([acc1[t] for t in ext_idx], level)
+
+    def mod_up(self, d, level):
+        """ModUp of the NTT-domain polynomial d (level+1 limbs): for each
+        digit D_j (consecutive blocks of `digit` primes of q[0..level]) the
+        extension of [d]_{D_j} to every prime of Q_level u P by the plain fast
+        base conversion, NTT domain, rows q[0..level] then P; the digit's own
+        rows are d's."""
+        nq_l = level + 1
+        p_idx = list(range(len(self.q), len(self.primes)))
+        ext_idx = list(range(nq_l)) + p_idx
+        out = []
         for j in range(self.dnum):
             dj = [t for t in range(j * self.digit, min((j + 1) * self.digit, nq_l))]
             if not dj:
@@ -389,15 +407,11 @@ class Context:
             coeff = [self.intt(d[t], t) for t in dj]
             others = [t for t in ext_idx if t not in dj]
             conv = self.base_convert(coeff, dj, others)
-            ext = {t: d[t] for t in dj}
+            ext = {t: np.asarray(d[t], dtype=np.uint64).copy() for t in dj}
             for t, c in zip(others, conv):
                 ext[t] = self.ntt(c, t)
-            bj, aj = key[j]
-            for t in ext_idx:
-                acc0[t] = self.add(acc0[t], self.mul(ext[t], bj[t], t), t)
-                acc1[t] = self.add(acc1[t], self.mul(ext[t], aj[t], t), t)
-        return self.mod_down([acc0[t] for t in ext_idx], level), \
-            self.mod_down([acc1[t] for t in ext_idx], level)
+            out.append(np.stack([ext[t] for t in ext_idx]))
+        return out
 
     def mod_down(self, limbs, level):
         """(c - Conv_{P->Q}([c]_P)) * P^-1 mod q_i for limbs over q[0..level] u P."""

@@ -34,6 +34,8 @@
 #include <map>
 #include <set>
 
+#include <quadmath.h>
+
 #include "host.h"
 #include "poly.h"
 #include "softmax.h"
@@ -288,10 +290,9 @@ static BootCtx& boot_ctx(Context& c) {
     }
     // ---- EvalMod polynomials (parity enforced: cos is even, sin is odd)
     {
-        const long double two_pi = 6.283185307179586476925286766559005768L;
-        const long double w = two_pi * (bp.K + 1) * ldexpl(1.0L, -bp.double_angle);
-        B->pcos = cheb_fit([&](long double u) { return cosl(w * u); }, -1.0, 1.0, bp.cos_degree);
-        B->psin = cheb_fit([&](long double u) { return sinl(w * u); }, -1.0, 1.0, bp.cos_degree);
+        const quad w = 2 * M_PIq * (bp.K + 1) * ldexpq(1, -bp.double_angle);
+        B->pcos = cheb_fit([&](quad u) { return cosq(w * u); }, -1.0, 1.0, bp.cos_degree);
+        B->psin = cheb_fit([&](quad u) { return sinq(w * u); }, -1.0, 1.0, bp.cos_degree);
         for (size_t j = 0; j < B->pcos.c.size(); j++) (j % 2 ? B->pcos.c[j] : B->psin.c[j]) = 0.0;
     }
     c.boot = B;

@@ -593,6 +593,89 @@ hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int i
     });
 }
 
+hs_status hs_dbg_ring(hs_ctx* ctx, int op, int level, int arg, const uint64_t* in, size_t in_words, uint64_t* out,
+                      size_t out_cap, size_t* out_words) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(in);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(level >= 0 && level <= c.L, hs::E_LEVEL, "level out of range");
+        const size_t N = c.N, nql = (size_t)level + 1, E = nql + c.np;
+        const size_t beta = (nql + c.prm.digit - 1) / c.prm.digit;
+        size_t win = nql * N, wout = nql * N;
+        switch (op) {
+            case HS_DBG_NTT:
+            case HS_DBG_INTT:
+            case HS_DBG_AUTO: break;
+            case HS_DBG_MODUP: wout = beta * E * N; break;
+            case HS_DBG_MODDOWN: win = E * N; break;
+            case HS_DBG_RESCALE:
+                HS_REQUIRE(level >= 1, hs::E_LEVEL, "rescale needs level >= 1");
+                wout = (nql - 1) * N;
+                break;
+            case HS_DBG_TENSOR:
+                win = 4 * nql * N;
+                wout = 3 * nql * N;
+                break;
+            default: throw hs::Error(hs::E_ARG, "unknown ring operation");
+        }
+        if (out_words) *out_words = wout;
+        HS_REQUIRE(in_words == win, hs::E_ARG, "input size does not match the operation and level");
+        if (!out || out_cap == 0) return;
+        HS_REQUIRE(out_cap >= wout, hs::E_ARG, "output buffer too small");
+        u64* din = c.alloc_words(win);
+        c.upload(din, in, win * 8);
+        u64* dout = nullptr;
+        hs::Ct tmp;
+        switch (op) {
+            case HS_DBG_NTT:
+            case HS_DBG_INTT: {
+                dout = c.alloc_words(wout);
+                hs::Rows rs = c.rows(din, 1, (int)nql, win), rd = c.rows(dout, 1, (int)nql, wout);
+                hs::k_ntt_from(c.T, rd, rs, op == HS_DBG_INTT, c.stream);
+                break;
+            }
+            case HS_DBG_MODUP:
+                dout = hs::op_modup_rows(c, c.rows(din, 1, (int)nql, win), level);
+                break;
+            case HS_DBG_MODDOWN:
+                dout = c.alloc_words(wout);
+                hs::op_mod_down_rows(c, din, level, dout);
+                break;
+            case HS_DBG_AUTO: {
+                HS_REQUIRE(arg % 2 != 0, hs::E_ARG, "the Galois element must be odd");
+                const int g = ((arg % (2 * c.N)) + 2 * c.N) % (2 * c.N);
+                dout = c.alloc_words(wout);
+                hs::k_permute(c.T, c.rows(dout, 1, (int)nql, wout), c.rows(din, 1, (int)nql, win), c.perm(g),
+                              c.stream);
+                break;
+            }
+            case HS_DBG_RESCALE: {
+                hs::Ct a;
+                a.d = din;
+                a.m = 1;
+                a.ncomp = 1;
+                a.level = level;
+                tmp = hs::op_rescale(c, a);
+                dout = tmp.d;
+                break;
+            }
+            case HS_DBG_TENSOR: {
+                hs::Ct a, b;
+                a.d = din;
+                a.level = b.level = level;
+                b.d = din + 2 * nql * N;
+                tmp = hs::op_tensor(c, a, b);
+                dout = tmp.d;
+                break;
+            }
+        }
+        c.download(out, dout, wout * 8);
+        c.free_words(din);
+        c.free_words(dout);
+    });
+}
+
 static hs::SoftmaxOpts softmax_opts(const hs_softmax_opts* opts) {
     hs::SoftmaxOpts o;
     if (opts) {

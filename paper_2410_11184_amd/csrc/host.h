@@ -275,6 +275,13 @@ Ct op_rotate_hoisted_batch(Context& c, const Ct& a, const std::vector<int>& rots
 Ct op_galois_batch(Context& c, const Ct& a, const std::vector<int>& gal, int per);
 Ct op_mod_raise(Context& c, const Ct& a, int level);
 Ct op_mul_monomial(Context& c, const Ct& a, int k);
+// ModUp of the polynomials d (level l, NTT domain): [groups][beta][l + 1 +
+// n_p][N], every digit lifted to Q_l u P in the NTT domain (pool buffer, the
+// caller frees it)
+u64* op_modup_rows(Context& c, const Rows& d, int level);
+// ModDown of one polynomial over Q_l u P (rows q_0..q_l, p_0..), NTT domain,
+// into out (rows q_0..q_l)
+void op_mod_down_rows(Context& c, const u64* in, int level, u64* out);
 void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1,
                 size_t out_gstride, const Rows* add0, const Rows* add1);
 

@@ -299,6 +299,42 @@ static void ks_finish(Context& c, const u64* ext, int m, int level, const KeyLis
     c.free_words(conv);
 }
 
+u64* op_modup_rows(Context& c, const Rows& d, int level) { return ks_modup(c, d, level); }
+
+// ModDown of one polynomial over Q_l u P (NTT domain, rows q_0..q_l then
+// p_0..p_{alpha-1}): the Q rows are first multiplied by P^-1 (the form the
+// key inner product leaves them in, its keys carrying that factor), then the
+// same conversion and fused epilogue as the key switch.
+void op_mod_down_rows(Context& c, const u64* in, int level, u64* out) {
+    const int nql = level + 1;
+    const int E = nql + c.np;
+    const size_t N = c.N;
+    u64* acc = c.alloc_words((size_t)E * N);
+    Rows src{const_cast<u64*>(in), 1, E, (size_t)E * N, nql, 0, c.nq};
+    Rows racc{acc, 1, E, (size_t)E * N, nql, 0, c.nq};
+    k_copy_rows(c.T, racc, src, c.stream);
+    std::vector<u64> pinv(nql);
+    for (int i = 0; i < nql; i++) pinv[i] = invmod_h(c.P_mod[i], c.primes[i]);
+    Rows accq{acc, 1, nql, (size_t)E * N, nql, 0, c.nq};
+    k_mul_row_const(c.T, accq, accq, c.shoup_consts(pinv, 0), c.stream);
+    Rows accp{acc + (size_t)nql * N, 1, c.np, (size_t)E * N, 0, 0, c.nq};
+    k_ntt(c.T, accp, true, c.stream);
+    u64* conv = c.alloc_words((size_t)nql * N);
+    const ConvDev& md = c.moddown_tables(level);
+    k_base_convert(c.T, md.t, conv, (size_t)nql * N, acc, (size_t)E * N, 1, c.stream);
+    Rows rconv{conv, 1, nql, (size_t)nql * N, nql, 0, c.nq};
+    NttEpilogue e;
+    e.mul = false;
+    e.split = 1;
+    e.a = acc;
+    e.a_gs = (size_t)E * N;
+    e.out[0] = out;
+    e.out_gs[0] = (size_t)nql * N;
+    k_ntt_epilogue(c.T, rconv, e, c.stream);
+    c.free_words(acc);
+    c.free_words(conv);
+}
+
 void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0, u64* out1, size_t out_gstride,
                 const Rows* add0, const Rows* add1) {
     u64* ext = ks_modup(c, d, level);

@@ -5,7 +5,7 @@
 // ceil(log(d+1)) levels and O(sqrt d) products (Section 2.2, "Functions as
 // polynomials", Paterson-Stockmeyer).  Here:
 //  * coefficients: Chebyshev interpolation at the d+1 first-kind nodes,
-//    computed in long double;
+//    computed in binary128 and rounded once to double;
 //  * evaluation: baby-step giant-step in the Chebyshev basis.  Baby steps
 //    T_1..T_{B-1} by T_2k = 2 T_k^2 - 1 and T_2k+1 = 2 T_k T_k+1 - T_1; giant
 //    steps T_B, T_2B, ...; the polynomial splits as q_lo + q_hi T_n
@@ -19,27 +19,29 @@
 #include <functional>
 #include <map>
 
+#include <quadmath.h>
+
 #include "host.h"
 #include "poly.h"
 
 namespace hs {
 
-ChebPoly cheb_fit(const std::function<long double(long double)>& f, double a, double b, int d) {
+ChebPoly cheb_fit(const std::function<quad(quad)>& f, double a, double b, int d) {
     ChebPoly p;
     p.a = a;
     p.b = b;
     p.c.assign(d + 1, 0.0);
-    std::vector<long double> fx(d + 1);
-    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<quad> fx(d + 1);
+    const quad pi = M_PIq;
     for (int k = 0; k <= d; k++) {
-        const long double u = cosl(pi * (k + 0.5L) / (d + 1));
-        const long double x = (u * ((long double)b - a) + (long double)a + b) / 2;
+        const quad u = cosq(pi * (k + (quad)0.5) / (d + 1));
+        const quad x = (u * ((quad)b - (quad)a) + (quad)a + (quad)b) / 2;
         fx[k] = f(x);
     }
     for (int j = 0; j <= d; j++) {
-        long double s = 0;
-        for (int k = 0; k <= d; k++) s += fx[k] * cosl(pi * j * (k + 0.5L) / (d + 1));
-        long double cj = 2.0L / (d + 1) * s;
+        quad s = 0;
+        for (int k = 0; k <= d; k++) s += fx[k] * cosq(pi * j * (k + (quad)0.5) / (d + 1));
+        quad cj = (quad)2 / (d + 1) * s;
         if (j == 0) cj /= 2;
         p.c[j] = (double)cj;
     }

@@ -13,7 +13,12 @@ struct ChebPoly {
     std::vector<double> c;
 };
 
-ChebPoly cheb_fit(const std::function<long double(long double)>& f, double a, double b, int degree);
+// Interpolation at the degree + 1 Chebyshev nodes of the first kind, every
+// step in binary128 (f too), so the coefficients are the exact interpolant's
+// rounded to the nearest double: the same doubles any correct high-precision
+// computation of that interpolant gives.
+typedef __float128 quad;
+ChebPoly cheb_fit(const std::function<quad(quad)>& f, double a, double b, int degree);
 double cheb_eval_plain(const ChebPoly& p, double x);
 int cheb_depth(int degree);   // levels used by eval_cheb (plus 1 if the affine map needs one)
 // Evaluate p on every slot of the batch x; result at scale target_scale.

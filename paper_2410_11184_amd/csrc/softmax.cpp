@@ -31,6 +31,8 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <quadmath.h>
+
 #include "host.h"
 #include "poly.h"
 #include "softmax.h"
@@ -179,10 +181,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     }
     // y0 = exp(x / 2^k) / sqrt(n)  (the 1/sqrt(n) keeps sum y0^2 in [e^(-2M/2^k), 1])
     const double isn = 1.0 / std::sqrt((double)n);
-    const long double Ml = M;
+    const quad Mq = M;
     const int kk = k;
-    ChebPoly pexp = cheb_fit([&](long double t) { return expl(Ml * t / ldexpl(1.0L, kk + 1)) * (long double)isn; },
-                             -2.0, 0.0, o.exp_degree);
+    ChebPoly pexp = cheb_fit([&](quad t) { return expq(Mq * t / ldexpq(1, kk + 1)) * (quad)isn; }, -2.0, 0.0,
+                             o.exp_degree);
     Ct y0 = eval_cheb(c, v, pexp, Delta);
     ct_free(c, v);
     if (o.debug_stop == 0) return y0;
@@ -214,7 +216,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         double a, b;
         free_interval(lo, hi, a, b);
         const double ee = e;
-        ChebPoly pinv = cheb_fit([&](long double s) { return powl(s, -(long double)ee); }, a, b, deg);
+        ChebPoly pinv = cheb_fit([&](quad s) { return powq(s, -(quad)ee); }, a, b, deg);
         const double delta = rel_error(pinv, lo, hi, e);
         const double lam_bound = max_abs(pinv, lo, hi) * 1.05;
         // main thread must keep one level for the square feeding S

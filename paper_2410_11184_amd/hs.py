@@ -107,6 +107,8 @@ def lib():
         "hs_mul_monomial": [_vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_dbg_ntt": [_vp, S, _u64p, ctypes.c_size_t, S],
         "hs_dbg_mul_rate": [_vp, ctypes.POINTER(ctypes.c_double)],
+        "hs_dbg_ring": [_vp, S, S, S, _u64p, ctypes.c_size_t, _u64p, ctypes.c_size_t,
+                        ctypes.POINTER(ctypes.c_size_t)],
         "hs_ctx_memory": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
         "hs_stream_create": [S, ctypes.POINTER(_vp)],
         "hs_stream_destroy": [_vp],
@@ -514,6 +516,19 @@ class Context:
         t = ctypes.c_double()
         _check(lib().hs_dbg_mul_rate(self.h, ctypes.byref(t)))
         return t.value
+
+    RING_OPS = {"ntt": 0, "intt": 1, "modup": 2, "moddown": 3, "auto": 4, "rescale": 5, "tensor": 6}
+
+    def ring(self, op, rows, level, arg=0):
+        """hs_dbg_ring: one raw ring operation on host rows (see include/hs.h)."""
+        x = np.ascontiguousarray(rows, dtype=np.uint64).reshape(-1)
+        code = self.RING_OPS[op]
+        used = ctypes.c_size_t()
+        _check(lib().hs_dbg_ring(self.h, code, level, arg, x, x.size, np.zeros(1, np.uint64), 0,
+                                 ctypes.byref(used)))
+        out = np.zeros(used.value, dtype=np.uint64)
+        _check(lib().hs_dbg_ring(self.h, code, level, arg, x, x.size, out, out.size, ctypes.byref(used)))
+        return out.reshape(-1, self.N)
 
     def ntt(self, rows, prime, inverse=False):
         x = np.ascontiguousarray(rows, dtype=np.uint64).copy()

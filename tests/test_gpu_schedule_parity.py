@@ -1,0 +1,87 @@
+"""The whole encrypted Softmax schedule (hs_softmax: Algorithm SM and SM
+version B with the auxiliary thread and the many-ciphertext packing) against
+the oracle's schedule (oracle/schedule.py, oracle/polyeval.py) on the same
+keys and encryptions: the output ciphertexts must be equal word for word.
+
+Both sides take every floating-point decision (polynomial coefficients,
+intervals, scales, integer constants) by the same specification, so one
+differing word would show a schedule, a polynomial or an evaluation-order
+mismatch.  The intermediate y0 = exp(x / 2^k) / sqrt(n) (after the first
+polynomial) is compared first, to localise a difference.  Toy ring N = 2^12
+(no bootstrapping: the schedule must fit its 23 levels)."""
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+SEED = 4242
+CASES = [
+    # (variant, m, n, M, exp degree, normalisation degrees)
+    (0, 1, 16, 8.0, 7, (15, 15, 31)),
+    (1, 1, 16, 8.0, 7, (15, 15, 31)),
+    (1, 2, 16, 8.0, 7, (15, 15, 31)),
+    (1, 4, 64, 8.0, 7, (15, 15, 15)),
+]
+
+
+@pytest.fixture(scope="module")
+def pair():
+    from paper_2410_11184_amd import hs
+    from oracle import ckks
+    p = synthetic.preset("toy12")
+    g = hs.Context(p)
+    o = ckks.Context(**p)
+    g.keygen(SEED)
+    o.keygen(SEED)
+    return g, o
+
+
+def _inputs(g, o, n, M, m, seed):
+    from oracle import softmax as S
+    L = m * o.slots // n
+    x = synthetic.logits_uniform(L, n, M, seed=seed)
+    packed = S.pack(x, m, o.slots)
+    scale = o.delta * 2.0 / M
+    top = synthetic.preset("toy12")["user_top"]
+    gx = [g.encrypt(packed[j], top, scale, seed + 100 + j) for j in range(m)]
+    ox = [o.encode_encrypt(packed[j], scale, top, seed + 100 + j) for j in range(m)]
+    for a, b in zip(gx, ox):
+        w = a.export()
+        assert np.array_equal(w[0], b.c[0]) and np.array_equal(w[1], b.c[1])
+    return x, gx, ox
+
+
+def _compare(g, o, gy, oy, what):
+    assert len(gy) == len(oy)
+    for i, (a, b) in enumerate(zip(gy, oy)):
+        assert a.level == b.level, (what, i, a.level, b.level)
+        assert a.scale == b.scale, (what, i, a.scale, b.scale)
+        w = a.export()
+        for k in range(2):
+            if not np.array_equal(w[k], b.c[k]):
+                diff = np.max(np.abs(g.decrypt(a) - o.decrypt_decode(b)))
+                bad = np.argwhere(w[k] != b.c[k])
+                pytest.fail("%s: ciphertext %d component %d differs in %d words (first %s); "
+                            "decrypted max difference %.3g" % (what, i, k, len(bad), bad[0], diff))
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "v%d-m%d-n%d" % (c[0], c[1], c[2]))
+def test_schedule_matches_oracle(pair, case):
+    from oracle import schedule, softmax as S
+    g, o = pair
+    variant, m, n, M, dexp, dinv = case
+    x, gx, ox = _inputs(g, o, n, M, m, seed=700 + 10 * variant + m)
+    # first polynomial alone
+    gy0 = g.softmax(gx, n, M, variant=variant, exp_degree=dexp, inv_degrees=dinv, debug_stop=0)
+    oy0 = schedule.softmax(o, ox, n, M, variant=variant, exp_degree=dexp, inv_degrees=dinv, debug_stop=0)
+    _compare(g, o, gy0, oy0, "y0")
+    # the whole schedule
+    gy = g.softmax(gx, n, M, variant=variant, exp_degree=dexp, inv_degrees=dinv)
+    oy = schedule.softmax(o, ox, n, M, variant=variant, exp_degree=dexp, inv_degrees=dinv)
+    _compare(g, o, gy, oy, "output")
+    y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy]), n)
+    bits = S.precision_bits(S.softmax(x), y)
+    print(case, bits)
+    assert bits["worst"] >= 16.0

@@ -133,3 +133,30 @@ def test_cheb_interp_reproduces_polynomials():
     e = P.exp_table(128.0, 5, 15)
     g = np.linspace(-128, 0, 10001)
     assert np.max(np.abs(P.cheb_eval(e, g, -128.0, 0.0) - np.exp(g / 32))) < 2 ** -40
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_encrypted_schedule_on_toy_ring(variant):
+    # The oracle's encrypted schedule (Algorithm SM / version B with the
+    # auxiliary thread, oracle/schedule.py) on the toy ring: after the first
+    # polynomial the slots hold exp(x / 2^k) / sqrt(n) (closed form), and the
+    # decrypted output is the FP64 Softmax to >= 16 bits with rows summing to 1.
+    import synthetic
+    from oracle import ckks, schedule
+    p = synthetic.preset("toy12")
+    o = ckks.Context(**p)
+    o.keygen(99)
+    n, M, m = 16, 8.0, 2
+    L = m * o.slots // n
+    x = synthetic.logits_uniform(L, n, M, seed=123 + variant)
+    packed = S.pack(x, m, o.slots)
+    xs = [o.encode_encrypt(packed[j], o.delta * 2.0 / M, p["user_top"], 5 + j) for j in range(m)]
+    k = schedule.theorem_k(n, M)
+    y0 = schedule.softmax(o, xs, n, M, variant=variant, exp_degree=7, inv_degrees=(15, 15, 31), debug_stop=0)
+    got0 = S.unpack(np.stack([o.decrypt_decode(c).real for c in y0]), n)
+    assert np.max(np.abs(got0 - np.exp(x / 2.0 ** k) / np.sqrt(n))) < 2.0 ** -20
+    ys = schedule.softmax(o, xs, n, M, variant=variant, exp_degree=7, inv_degrees=(15, 15, 31))
+    y = S.unpack(np.stack([o.decrypt_decode(c).real for c in ys]), n)
+    bits = S.precision_bits(S.softmax(x), y)
+    assert bits["worst"] >= 16.0, bits
+    assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2.0 ** -14
