@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = {
     "toy12": dict(modup=[20, 4, 23], moddown=[20, 4, 0], rescale=[23, 1], tensor=[7]),
-    "fgb16": dict(modup=[12, 30], moddown=[12, 30], rescale=[12, 1], tensor=[5]),
+    "fgb16": dict(modup=[12, 29], moddown=[12, 29], rescale=[12, 1], tensor=[5]),
 }
 
 
