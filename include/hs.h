@@ -174,6 +174,34 @@ hs_status hs_rescale(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
 /* Mult (Section 2.2): tensor, relinearise and, if rescale != 0, rescale;
  * operands at different levels are first brought to the lower one. */
 hs_status hs_mult_relin(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, int rescale, hs_ct** out);
+/* Allocation-free Mult, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the product of hs_mult_relin on raw device buffers, with every
+ * intermediate in a fixed scratch array of 96 MiB per device, held by the
+ * library from its first context on that device until the process ends.
+ * a, b: device pointers to two degree-1 ciphertexts at `level`, each
+ * [2][level+1][N] uint64 residues (NTT domain; the layout hs_ct_export
+ * writes), scales scale_a and scale_b.  out: device pointer receiving
+ * [2][level'+1][N] with level' = level - (rescale != 0); it must not overlap
+ * a or b.  All three 256-byte aligned; they stay owned by the caller, and
+ * the work is issued on the context's stream (asynchronous: synchronise
+ * before reading out).  *out_scale (may be NULL) receives the output scale.
+ * The words equal those of hs_mult_relin(a, b, rescale).  The call makes no
+ * hipMalloc / hipFree and tunes nothing.
+ * Errors: HS_E_ARG for null or misaligned pointers, overlap, non-positive
+ * scales, or a level whose intermediates exceed the scratch (the message
+ * gives the need; at N = 2^16 with 9 special primes and 8-prime digits,
+ * levels up to 13 fit, every user level of that chain); HS_E_LEVEL for a level outside 0..top (or 0 with
+ * rescale); HS_E_KEY without the relinearisation key; HS_E_STATE while the
+ * launch profiler is on, or before the key-switching tables of this level
+ * exist (they are built by the first key switch at that level, e.g. one
+ * hs_mult_relin); HS_E_DEVICE if the scratch array's device address could
+ * not be looked up.  Every call on one device shares that device's array and
+ * leaves its contents behind: calls that overlap on one GPU (two host
+ * threads, or contexts on different streams) race and must be serialised by
+ * the caller. */
+hs_status hs_mult_relin_noalloc(hs_ctx* ctx, const uint64_t* a, const uint64_t* b, int level, double scale_a,
+                                double scale_b, int rescale, uint64_t* out, double* out_scale);
 /* Rot (Section 2.2): left rotation of the slots by r (needs its key). */
 hs_status hs_rotate(hs_ctx* ctx, const hs_ct* a, int32_t r, hs_ct** out);
 /* Rot by several offsets of one ciphertext sharing one ModUp (hoisting; the

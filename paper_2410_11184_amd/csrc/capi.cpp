@@ -425,6 +425,82 @@ hs_status hs_mult_relin(hs_ctx* ctx, const hs_ct* a, const hs_ct* b, int rescale
     });
 }
 
+// Scratch bytes of op_mult_into at one level (one ciphertext), by the order of
+// its allocations: tensor d, relinearised r (rescale only), ModUp's extension
+// and coefficient copy, then the inner product and the conversion; the
+// rescale's two buffers fit in the tensor's freed block.
+static size_t mult_scratch_bytes(const hs::Context& c, int level, bool rescale) {
+    const size_t row = (size_t)c.N * 8;
+    auto blk = [&](size_t rows) { return (rows * row + 255) & ~(size_t)255; };
+    const size_t nql = (size_t)level + 1, E = nql + c.np;
+    const size_t beta = (nql + c.prm.digit - 1) / c.prm.digit;
+    const size_t base = blk(3 * nql) + (rescale ? blk(2 * nql) : 0) + blk(beta * E);
+    return std::max(base + blk(nql), base + blk(2 * E) + blk(2 * nql));
+}
+
+hs_status hs_mult_relin_noalloc(hs_ctx* ctx, const uint64_t* a, const uint64_t* b, int level, double scale_a,
+                                double scale_b, int rescale, uint64_t* out, double* out_scale) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(a);
+        NEED(b);
+        NEED(out);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(level >= 0 && level <= c.L, hs::E_LEVEL, "level out of range");
+        HS_REQUIRE(!rescale || level >= 1, hs::E_LEVEL, "rescale needs level >= 1");
+        HS_REQUIRE(scale_a > 0 && scale_b > 0, hs::E_ARG, "scales must be positive");
+        const size_t need = mult_scratch_bytes(c, level, rescale != 0);
+        if (need > hs::kScratchBytes) {
+            char msg[200];
+            std::snprintf(msg, sizeof msg, "this level needs %.1f MiB of scratch; the fixed scratch holds %.0f MiB",
+                          need / 1048576.0, hs::kScratchBytes / 1048576.0);
+            throw hs::Error(hs::E_ARG, msg);
+        }
+        const size_t in_bytes = (size_t)2 * (level + 1) * c.N * 8;
+        const size_t out_bytes = (size_t)2 * (level + (rescale ? 0 : 1)) * c.N * 8;
+        for (const void* p : {(const void*)a, (const void*)b, (const void*)out})
+            HS_REQUIRE(((uintptr_t)p & 255) == 0, hs::E_ARG, "device pointers must be 256-byte aligned");
+        auto overlap = [](const void* x, size_t nx, const void* y, size_t ny) {
+            const uintptr_t u = (uintptr_t)x, v = (uintptr_t)y;
+            return u < v + ny && v < u + nx;
+        };
+        HS_REQUIRE(!overlap(out, out_bytes, a, in_bytes) && !overlap(out, out_bytes, b, in_bytes), hs::E_ARG,
+                   "out overlaps an input");
+        HS_REQUIRE(hs::has_key(c, 0), hs::E_KEY, "relinearisation key missing");
+        HS_REQUIRE(!hs::prof_enabled(c.T.prof), hs::E_STATE, "the launch profiler allocates events: disable it");
+        const int nql = level + 1;
+        const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
+        for (int j = 0; j < beta; j++)
+            HS_REQUIRE(c.modup.count(std::make_pair(level, j)) != 0, hs::E_STATE,
+                       "key-switching tables of this level not built yet: run one hs_mult_relin at this level first");
+        HS_REQUIRE(c.moddown.count(level) != 0, hs::E_STATE,
+                   "key-switching tables of this level not built yet: run one hs_mult_relin at this level first");
+        void* base = hs::scratch_device_ptr(c.device);
+        HS_REQUIRE(base != nullptr, hs::E_DEVICE, "device address of the scratch array unknown (lookup failed)");
+        hs::Pool sp;
+        sp.adopt(base, hs::kScratchBytes);
+        hs::Pool* prev = c.cur;
+        c.cur = &sp;
+        hs::tune_suspend(true);
+        struct Restore {
+            hs::Context& c;
+            hs::Pool* prev;
+            ~Restore() {
+                c.cur = prev;
+                hs::tune_suspend(false);
+            }
+        } restore{c, prev};
+        hs::Ct A, B;
+        A.d = const_cast<uint64_t*>(a);
+        B.d = const_cast<uint64_t*>(b);
+        A.level = B.level = level;
+        A.scale = scale_a;
+        B.scale = scale_b;
+        const double s = hs::op_mult_into(c, A, B, rescale != 0, out);
+        if (out_scale) *out_scale = s;
+    });
+}
+
 hs_status hs_rotate(hs_ctx* ctx, const hs_ct* a, int32_t r, hs_ct** out) {
     if (out) *out = nullptr;
     return guard([&] {

@@ -145,6 +145,7 @@ void Pool::remove_free(int c, size_t off, size_t size) {
 void* Pool::alloc(size_t bytes) {
     bytes = ((bytes ? bytes : 1) + 255) & ~(size_t)255;
     auto it = by_size_.lower_bound(bytes);
+    if (it == by_size_.end() && fixed_) throw Error(E_OOM, "fixed scratch region exhausted");
     if (it == by_size_.end()) {
         // new chunk: 8 GiB, or the request rounded up to 1 GiB
         size_t want = std::max(kChunk, (bytes + ((size_t)1 << 30) - 1) & ~(((size_t)1 << 30) - 1));
@@ -212,8 +213,20 @@ void Pool::free(void* p) {
     add_free(c, off, size);
 }
 
+void Pool::adopt(void* base, size_t bytes) {
+    release_all();
+    fixed_ = true;
+    Chunk ch;
+    ch.base = (char*)base;
+    ch.size = bytes & ~(size_t)255;
+    chunks_.push_back(ch);
+    reserved_ = ch.size;
+    add_free(0, 0, ch.size);
+}
+
 size_t Pool::trim(size_t bytes) {
     // only chunks with no live block can go back to the device
+    if (fixed_) return 0;
     size_t released = 0;
     for (int c = (int)chunks_.size() - 1; c >= 0 && released < bytes; c--) {
         Chunk& ch = chunks_[c];
@@ -231,8 +244,9 @@ size_t Pool::trim(size_t bytes) {
 }
 
 void Pool::release_all() {
-    for (auto& ch : chunks_)
-        if (ch.base) hipFree(ch.base);
+    if (!fixed_)
+        for (auto& ch : chunks_)
+            if (ch.base) hipFree(ch.base);
     chunks_.clear();
     by_size_.clear();
     live_.clear();
@@ -308,6 +322,10 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     for (int b : p.q_bits) HS_REQUIRE(b >= 32 && b <= 61, E_PARAM, "prime sizes must be in [32, 61] bits");
     for (int b : p.p_bits) HS_REQUIRE(b >= 32 && b <= 61, E_PARAM, "prime sizes must be in [32, 61] bits");
     check_hip(hipSetDevice(dev), "hipSetDevice");
+    // device address of the allocation-free entry point's scratch array (once
+    // per device, with the device current); a failed lookup only disables
+    // that entry point
+    scratch_init(dev);
     stream = st;
     logN = p.logN;
     N = 1 << logN;

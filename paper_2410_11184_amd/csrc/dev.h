@@ -96,6 +96,15 @@ struct ConvTables {
     int ntb;                // ceil(m / 16): 16-target blocks
 };
 
+// Fixed device scratch of the allocation-free entry point (scratch.hip):
+// kScratchBytes per device, looked up once per device at context creation
+// (with the device current).  scratch_init returns 1 when the array's device
+// address is known, -1 when the lookup failed; scratch_device_ptr returns
+// that address (null before a successful lookup).
+constexpr size_t kScratchBytes = (size_t)96 << 20;
+int scratch_init(int device);
+void* scratch_device_ptr(int device);
+
 // Autotuner over interchangeable kernel variants (base conversion: VALU or
 // matrix cores; N = 2^16 NTT: row order and launch batching).  Off unless
 // enabled (or HS_TUNE=1); decisions are process-wide.
@@ -103,6 +112,9 @@ void tune_enable(bool on);
 void tune_clear();                       // forget every decision (defaults again)
 std::string tune_dump();                 // one JSON object per line
 int tune_load(const std::string& text);  // entries taken
+// while suspended (a counter: nested calls), shapes without a decision use the
+// default kernel and nothing is timed (timing allocates scratch buffers)
+void tune_suspend(bool on);
 
 // Epilogue of a forward NTT of rows x (groups G = 0..ngroups-1, rows r of a
 // group use primes q_off + r): instead of NTT(x), write

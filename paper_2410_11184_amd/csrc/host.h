@@ -76,6 +76,9 @@ public:
     void free(void* p);
     void release_all();
     size_t trim(size_t bytes);   // release wholly free chunks until >= bytes freed
+    // a fixed region instead of hipMalloc chunks: the pool never grows (an
+    // allocation that does not fit raises E_OOM) and never frees it
+    void adopt(void* base, size_t bytes);
     bool owns(const void* p) const { return live_.count(const_cast<void*>(p)) != 0; }
     size_t bytes_in_use() const { return in_use_; }
     size_t bytes_reserved() const { return reserved_; }
@@ -91,6 +94,7 @@ private:
     std::multimap<size_t, std::pair<int, size_t>> by_size_;   // size -> (chunk, offset)
     std::map<void*, std::pair<int, size_t>> live_;            // pointer -> (chunk, size)
     size_t in_use_ = 0, reserved_ = 0;
+    bool fixed_ = false;
     void add_free(int c, size_t off, size_t size);
     void remove_free(int c, size_t off, size_t size);
 };
@@ -264,6 +268,9 @@ Ct op_square_sum_jobs(Context& c, const Ct& a, int jobs);  // one such sum per g
 Ct op_relin(Context& c, const Ct& d);
 Ct op_rescale(Context& c, const Ct& a);
 Ct op_mult(Context& c, const Ct& a, const Ct& b);            // tensor, relin, rescale
+// the same product of two ciphertexts of one level written to out (rows of
+// the output level); returns the output scale
+double op_mult_into(Context& c, const Ct& a, const Ct& b, bool rescale, u64* out);
 Ct op_apply_galois(Context& c, const Ct& a, int g);
 Ct op_rotate(Context& c, const Ct& a, int r);
 Ct op_conjugate(Context& c, const Ct& a);

@@ -1213,8 +1213,10 @@ struct TuneEntry {
 std::mutex g_tune_mu;
 std::map<std::string, TuneEntry> g_tune;
 int g_tune_on = -1;
+thread_local int g_tune_suspended = 0;
 
 bool tuning_on() {
+    if (g_tune_suspended > 0) return false;
     if (g_tune_on < 0) {
         const char* e = std::getenv("HS_TUNE");
         g_tune_on = (e && std::string(e) == "1") ? 1 : 0;
@@ -1365,6 +1367,8 @@ int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st, 
 }
 
 void tune_enable(bool on) { g_tune_on = on ? 1 : 0; }
+
+void tune_suspend(bool on) { g_tune_suspended += on ? 1 : -1; }
 
 void tune_clear() {
     std::lock_guard<std::mutex> lk(g_tune_mu);

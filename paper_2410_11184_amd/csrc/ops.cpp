@@ -119,7 +119,9 @@ void op_add_const_inplace(Context& c, Ct& a, double v) {
     k_add_row_const(c.T, r, r, rc, c.stream);
 }
 
-Ct op_rescale(Context& c, const Ct& a) {
+// Rescale of a into out (a.m a.ncomp groups of l rows, l = a.level): the
+// rows are written, nothing else; returns the output scale.
+static double rescale_into(Context& c, const Ct& a, u64* out) {
     HS_REQUIRE(a.level >= 1, E_LEVEL, "rescale: no level left");
     const int l = a.level;
     const int np_ = a.m * a.ncomp;
@@ -130,13 +132,12 @@ Ct op_rescale(Context& c, const Ct& a) {
     Rows r_last{last, np_, 1, N, 1, l, c.nq};
     k_ntt_from(c.T, r_last, in_last, true, c.stream);
     Rows r_lift{lifted, np_, l, (size_t)l * N, l, 0, c.nq};
-    Ct o = ct_alloc(c, a.m, a.ncomp, l - 1);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = invmod_h(c.primes[l] % c.primes[i], c.primes[i]);
     // out = (a - NTT(lifted)) q_l^-1, fused into the transform's last pass
     NttEpilogue e;
     e.c = c.shoup_consts(inv, 0);
-    e.out[0] = o.d;
+    e.out[0] = out;
     e.out_gs[0] = (size_t)l * N;
     e.a = a.d;
     e.a_gs = (size_t)(l + 1) * N;
@@ -146,9 +147,15 @@ Ct op_rescale(Context& c, const Ct& a) {
     lf.gs = N;
     lf.src_prime = l;
     k_ntt_epilogue(c.T, r_lift, e, c.stream, &lf);
-    o.scale = a.scale / (double)c.primes[l];
     c.free_words(last);
     c.free_words(lifted);
+    return a.scale / (double)c.primes[l];
+}
+
+Ct op_rescale(Context& c, const Ct& a) {
+    HS_REQUIRE(a.level >= 1, E_LEVEL, "rescale: no level left");
+    Ct o = ct_alloc(c, a.m, a.ncomp, a.level - 1);
+    o.scale = rescale_into(c, a, o.d);
     return o;
 }
 
@@ -225,11 +232,12 @@ static u64* ks_modup(Context& c, const Rows& d, int level) {
     const int E = nql + c.np;
     const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
     const size_t N = c.N;
-    // coefficient-domain copy of d
+    // the extension first, then the coefficient-domain copy of d (freed
+    // first, so its block rejoins the free space behind the extension)
+    u64* ext = c.alloc_words((size_t)m * beta * E * N);
     u64* dc = c.alloc_words((size_t)m * nql * N);
     Rows rdc{dc, m, nql, (size_t)nql * N, nql, 0, c.nq};
     k_ntt_from(c.T, rdc, d, true, c.stream);
-    u64* ext = c.alloc_words((size_t)m * beta * E * N);
     const size_t xg = (size_t)beta * E * N;
     // at N = 2^16 the digit's own rows are taken from d (already in the NTT
     // domain) and the one forward launch skips them; elsewhere they are
@@ -346,15 +354,44 @@ void key_switch(Context& c, const Rows& d, int level, const u64* key, u64* out0,
     c.free_words(ext);
 }
 
-Ct op_relin(Context& c, const Ct& d) {
+// relinearisation of d into o (allocated by the caller, d's shape with two
+// components)
+static void relin_into(Context& c, const Ct& d, Ct& o) {
     HS_REQUIRE(d.ncomp == 3, E_ARG, "relin: degree-2 input expected");
     HS_REQUIRE(has_key(c, 0), E_KEY, "relinearisation key missing");
-    Ct o = ct_alloc(c, d.m, 2, d.level);
     o.scale = d.scale;
     Rows d2 = c.comp_rows(d, 2);
     Rows a0 = c.comp_rows(d, 0), a1 = c.comp_rows(d, 1);
     key_switch(c, d2, d.level, c.keys.at(0), o.d, o.d + o.comp_words(c.N), o.ct_words(c.N), &a0, &a1);
+}
+
+Ct op_relin(Context& c, const Ct& d) {
+    HS_REQUIRE(d.ncomp == 3, E_ARG, "relin: degree-2 input expected");
+    HS_REQUIRE(has_key(c, 0), E_KEY, "relinearisation key missing");
+    Ct o = ct_alloc(c, d.m, 2, d.level);
+    relin_into(c, d, o);
     return o;
+}
+
+// Mult (tensor, relinearisation and, when rescale is set, rescale) of two
+// degree-1 ciphertexts of one level, written to out (two components at the
+// output level); intermediates come from the current arena.  The kernels and
+// their order are op_mult's (and hs_mult_relin's without rescale), so the
+// words are the same.  Returns the output scale.
+double op_mult_into(Context& c, const Ct& a, const Ct& b, bool rescale, u64* out) {
+    HS_REQUIRE(a.level == b.level, E_LEVEL, "mult: levels differ");
+    Ct d = op_tensor(c, a, b);
+    Ct r;
+    r.m = d.m;
+    r.ncomp = 2;
+    r.level = d.level;
+    r.d = rescale ? c.alloc_words(r.ct_words(c.N)) : out;
+    relin_into(c, d, r);
+    ct_free(c, d);
+    if (!rescale) return r.scale;
+    const double s = rescale_into(c, r, out);
+    c.free_words(r.d);
+    return s;
 }
 
 Ct op_mult(Context& c, const Ct& a, const Ct& b) {

@@ -65,6 +65,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libhs.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    # torch first: its HIP runtime (same soname as the one libhs.so names) is
+    # then the only one in the process, shared by the library and by the
+    # device memory and streams that torch hands to it; loading the library
+    # first would bring a second HIP runtime in beside torch's
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     S = ctypes.c_int
     L.hs_version.restype = ctypes.c_char_p
@@ -94,6 +99,8 @@ def lib():
         "hs_relinearize": [_vp, _vp, ctypes.POINTER(_vp)],
         "hs_rescale": [_vp, _vp, ctypes.POINTER(_vp)],
         "hs_mult_relin": [_vp, _vp, _vp, S, ctypes.POINTER(_vp)],
+        "hs_mult_relin_noalloc": [_vp, _vp, _vp, S, ctypes.c_double, ctypes.c_double, S, _vp,
+                                  ctypes.POINTER(ctypes.c_double)],
         "hs_rotate": [_vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)],
         "hs_rotate_hoisted": [_vp, _vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, ctypes.POINTER(_vp)],
         "hs_rotate_batch": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
@@ -406,6 +413,16 @@ class Context:
 
     def mult(self, a, b, rescale=True):
         return self._op("hs_mult_relin", a.h, b.h, 1 if rescale else 0)
+
+    def mult_noalloc(self, a_ptr, b_ptr, level, scale_a, scale_b, out_ptr, rescale=True):
+        """hs_mult_relin_noalloc on raw device buffers (integer addresses of
+        [2][level+1][N] uint64 residues each; out receives the product's
+        [2][level'+1][N]); returns the output scale.  Asynchronous on the
+        context's stream."""
+        sc = ctypes.c_double()
+        _check(lib().hs_mult_relin_noalloc(self.h, _vp(a_ptr), _vp(b_ptr), level, scale_a, scale_b,
+                                           1 if rescale else 0, _vp(out_ptr), ctypes.byref(sc)))
+        return sc.value
 
     def rotate(self, a, r):
         return self._op("hs_rotate", a.h, r)
