@@ -1,0 +1,102 @@
+"""The N = 2^16 workloads beyond the metric's job, on the benchmark's ring:
+
+* lockstep jobs of the attention-layer shape (Section 5.2, the LLaMA-shaped
+  run: 16 ciphertexts per job, 4096 Softmax of dimension 128, logits
+  N(0, 4^2) clipped to [-64, 0]): every job's output ciphertexts are the
+  same words alone and in the lockstep batch, and each job meets >= 16 bits
+  against the FP64 Softmax;
+* the paper's own input law (Section 5.2, "Input distribution":
+  N(-M/2, (M/6)^2) tail-cut to [-M, 0]) at dimension 256 with M = 128
+  (version B, 64 ciphertexts: 8192 Softmax, more than the paper's 5000) and
+  M = 256 (Algorithm SM, as in the paper's table for that range: version B's
+  main thread needs k + 2 levels after the exponential, one more than the
+  twelve user levels leave at k = 6; 8 ciphertexts, 1024 Softmax);
+* a small serving mix at full size (dimensions 256, 4096 and 32768, two
+  workers): each result the same alone and in the mix, the batches of the
+  two workers overlapping in time, and the precision of each dimension
+  (>= 16 bits at 256; the larger dimensions at the precision their
+  polynomials reach, reported)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import softmax as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_11184_amd import hs
+    c = hs.Context(synthetic.preset("fgb16"), device=0, stream=hs.current_stream())
+    c.keygen(2003)
+    return c
+
+
+def test_layer_jobs_in_lockstep(ctx):
+    from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
+    g = synthetic.WORKLOADS["fgb16_uneven"]["groups"][0]
+    J, n, M, m = 3, g["n"], g["M"], g["m"]
+    xs = [synthetic.group_logits("fgb16_uneven", 0, j) for j in range(J)]
+    cts = [encrypt_logits(ctx, x, M, seed=4000 + j) for j, x in enumerate(xs)]
+    print("layer jobs: %d x %d ciphertexts, n=%d, M=%g" % (J, m, n, M), flush=True)
+    together = ctx.softmax([c for cj in cts for c in cj], n, M, variant=1, jobs=J)
+    assert len(together) == J * m
+    for j in range(J):
+        alone = ctx.softmax(cts[j], n, M, variant=1)
+        for i in range(m):
+            assert np.array_equal(alone[i].export(), together[j * m + i].export()), (j, i)
+        bits = S.precision_bits(S.softmax(xs[j]), decrypt_outputs(ctx, together[j * m:(j + 1) * m], n))
+        print("job %d: %s" % (j, bits))
+        assert bits["worst"] >= 16.0, (j, bits)
+
+
+@pytest.mark.parametrize("M", [128.0, 256.0])
+def test_paper_input_law(ctx, M):
+    from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
+    n = 256
+    m, variant = (64, 1) if M <= 128 else (8, 0)
+    L = m * ctx.slots // n
+    x = synthetic.logits_paper(L, n, M, seed=1160 + int(M))
+    cts = encrypt_logits(ctx, x, M, seed=5160 + int(M))
+    print("paper law: M=%g, %d Softmax of dim %d" % (M, L, n), flush=True)
+    y = decrypt_outputs(ctx, ctx.softmax(cts, n, M, variant=variant), n)
+    bits = S.precision_bits(S.softmax(x), y)
+    print("M=%g: %s, stats %s" % (M, bits, ctx.softmax_stats()))
+    assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -12
+    # M = 128 carries the metric's 16-bit bar; at M = 256 the paper reports
+    # 16.6 bits worst case for Algorithm SM with weighted-minimax
+    # normalisation polynomials, and these Chebyshev interpolants reach about
+    # 15.8 (measured 15.77 on this input)
+    assert bits["worst"] >= (16.0 if M <= 128 else 15.5), bits
+
+
+def test_serving_at_full_size():
+    from paper_2410_11184_amd import serve
+    p = synthetic.preset("fgb16")
+    rng = np.random.default_rng(1004)
+    mix = []
+    for rid, (n, V) in enumerate([(256, 300), (4096, 5), (256, 40), (32768, 1), (4096, 3), (256, 128)]):
+        mix.append((rid, synthetic.logits_uniform(V, n, 128.0 if n < 32768 else 256.0, seed=int(rng.integers(1 << 30)))))
+    srv = serve.SoftmaxServer(p, workers=2, hbm_budget_gb=120.0, variant=1, key_seed=2004)
+    mixed = [srv.submit(rid, x, 128.0 if x.shape[1] < 32768 else 256.0) for rid, x in mix]
+    for r in mixed:
+        assert r.done.wait(600)
+    srv.close()
+    assert all(r.error is None for r in mixed), [str(r.error) for r in mixed if r.error]
+    assert len({r.worker for r in mixed}) == 2, "one worker did all the work"
+    spans = sorted((r.t_start, r.t_done, r.worker) for r in mixed)
+    overlap = any(a[2] != b[2] and a[0] < b[1] and b[0] < a[1] for i, a in enumerate(spans) for b in spans[i + 1:])
+    assert overlap, "the two workers' batches never overlapped in time"
+    alone = serve.SoftmaxServer(p, workers=1, hbm_budget_gb=120.0, variant=1, key_seed=2004)
+    worst = {}
+    for (rid, x), rm in zip(mix, mixed):
+        ra = alone.submit(rid, x, 128.0 if x.shape[1] < 32768 else 256.0)
+        assert ra.done.wait(600) and ra.error is None
+        assert np.array_equal(ra.result, rm.result), "request %d differs alone and in the mix" % rid
+        b = S.precision_bits(S.softmax(x), rm.result)["worst"]
+        worst[x.shape[1]] = min(worst.get(x.shape[1], 99.0), b)
+    alone.close()
+    print("worst bits by dimension:", worst, "latency:", serve.latency_stats(mixed))
+    assert worst[256] >= 16.0, worst
+    assert worst[4096] >= 12.0 and worst[32768] >= 7.0, worst
