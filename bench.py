@@ -72,29 +72,135 @@ def _traffic(kind, algorithmic_bytes_per_launch):
         return None
 
 
-def cpu_baseline(seconds_budget=12.0):
-    """The oracle (plain single-threaded C + Python) timed on this host on a
-    bounded sample: key switches of one ciphertext at N = 2^16, which dominate
-    the job.  Returned as Softmax calls/s by scaling with the number of key
-    switches (at their levels) the GPU job performed."""
+ORACLE_LEVELS = (1, 6, 12, 20, 29)
+OP_KINDS = ("keyswitch", "tensor", "rescale", "ptmul", "add")
+
+
+def oracle_op_seconds(levels=ORACLE_LEVELS):
+    """The oracle (plain single-threaded C + Python) timed on this host, pinned
+    to one CPU, on one operation of each counted kind at each of `levels` of
+    the N = 2^16 ring: key switch (a relinearisation), tensor product,
+    rescale, plaintext product, addition.  Returns ({kind: {level: s}},
+    total seconds of the sample)."""
     import synthetic
     from oracle import ckks
-    p = synthetic.preset("fgb16")
+    cpus = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {min(cpus)})
+    try:
+        t_start = time.perf_counter()
+        p = synthetic.preset("fgb16")
+        o = ckks.Context(**p)
+        o.keygen(11)                      # relinearisation key
+        z = np.random.default_rng(0).uniform(-1, 1, o.slots)
+        out = {k: {} for k in OP_KINDS}
+        for lv in levels:
+            a = o.encode_encrypt(z, o.delta, lv, 3)
+            b = o.encode_encrypt(z, o.delta, lv, 4)
+            pt = [o.ntt(np.zeros(o.N, dtype=np.uint64), i) for i in range(lv + 1)]
+            t = time.perf_counter()
+            d = o.tensor(a, b)
+            out["tensor"][lv] = time.perf_counter() - t
+            t = time.perf_counter()
+            r = o.relinearize(d)
+            out["keyswitch"][lv] = time.perf_counter() - t
+            t = time.perf_counter()
+            o.rescale(r)
+            out["rescale"][lv] = time.perf_counter() - t
+            t = time.perf_counter()
+            o.mul_plain(a, pt, 1.0)
+            out["ptmul"][lv] = time.perf_counter() - t
+            t = time.perf_counter()
+            o.add_ct(a, b)
+            out["add"][lv] = time.perf_counter() - t
+        return out, time.perf_counter() - t_start
+    finally:
+        os.sched_setaffinity(0, cpus)
+
+
+def oracle_job_model(counts, op_s):
+    """Seconds the oracle would take for a job with these operation counts
+    ({kind: {level: ciphertext equivalents}}), each operation at its level
+    priced by linear interpolation between the timed levels."""
+    total = 0.0
+    for kind, by_level in counts.items():
+        lv_t = sorted(op_s[kind].items())
+        xs = [l for l, _ in lv_t]
+        ys = [v for _, v in lv_t]
+        for lv, n in by_level.items():
+            total += n * float(np.interp(lv, xs, ys))
+    return total
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_toy_job(seed, cpu):
+    """One end-to-end run of the oracle on the plain toy workload (N = 2^12,
+    one ciphertext of 128 Softmax of dimension 16, logits U[-8, 0], Algorithm
+    SM without bootstrapping): keygen, encryption, the Softmax schedule,
+    decryption; pinned to one CPU when `cpu` is given.  Runs in a child
+    process started before this process touches the GPU; prints one JSON
+    line."""
+    if cpu is not None:
+        os.sched_setaffinity(0, {cpu})
+    import synthetic
+    from oracle import ckks, schedule, softmax as S
+    p = synthetic.preset("toy12")
+    w = synthetic.WORKLOADS["toy12_sm"]
     t0 = time.perf_counter()
     o = ckks.Context(**p)
-    o.keygen(11)                      # relinearisation key only
-    setup = time.perf_counter() - t0
-    z = np.random.default_rng(0).uniform(-1, 1, o.slots)
-    a = o.encode_encrypt(z, o.delta, p["user_top"], 3)
-    times = []
+    o.keygen(2000 + seed)
+    x = synthetic.workload_logits("toy12_sm", seed=w["seed"] + seed)
+    packed = S.pack(x, 1, o.slots)
+    ct = [o.encode_encrypt(packed[0], o.delta * 2.0 / w["M"], p["user_top"], 3000 + seed)]
+    t1 = time.perf_counter()
+    out = schedule.softmax(o, ct, w["n"], w["M"], variant=0, exp_degree=7, inv_degrees=(15, 15, 31))
+    t2 = time.perf_counter()
+    y = S.unpack(np.stack([o.decrypt_decode(c).real for c in out]), w["n"])
+    t3 = time.perf_counter()
+    print(json.dumps({"calls": w["L"], "setup_s": t1 - t0, "softmax_s": t2 - t1, "decrypt_s": t3 - t2,
+                      "worst_bits": S.precision_bits(S.softmax(x), y)["worst"]}), flush=True)
+
+
+def oracle_toy_runs(procs):
+    """The oracle's toy job end to end: once pinned to one CPU, then `procs`
+    independent copies at once, each pinned to its own CPU.  Child processes,
+    started before the GPU is touched."""
+    import subprocess
+    cpus = sorted(os.sched_getaffinity(0))
+
+    def launch(seed, cpu):
+        return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-job", str(seed),
+                                 "--oracle-cpu", str(cpu)], stdout=subprocess.PIPE, text=True)
+
+    def collect(ps):
+        out = []
+        for pr in ps:
+            txt, _ = pr.communicate(timeout=600)
+            if pr.returncode != 0:
+                raise RuntimeError("oracle job failed")
+            out.append(json.loads(txt.strip().splitlines()[-1]))
+        return out
+
     t0 = time.perf_counter()
-    while True:
-        s = time.perf_counter()
-        o.mult(a, a)
-        times.append(time.perf_counter() - s)
-        if time.perf_counter() - t0 > seconds_budget or len(times) >= 12:
-            break
-    return dict(hmult_s=float(np.median(times)), setup_s=setup, samples=len(times))
+    single = collect([launch(0, cpus[0])])[0]
+    t1 = time.perf_counter()
+    P = max(1, min(procs, len(cpus)))
+    runs = collect([launch(1 + i, cpus[i]) for i in range(P)])
+    t2 = time.perf_counter()
+    return {"workload": "toy ring N=2^12, 1 ciphertext, 128 Softmax of dim 16, U[-8,0], SM (configs[0] shape)",
+            "single_core": {"calls_per_s": single["calls"] / single["softmax_s"], "softmax_s": single["softmax_s"],
+                            "wall_s_incl_keygen_encrypt_decrypt": t1 - t0, "worst_bits": single["worst_bits"]},
+            "concurrent": {"processes": P, "calls_per_s": sum(r["calls"] for r in runs) /
+                           max(r["softmax_s"] for r in runs), "wall_s": t2 - t1,
+                           "worst_bits": min(r["worst_bits"] for r in runs)}}
 
 
 def calibrate_copy(nbytes=1 << 30, reps=3):
@@ -252,7 +358,14 @@ def main():
                     help="where --tune writes its decisions (the committed ones are %s)" % TUNE_FILE)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for the HBM byte counters)")
+    ap.add_argument("--oracle-job", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-cpu", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-procs", type=int, default=16,
+                    help="concurrent oracle processes for the host throughput figure (capped by the CPUs)")
     args = ap.parse_args()
+    if args.oracle_job is not None:
+        oracle_toy_job(args.oracle_job, args.oracle_cpu)
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return
@@ -262,6 +375,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    toy_oracle = None
+    if not args.no_cpu_baseline and args.workload == "fgb16_smb64":
+        # child processes: before this process touches the GPU
+        _log("oracle end to end on the toy workload (single core, then %d processes) ..." % args.oracle_procs)
+        toy_oracle = oracle_toy_runs(args.oracle_procs)
+        _log("oracle toy: %s" % toy_oracle)
     if args.workload == "fgb16_uneven":
         run_uneven(args)
         return
@@ -348,6 +467,7 @@ def main():
     # pair around every launch (graph replays carry no per-kernel events)
     ctx.prof_enable(True)
     ctx.sync()
+    ctx.op_counts(clear=True)
     t0 = time.perf_counter()
     for i in range(args.steps):
         out_e = ctx.softmax(cts, n, M, variant=variant)
@@ -355,6 +475,7 @@ def main():
     eager_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     ctx.prof_enable(False)
     prof = ctx.prof_collect()
+    job_ops = {k: {l: c / args.steps for l, c in v.items()} for k, v in ctx.op_counts(clear=True).items()}
     if graph:
         same = all(np.array_equal(a.export(), b.export()) for a, b in zip(out[:4], out_e[:4]))
         graph.update({"eager_profiled_ms_per_step": eager_ms, "replay_equals_eager_first4": same})
@@ -478,22 +599,21 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        _log("cpu baseline (oracle) ...")
-        cb = cpu_baseline()
-        # key switches of the job: one per ciphertext-level HMult/rotation; the
-        # GPU op trace is approximated by the profiler's key-inner launches
-        ks_rows = prof["keyip"]["bytes"] / (8.0 * p["N"]) if prof["keyip"]["launches"] else 0.0
-        cpu = dict(value=None, unit="Softmax calls/s", cores=1, kind="oracle",
-                   sample="median of %d oracle HMults (tensor+relinearise+rescale) of one N=2^16 ciphertext at "
-                          "level %d, single thread: %.2f s each" % (cb["samples"], p["user_top"], cb["hmult_s"]))
-        # model: the job's key-switch work divided by the level-12 HMult's
-        level_rows = (p["user_top"] + 1 + len(p["p_bits"]))
-        ref_ks = 8.0 * p["N"] * level_rows * (2 * 2 + 1 * (2 + 2))
-        if ks_rows > 0:
-            hmult_equiv = prof["keyip"]["bytes"] / args.steps / ref_ks
-            cpu["value"] = L / (hmult_equiv * cb["hmult_s"])
-            cpu["sample"] += "; scaled by the job's key-switch bytes (%.0f level-%d HMult equivalents per job)" % (
-                hmult_equiv, p["user_top"])
+        _log("cpu baseline (oracle operations at N=2^16) ...")
+        op_s, sample_s = oracle_op_seconds()
+        job_s = oracle_job_model(job_ops, op_s)
+        cpu = dict(value=L / job_s, unit="Softmax calls/s", cores=1, kind="oracle", modelled=True,
+                   sample="the oracle pinned to one CPU: one key switch, tensor, rescale, plaintext product and "
+                          "addition of an N=2^16 ciphertext at each of levels %s (%.1f s); the metric job's "
+                          "operation counts per level (the library's counters over the eager pass) priced with "
+                          "these times, linear in the level between samples: %.0f s per job of %d Softmax"
+                          % (list(ORACLE_LEVELS), sample_s, job_s, L),
+                   cpu_model=cpu_model(), host_cpus=len(os.sched_getaffinity(0)),
+                   job_ops={k: round(sum(v.values()), 1) for k, v in job_ops.items()},
+                   oracle_op_seconds={k: {str(l): round(t, 4) for l, t in v.items()} for k, v in op_s.items()},
+                   job_seconds_modelled=job_s,
+                   end_to_end_toy=toy_oracle)
+        _log("cpu baseline: %.2f calls/s modelled (%.0f s per job)" % (cpu["value"], job_s))
 
     rec = {
         "metric": "encrypted Softmax calls/s at dim 256, >=16-bit precision, batched vs plain",

@@ -359,6 +359,16 @@ hs_status hs_bootstrap(hs_ctx* ctx, const hs_ct* a, hs_ct** out);
 hs_status hs_prof_enable(hs_ctx* ctx, int on);
 hs_status hs_prof_collect(hs_ctx* ctx, double* out, size_t n);
 
+/* Homomorphic operations issued by the context since the last clear (not an
+ * operation of the paper: an account of the schedule for cost models of other
+ * implementations of it), by kind and input level, in ciphertext equivalents
+ * (one degree-1 ciphertext = 1): kind 0 key switches (relinearisations,
+ * rotations, conjugations), 1 tensor products (squares included), 2 rescales,
+ * 3 plaintext or constant products, 4 additions.  Writes min(n, 5 * 64)
+ * values out[kind * 64 + level] (out may be NULL); clears the counts when
+ * clear != 0.  Graph replays (hs_softmax_plan_run) are not counted. */
+hs_status hs_op_counts(hs_ctx* ctx, double* out, size_t n, int clear);
+
 /* Intermediate ciphertexts of hs_bootstrap, for tests: stage 1 = after
  * ModRaise (declared scale 2 q0 (K+1) N/2), 2 = after CoeffToSlot, 3 = real
  * part u after the conjugation split, 4 = real-part half of

@@ -352,6 +352,8 @@ static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x, bool do_resca
         }
         u64* dst = kv.first == 0 ? acc.d : inner.d + (size_t)(gi++) * cw;
         if (kv.first == 0) have0 = true;
+        c.count(OC_PTMUL, x.level, (double)x.m * as.size());
+        c.count(OC_ADD, x.level, (double)x.m * (as.size() - 1));
         k_mul_plain_acc(c.T, dst, as.data(), ps.data(), (int)as.size(), x.m * 2, x.level + 1, c.stream);
     }
     if (babies.d) ct_free(c, babies);
@@ -364,8 +366,12 @@ static Ct apply_level(Context& c, const LinLevel& lv, const Ct& x, bool do_resca
         for (size_t i = 0; i < giants.size(); i++) {
             Rows rr = ra;
             rr.base = rot.d + i * cw;
-            if (i == 0 && !have0) k_copy_rows(c.T, ra, rr, c.stream);
-            else k_add(c.T, ra, ra, rr, c.stream);
+            if (i == 0 && !have0) {
+                k_copy_rows(c.T, ra, rr, c.stream);
+            } else {
+                c.count(OC_ADD, acc.level, acc.m);
+                k_add(c.T, ra, ra, rr, c.stream);
+            }
         }
         ct_free(c, rot);
     }

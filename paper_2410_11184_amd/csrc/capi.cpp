@@ -1036,6 +1036,19 @@ hs_status hs_tune_load(const char* path, int* entries) {
     });
 }
 
+hs_status hs_op_counts(hs_ctx* ctx, double* out, size_t n, int clear) {
+    return guard([&] {
+        NEED(ctx);
+        hs::Context& c = *ctx->c;
+        const size_t total = (size_t)hs::OC_COUNT * hs::kMaxRows;
+        if (out)
+            for (size_t i = 0; i < std::min(n, total); i++) out[i] = c.opc[i / hs::kMaxRows][i % hs::kMaxRows];
+        if (clear)
+            for (int k = 0; k < hs::OC_COUNT; k++)
+                for (int l = 0; l < hs::kMaxRows; l++) c.opc[k][l] = 0;
+    });
+}
+
 hs_status hs_softmax_stats(hs_ctx* ctx, double* out, size_t n) {
     return guard([&] {
         NEED(ctx);

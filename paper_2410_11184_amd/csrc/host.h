@@ -123,6 +123,12 @@ struct ConvDev {
 
 struct Context;
 
+// Homomorphic operations counted per level (ciphertext equivalents: one
+// degree-1 ciphertext = 1), for cost models of other implementations of the
+// same schedule: key switches, tensor products (squares included), rescales,
+// plaintext or constant products, additions.
+enum OpKind { OC_KS = 0, OC_TENSOR, OC_RESCALE, OC_PTMUL, OC_ADD, OC_COUNT };
+
 // Owned ciphertext handle (frees its buffer through the context's pool).
 struct CtHandle {
     Context* ctx = nullptr;
@@ -175,6 +181,10 @@ struct Context {
     static constexpr size_t kMaskCacheBytes = (size_t)8 << 30;
     std::vector<void*> owned;                       // device tables
     std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
+    double opc[OC_COUNT][kMaxRows] = {};            // operation counts by level
+    void count(int kind, int level, double n) {
+        if (level >= 0 && level < kMaxRows) opc[kind][level] += n;
+    }
 
     Context(const Params& p, int device, void* stream);
     ~Context();

@@ -36,6 +36,7 @@ void op_add_inplace(Context& c, Ct& a, const Ct& b) {
     HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "add: batch sizes differ");
     HS_REQUIRE(b.ncomp <= a.ncomp, E_ARG, "add: component count");
     check_scales(a.scale, b.scale, "add");
+    c.count(OC_ADD, a.level, a.m * b.ncomp / 2.0);
     for (int k = 0; k < b.ncomp; k++) {
         Rows o = c.comp_rows(a, k);
         k_add(c.T, o, o, comp_rows_bcast(c, b, k, a.m), c.stream);
@@ -47,6 +48,7 @@ void op_sub_inplace(Context& c, Ct& a, const Ct& b) {
     HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "sub: batch sizes differ");
     HS_REQUIRE(b.ncomp <= a.ncomp, E_ARG, "sub: component count");
     check_scales(a.scale, b.scale, "sub");
+    c.count(OC_ADD, a.level, a.m * b.ncomp / 2.0);
     for (int k = 0; k < b.ncomp; k++) {
         Rows o = c.comp_rows(a, k);
         k_sub(c.T, o, o, comp_rows_bcast(c, b, k, a.m), c.stream);
@@ -71,6 +73,7 @@ void op_neg_inplace(Context& c, Ct& a) {
 }
 
 void op_mul_residues_inplace(Context& c, Ct& a, const std::vector<u64>& res) {
+    c.count(OC_PTMUL, a.level, a.m * a.ncomp / 2.0);
     RowConsts rc = c.shoup_consts(std::vector<u64>(res.begin(), res.begin() + a.level + 1), 0);
     Rows r = c.ct_rows(a);
     k_mul_row_const(c.T, r, r, rc, c.stream);
@@ -132,6 +135,7 @@ static double rescale_into(Context& c, const Ct& a, u64* out) {
     Rows r_last{last, np_, 1, N, 1, l, c.nq};
     k_ntt_from(c.T, r_last, in_last, true, c.stream);
     Rows r_lift{lifted, np_, l, (size_t)l * N, l, 0, c.nq};
+    c.count(OC_RESCALE, l, np_ / 2.0);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = invmod_h(c.primes[l] % c.primes[i], c.primes[i]);
     // out = (a - NTT(lifted)) q_l^-1, fused into the transform's last pass
@@ -171,6 +175,7 @@ Ct op_mul_const(Context& c, const Ct& a, double v, double target_scale) {
 }
 
 Ct op_mul_plain(Context& c, const Ct& a, const u64* pt, double pt_scale, bool rescale) {
+    c.count(OC_PTMUL, a.level, a.m * a.ncomp / 2.0);
     Ct o = ct_alloc(c, a.m, a.ncomp, a.level);
     Rows rp{const_cast<u64*>(pt), a.m * a.ncomp, a.level + 1, 0, a.level + 1, 0, c.nq};
     k_mul(c.T, c.ct_rows(o), c.ct_rows(a), rp, c.stream);
@@ -185,6 +190,7 @@ Ct op_tensor(Context& c, const Ct& a, const Ct& b) {
     HS_REQUIRE(a.ncomp == 2 && b.ncomp == 2, E_ARG, "tensor: degree-1 inputs expected");
     HS_REQUIRE(a.level == b.level, E_LEVEL, "tensor: levels differ");
     HS_REQUIRE(b.m == a.m || b.m == 1, E_ARG, "tensor: batch sizes differ");
+    c.count(OC_TENSOR, a.level, a.m);
     Ct d = ct_alloc(c, a.m, 3, a.level);
     d.scale = a.scale * b.scale;
     const size_t cw = a.comp_words(c.N);
@@ -197,6 +203,8 @@ Ct op_tensor(Context& c, const Ct& a, const Ct& b) {
 
 Ct op_square_sum(Context& c, const Ct& a) {
     HS_REQUIRE(a.ncomp == 2, E_ARG, "square_sum: degree-1 inputs expected");
+    c.count(OC_TENSOR, a.level, a.m);
+    c.count(OC_ADD, a.level, 1.5 * (a.m - 1));
     Ct d = ct_alloc(c, 1, 3, a.level);
     d.scale = a.scale * a.scale;
     Rows ra{a.d, a.m, a.level + 1, a.ct_words(c.N), a.level + 1, 0, c.nq};
@@ -210,6 +218,8 @@ Ct op_square_sum_jobs(Context& c, const Ct& a, int jobs) {
     HS_REQUIRE(a.ncomp == 2, E_ARG, "square_sum: degree-1 inputs expected");
     HS_REQUIRE(jobs >= 1 && a.m % jobs == 0, E_ARG, "square_sum: batch not divisible into jobs");
     const int m = a.m / jobs;
+    c.count(OC_TENSOR, a.level, a.m);
+    c.count(OC_ADD, a.level, 1.5 * (a.m - jobs));
     Ct d = ct_alloc(c, jobs, 3, a.level);
     d.scale = a.scale * a.scale;
     for (int j = 0; j < jobs; j++) {
@@ -272,6 +282,7 @@ static void ks_finish(Context& c, const u64* ext, int m, int level, const KeyLis
     const int E = nql + c.np;
     const int beta = (nql + c.prm.digit - 1) / c.prm.digit;
     const size_t N = c.N;
+    c.count(OC_KS, l, m);
     // inner product with the key: acc [m][2][E][N]
     u64* acc = c.alloc_words((size_t)m * 2 * E * N);
     HS_REQUIRE(keys.n * keys.per == m, E_ARG, "key switch: key list does not cover the batch");
@@ -552,6 +563,7 @@ Ct op_mul_monomial(Context& c, const Ct& a, int k) {
     } else {
         mono = it->second;
     }
+    c.count(OC_PTMUL, a.level, a.m * a.ncomp / 2.0);
     Ct o = ct_alloc(c, a.m, a.ncomp, a.level);
     o.scale = a.scale;
     Rows rp{mono, a.m * a.ncomp, a.level + 1, 0, a.level + 1, 0, c.nq};

@@ -125,6 +125,7 @@ struct Evaluator {
         u64* pt = mask_pt(value * a.scale, a.level, &owned);
         Rows r0 = c.comp_rows(a, 0);
         Rows rp{pt, a.m, a.level + 1, 0, a.level + 1, 0, c.nq};
+        c.count(OC_ADD, a.level, a.m / 2.0);
         k_add(c.T, r0, r0, rp, c.stream);
         if (owned) c.free_words(pt);
     }
@@ -243,6 +244,8 @@ struct Evaluator {
             if (terms[part].empty()) continue;
             Ct s = ct_alloc(c, m, 2, lv + 1);
             s.scale = S * ql;
+            c.count(OC_PTMUL, lv + 1, (double)m * terms[part].size());
+            c.count(OC_ADD, lv + 1, (double)m * (terms[part].size() - 1));
             k_leaf_mac(c.T, s.d, 2 * m, lv + 2, terms[part].data(), (int)terms[part].size(), c.stream);
             if (part == 1) {
                 Ct t = op_mul_monomial(c, s, c.N / 2);

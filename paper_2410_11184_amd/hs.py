@@ -131,6 +131,7 @@ def lib():
         "hs_softmax_jobs": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_uint32,
                             ctypes.c_double, ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_stats": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+        "hs_op_counts": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, S],
         "hs_softmax_plan_create": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.c_size_t, ctypes.c_uint32,
                                    ctypes.c_double, ctypes.POINTER(hs_softmax_opts), ctypes.POINTER(_vp)],
         "hs_softmax_plan_run": [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp)],
@@ -510,6 +511,15 @@ class Context:
         h = _vp()
         _check(lib().hs_softmax_plan_create(self.h, arr, m, jobs, n, M, ctypes.byref(o), ctypes.byref(h)))
         return SoftmaxPlan(self, h, m)
+
+    OP_KINDS = ("keyswitch", "tensor", "rescale", "ptmul", "add")
+
+    def op_counts(self, clear=True):
+        """hs_op_counts: {kind: {level: ciphertext equivalents}} since the last
+        clear (eager launches only)."""
+        buf = (ctypes.c_double * (5 * 64))()
+        _check(lib().hs_op_counts(self.h, buf, 5 * 64, 1 if clear else 0))
+        return {k: {l: buf[i * 64 + l] for l in range(64) if buf[i * 64 + l]} for i, k in enumerate(self.OP_KINDS)}
 
     def softmax_stats(self):
         buf = (ctypes.c_double * 4)()
