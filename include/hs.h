@@ -93,9 +93,28 @@ const char* hs_version(void);
 /* Message of the last failure on this thread (static thread-local storage). */
 const char* hs_last_error(void);
 
+/* Device memory callbacks of a context.  alloc returns `bytes` of device
+ * memory on the context's device usable in stream order on `hip_stream` (the
+ * context's stream), or NULL when none is available (the call that needed it
+ * then fails with HS_E_OOM); free returns a block with the size it was
+ * allocated with.  The Python binding passes torch's caching allocator. */
+typedef void* (*hs_alloc_fn)(size_t bytes, void* hip_stream, void* user);
+typedef void (*hs_free_fn)(void* ptr, size_t bytes, void* user);
+
 /* Create a context on HIP device `device`, issuing all work on `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  Builds the NTT tables,
- * base-conversion constants and encoding twiddles. */
+ * base-conversion constants and encoding twiddles.  Every device allocation
+ * of the context (tables, keys, ciphertexts, the arena's chunks, the arenas
+ * of its captured schedules) goes through alloc_fn / free_fn with `user`
+ * (both or neither: HS_E_ARG); without them, hipMalloc / hipFree.  The
+ * callbacks must stay valid until hs_ctx_destroy, which returns every block
+ * (after waiting for the stream), as does a failed creation.  Not from the
+ * callbacks: the autotuner's timing buffers (process-wide) and the fixed
+ * scratch of hs_mult_relin_noalloc.  HS_E_OOM when a callback returns NULL
+ * during creation. */
+hs_status hs_ctx_create_ex(const hs_params* p, int device, void* hip_stream, hs_alloc_fn alloc_fn,
+                           hs_free_fn free_fn, void* user, hs_ctx** out);
+/* hs_ctx_create_ex without callbacks (hipMalloc / hipFree). */
 hs_status hs_ctx_create(const hs_params* p, int device, void* hip_stream, hs_ctx** out);
 void hs_ctx_destroy(hs_ctx* ctx);
 hs_status hs_ctx_get_info(const hs_ctx* ctx, hs_ctx_info* info);
@@ -249,9 +268,19 @@ typedef struct hs_softmax_opts {
                           /* table: 6, 5, 7); n <= 1024: 6, 6, 8; larger:     */
                           /* 7, 7, 8                                          */
     double alpha;         /* reserved (0)                                     */
-    int plain_per_ct;     /* reserved (0)                                     */
+    int power;            /* t of the normalize-and-t-th-power variant (the   */
+                          /* appendix on other normalisations: lambda =      */
+                          /* (sum y^t)^(-1/t), y <- (lambda y)^t, exp of     */
+                          /* x / t^k with M / t^k ~ ln n); 0 or 2 = squares; */
+                          /* 3 or 4 with variant 0 only (HS_E_PARAM else)    */
     int debug_stop;       /* tests: >= 0 returns y after that iteration
                              (0 = after the exponential); -1 = off          */
+    int newton_steps;     /* > 0: each inverse root by that many Newton steps */
+                          /* (Appendix A, inverse square roots) from the      */
+                          /* normalisation polynomial as first guess; 0 off   */
+    int mask_mode;        /* 0: mask = indicator of slots [0, L); 1: the      */
+                          /* averaging mask (m / n on every slot, no          */
+                          /* plaintext; bootstraps of the factors unmasked)   */
 } hs_softmax_opts;
 
 /* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n
@@ -259,9 +288,13 @@ typedef struct hs_softmax_opts {
  * the same level and scale, inputs in [-M, 0] (the paper's assumption of
  * Section 3.1; values outside give unspecified results).  For the first step
  * to cost no level, encrypt the inputs at scale 2^(log_scale + 1) / M.
- * Writes m new handles to out[0..m).  Needs n a power of two, m | n,
- * n <= N/2 (HS_E_PARAM / HS_E_ARG otherwise), enough levels or bootstrapping
- * parameters (HS_E_LEVEL).  Rotation keys for strides +-L 2^t are generated
+ * Writes m new handles to out[0..m).  A dimension n that is not a power of
+ * two is packed (hs_pack_softmax) as the next power of two n2, and the
+ * exponentials of the extra coordinates are removed by one plaintext mask
+ * product (one level) before the first normalisation, so every sum runs over
+ * the n real coordinates (the rounded-up log n of the auxiliary thread's
+ * rotation count).  Needs m | n2, n2 <= N/2 (HS_E_ARG otherwise), enough
+ * levels or bootstrapping parameters (HS_E_LEVEL).  Rotation keys for strides +-L 2^t are generated
  * on first use. */
 hs_status hs_softmax(hs_ctx* ctx, hs_ct* const* in, size_t m, uint32_t n, double M, const hs_softmax_opts* opts,
                      hs_ct** out);
@@ -334,13 +367,15 @@ hs_status hs_tune_report(char* buf, size_t cap, size_t* used);
 hs_status hs_tune_save(const char* path);
 hs_status hs_tune_load(const char* path, int* entries);
 
-/* Packing of Section 4 (host only).  logits: [L][n] row-major, L n =
- * m (N/2); out: [m][slots] with ciphertext j holding coordinate
- * j (n/m) + c of Softmax l in slot c L + l.  Checks every logit is in
+/* Packing of Section 4 (host only).  logits: [L][n] row-major, L n2 =
+ * m (N/2) with n2 the power of two at or above n; out: [m][slots] with
+ * ciphertext j holding coordinate j (n2/m) + c of Softmax l in slot c L + l
+ * (coordinates n..n2-1, if any, set to -M).  Checks every logit is in
  * [-M, 0] (HS_E_RANGE otherwise). */
 hs_status hs_pack_softmax(const double* logits, size_t L, uint32_t n, size_t slots, double M, double* out,
                           size_t* m_out);
-/* Inverse of hs_pack_softmax: slots [m][slots] -> out [L][n]. */
+/* Inverse of hs_pack_softmax: slots [m][slots] -> out [L][n] (padding
+ * coordinates dropped). */
 hs_status hs_unpack_softmax(const double* slots_in, size_t m, uint32_t n, size_t slots, double* out);
 
 /* Bootstrapping: refresh a ciphertext (any level) to the top user level

@@ -52,11 +52,14 @@ extern "C" {
 const char* hs_version(void) { return "hs 0.1 (gfx950)"; }
 const char* hs_last_error(void) { return g_err.c_str(); }
 
-hs_status hs_ctx_create(const hs_params* p, int device, void* stream, hs_ctx** out) {
+hs_status hs_ctx_create_ex(const hs_params* p, int device, void* stream, hs_alloc_fn alloc_fn, hs_free_fn free_fn,
+                            void* user, hs_ctx** out) {
     if (out) *out = nullptr;
     return guard([&] {
         NEED(p);
         NEED(out);
+        HS_REQUIRE((alloc_fn == nullptr) == (free_fn == nullptr), hs::E_ARG,
+                   "give both allocator callbacks or neither");
         NEED(p->q_bits);
         NEED(p->p_bits);
         hs::Params q;
@@ -79,15 +82,23 @@ hs_status hs_ctx_create(const hs_params* p, int device, void* stream, hs_ctx** o
             const int nb = q.boot.cts_levels + q.boot.evalmod_levels + q.boot.stc_levels;
             HS_REQUIRE(q.user_top == p->n_q - 1 - nb, hs::E_PARAM, "user_top inconsistent with bootstrapping levels");
         }
+        hs::DevAllocator da;
+        da.alloc_fn = alloc_fn;
+        da.free_fn = free_fn;
+        da.user = user;
         hs_ctx* h = new hs_ctx;
         try {
-            h->c = new hs::Context(q, device, stream);
+            h->c = new hs::Context(q, device, stream, &da);
         } catch (...) {
             delete h;
             throw;
         }
         *out = h;
     });
+}
+
+hs_status hs_ctx_create(const hs_params* p, int device, void* stream, hs_ctx** out) {
+    return hs_ctx_create_ex(p, device, stream, nullptr, nullptr, nullptr, out);
 }
 
 void hs_ctx_destroy(hs_ctx* ctx) {
@@ -762,6 +773,9 @@ static hs::SoftmaxOpts softmax_opts(const hs_softmax_opts* opts) {
         if (opts->inv_degree_mid > 0) o.inv_degree_mid = opts->inv_degree_mid;
         if (opts->inv_degree_last > 0) o.inv_degree_last = opts->inv_degree_last;
         o.debug_stop = opts->debug_stop;
+        if (opts->power > 0) o.power = opts->power;
+        o.newton_steps = opts->newton_steps;
+        o.mask_mode = opts->mask_mode;
     }
     return o;
 }
@@ -881,6 +895,7 @@ hs_status hs_softmax_plan_create(hs_ctx* ctx, hs_ct* const* in, size_t m, size_t
         const hs::SoftmaxOpts o = softmax_opts(opts);
         std::unique_ptr<hs_softmax_plan> P(new hs_softmax_plan);
         P->ctx = ctx;
+        P->pool.set_source(&ctx->c->da);   // the plan's arena draws on the context's allocator
         HS_REQUIRE(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) == hipSuccess, hs::E_DEVICE,
                    "hipStreamCreate failed");
         c.sync();                                   // inputs were produced on the context's stream
@@ -1062,18 +1077,24 @@ hs_status hs_pack_softmax(const double* logits, size_t L, uint32_t n, size_t slo
     return guard([&] {
         NEED(logits);
         NEED(m_out);
-        HS_REQUIRE(n >= 1 && (n & (n - 1)) == 0 && n <= slots, hs::E_PARAM, "n must be a power of two <= slots");
-        HS_REQUIRE((L * n) % slots == 0 && L * n >= slots, hs::E_ARG, "L n must be a multiple of the slot count");
-        const size_t m = L * n / slots;
-        HS_REQUIRE(n % m == 0, hs::E_ARG, "m must divide n");
+        size_t np2 = 1;
+        while (np2 < n) np2 <<= 1;
+        HS_REQUIRE(n >= 1 && np2 <= slots, hs::E_PARAM, "n must be <= slots");
+        HS_REQUIRE((L * np2) % slots == 0 && L * np2 >= slots, hs::E_ARG,
+                   "L times the padded dimension must be a multiple of the slot count");
+        const size_t m = L * np2 / slots;
+        HS_REQUIRE(np2 % m == 0, hs::E_ARG, "m must divide the padded dimension");
         *m_out = m;
         for (size_t i = 0; i < L * n; i++)
             HS_REQUIRE(logits[i] >= -M && logits[i] <= 0.0, hs::E_RANGE, "logit outside [-M, 0]");
         if (!out) return;
-        const size_t per = n / m;
+        const size_t per = np2 / m;
         for (size_t j = 0; j < m; j++)
             for (size_t c = 0; c < per; c++)
-                for (size_t l = 0; l < L; l++) out[j * slots + c * L + l] = logits[l * n + j * per + c];
+                for (size_t l = 0; l < L; l++) {
+                    const size_t coord = j * per + c;
+                    out[j * slots + c * L + l] = coord < n ? logits[l * n + coord] : -M;
+                }
     });
 }
 
@@ -1081,11 +1102,16 @@ hs_status hs_unpack_softmax(const double* slots_in, size_t m, uint32_t n, size_t
     return guard([&] {
         NEED(slots_in);
         NEED(out);
-        HS_REQUIRE(m >= 1 && n % m == 0 && (m * slots) % n == 0, hs::E_ARG, "bad shape");
-        const size_t L = m * slots / n, per = n / m;
+        size_t np2 = 1;
+        while (np2 < n) np2 <<= 1;
+        HS_REQUIRE(m >= 1 && n >= 1 && np2 % m == 0 && (m * slots) % np2 == 0, hs::E_ARG, "bad shape");
+        const size_t L = m * slots / np2, per = np2 / m;
         for (size_t j = 0; j < m; j++)
-            for (size_t c = 0; c < per; c++)
-                for (size_t l = 0; l < L; l++) out[l * n + j * per + c] = slots_in[j * slots + c * L + l];
+            for (size_t c = 0; c < per; c++) {
+                const size_t coord = j * per + c;
+                if (coord >= n) continue;
+                for (size_t l = 0; l < L; l++) out[l * n + coord] = slots_in[j * slots + c * L + l];
+            }
     });
 }
 

@@ -127,6 +127,37 @@ static u64 brv(u64 x, int bits) {
 // ----------------------------------------------------------------- pool
 static constexpr size_t kChunk = (size_t)8 << 30;
 
+void* DevAllocator::get(size_t bytes) const {
+    if (alloc_fn) return alloc_fn(bytes, stream, user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void DevAllocator::put(void* p, size_t bytes) const {
+    if (!p) return;
+    if (free_fn) free_fn(p, bytes, user);
+    else (void)hipFree(p);
+}
+
+void* Pool::get_chunk(size_t bytes) {
+    if (src_) return src_->get(bytes);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void Pool::put_chunk(void* p, size_t bytes) {
+    if (src_) src_->put(p, bytes);
+    else (void)hipFree(p);
+}
+
 void Pool::add_free(int c, size_t off, size_t size) {
     chunks_[c].free_[off] = size;
     by_size_.emplace(size, std::make_pair(c, off));
@@ -149,19 +180,16 @@ void* Pool::alloc(size_t bytes) {
     if (it == by_size_.end()) {
         // new chunk: 8 GiB, or the request rounded up to 1 GiB
         size_t want = std::max(kChunk, (bytes + ((size_t)1 << 30) - 1) & ~(((size_t)1 << 30) - 1));
-        void* p = nullptr;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
+        void* p = get_chunk(want);
+        if (!p) {
             trim(want);
-            e = hipMalloc(&p, want);
+            p = get_chunk(want);
         }
-        if (e != hipSuccess && want > bytes) {
-            (void)hipGetLastError();
+        if (!p && want > bytes) {
             want = bytes;   // as much as the request alone
-            e = hipMalloc(&p, want);
+            p = get_chunk(want);
         }
-        if (e != hipSuccess) throw Error(E_OOM, "device allocation failed");
+        if (!p) throw Error(E_OOM, "device allocation failed");
         if (std::getenv("HS_TRACE"))
             std::fprintf(stderr, "[hs] pool: new chunk of %.2f GB (%.2f GB reserved, %.2f GB in use)\n", want / 1e9,
                          (reserved_ + want) / 1e9, in_use_ / 1e9);
@@ -234,7 +262,7 @@ size_t Pool::trim(size_t bytes) {
         auto f = ch.free_.find(0);
         if (f == ch.free_.end() || f->second != ch.size) continue;
         remove_free(c, 0, ch.size);
-        hipFree(ch.base);
+        put_chunk(ch.base, ch.size);
         released += ch.size;
         reserved_ -= ch.size;
         ch.base = nullptr;
@@ -246,7 +274,7 @@ size_t Pool::trim(size_t bytes) {
 void Pool::release_all() {
     if (!fixed_)
         for (auto& ch : chunks_)
-            if (ch.base) hipFree(ch.base);
+            if (ch.base) put_chunk(ch.base, ch.size);
     chunks_.clear();
     by_size_.clear();
     live_.clear();
@@ -280,17 +308,23 @@ void* Context::persistent_alloc(size_t bytes, const char* what) {
 }
 
 void* Context::raw_alloc(size_t bytes, const char* what) {
-    void* p = nullptr;
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
+    void* p = da.get(bytes);
+    if (!p) {
         // the pool's cached blocks may hold the memory
-        (void)hipGetLastError();
         pool.trim(bytes);
-        e = hipMalloc(&p, bytes);
+        p = da.get(bytes);
     }
-    if (e != hipSuccess) throw Error(E_OOM, std::string("device allocation failed: ") + what);
+    if (!p) throw Error(E_OOM, std::string("device allocation failed: ") + what);
+    raw_sizes[p] = bytes;
     return p;
+}
+
+void Context::raw_free(void* p) {
+    auto it = raw_sizes.find(p);
+    if (it == raw_sizes.end()) return;
+    da.put(p, it->second);
+    raw_sizes.erase(it);
 }
 
 void* Context::dev_table(const void* host, size_t bytes) {
@@ -311,7 +345,22 @@ RowConsts Context::shoup_consts(const std::vector<u64>& vals, int q_off, bool p_
     return rc;
 }
 
-Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
+Context::Context(const Params& p, int dev, void* st, const DevAllocator* alloc) : prm(p), device(dev) {
+    if (alloc) da = *alloc;
+    da.stream = st;
+    pool.set_source(&da);
+    try {
+        init();
+    } catch (...) {
+        release();   // a failed construction returns what it took
+        throw;
+    }
+}
+
+void Context::init() {
+    const Params& p = prm;
+    const int dev = device;
+    void* st = da.stream;
     HS_REQUIRE(p.logN >= 3 && p.logN <= 17, E_PARAM, "logN out of range");
     HS_REQUIRE(!p.q_bits.empty() && !p.p_bits.empty(), E_PARAM, "need Q and P primes");
     HS_REQUIRE((int)(p.q_bits.size() + p.p_bits.size()) <= kMaxRows, E_PARAM, "too many primes");
@@ -467,19 +516,34 @@ Context::Context(const Params& p, int dev, void* st) : prm(p), device(dev) {
     }
 }
 
-Context::~Context() {
+Context::~Context() { release(); }
+
+void Context::release() {
+    // pending work may still read the blocks
+    if (stream || T.prof) (void)hipStreamSynchronize((hipStream_t)stream);
     boot_release(this);
     prof_destroy(T.prof);
+    T.prof = nullptr;
     for (auto& kv : keys) pool.free(kv.second);
+    keys.clear();
     if (s_ntt) pool.free(s_ntt);
     if (pk) pool.free(pk);
+    s_ntt = pk = nullptr;
     pool.release_all();
-    for (void* p : owned) hipFree(p);
-    for (auto& kv : perms) hipFree(kv.second);
+    for (void* p : owned) raw_free(p);
+    owned.clear();
+    for (auto& kv : perms) raw_free(kv.second);
+    perms.clear();
     for (auto& kv : modup)
-        for (void* p : kv.second.bufs) hipFree(p);
+        for (void* p : kv.second.bufs) raw_free(p);
+    modup.clear();
     for (auto& kv : moddown)
-        for (void* p : kv.second.bufs) hipFree(p);
+        for (void* p : kv.second.bufs) raw_free(p);
+    moddown.clear();
+    mask_pts.clear();
+    monomials.clear();
+    for (auto& kv : raw_sizes) da.put(kv.first, kv.second);   // anything else raw_alloc gave out
+    raw_sizes.clear();
 }
 
 CtHandle::~CtHandle() {

@@ -64,6 +64,19 @@ struct Params {
 };
 
 // --------------------------------------------------------------- memory
+// Where a context's device memory comes from: the caller's callbacks (the
+// C ABI's hs_ctx_create_ex; the Python binding passes torch's caching
+// allocator) or, without them, hipMalloc / hipFree.  get returns null when
+// the memory is not available.
+struct DevAllocator {
+    void* (*alloc_fn)(size_t bytes, void* stream, void* user) = nullptr;
+    void (*free_fn)(void* p, size_t bytes, void* user) = nullptr;
+    void* user = nullptr;
+    void* stream = nullptr;
+    void* get(size_t bytes) const;
+    void put(void* p, size_t bytes) const;
+};
+
 // Device memory arena: chunks obtained from hipMalloc (8 GiB, or the request
 // rounded to 1 GiB when larger) and sub-allocated best-fit in 256-byte units,
 // with neighbouring free blocks coalesced.  Chunks are kept until the context
@@ -79,6 +92,8 @@ public:
     // a fixed region instead of hipMalloc chunks: the pool never grows (an
     // allocation that does not fit raises E_OOM) and never frees it
     void adopt(void* base, size_t bytes);
+    // chunks come from (and go back to) this source instead of hipMalloc
+    void set_source(const DevAllocator* d) { src_ = d; }
     bool owns(const void* p) const { return live_.count(const_cast<void*>(p)) != 0; }
     size_t bytes_in_use() const { return in_use_; }
     size_t bytes_reserved() const { return reserved_; }
@@ -95,6 +110,9 @@ private:
     std::map<void*, std::pair<int, size_t>> live_;            // pointer -> (chunk, size)
     size_t in_use_ = 0, reserved_ = 0;
     bool fixed_ = false;
+    const DevAllocator* src_ = nullptr;
+    void* get_chunk(size_t bytes);
+    void put_chunk(void* p, size_t bytes);
     void add_free(int c, size_t off, size_t size);
     void remove_free(int c, size_t off, size_t size);
 };
@@ -147,6 +165,7 @@ struct Context {
     DevTables T{};
     void* stream = nullptr;
     int device = 0;
+    DevAllocator da;             // source of every device allocation of the context
     Pool pool;
     // arena that alloc_words draws from: `pool`, or a captured Softmax
     // schedule's own arena while it is being recorded
@@ -180,14 +199,17 @@ struct Context {
     size_t mask_pts_bytes = 0;
     static constexpr size_t kMaskCacheBytes = (size_t)8 << 30;
     std::vector<void*> owned;                       // device tables
+    std::map<void*, size_t> raw_sizes;              // raw_alloc'd blocks and their sizes
     std::vector<double> tw_cos, tw_sin;             // encoding twiddles, [2N]
     double opc[OC_COUNT][kMaxRows] = {};            // operation counts by level
     void count(int kind, int level, double n) {
         if (level >= 0 && level < kMaxRows) opc[kind][level] += n;
     }
 
-    Context(const Params& p, int device, void* stream);
+    Context(const Params& p, int device, void* stream, const DevAllocator* alloc = nullptr);
     ~Context();
+    void release();   // returns every device block (destructor; failed construction)
+    void init();      // the constructor's work
 
     // helpers
     u64 q(int i) const { return primes[i]; }
@@ -216,7 +238,8 @@ struct Context {
     void download(void* dst, const void* src, size_t bytes);
     void* dev_table(const void* host, size_t bytes);   // permanent device copy
     void* persistent_alloc(size_t bytes, const char* what);  // device memory owned until the context ends
-    void* raw_alloc(size_t bytes, const char* what);          // hipMalloc, trimming the pool's cache if needed
+    void* raw_alloc(size_t bytes, const char* what);          // from da, trimming the pool's cache if needed
+    void raw_free(void* p);
 
     const ConvDev& modup_tables(int level, int j);
     const ConvDev& moddown_tables(int level);

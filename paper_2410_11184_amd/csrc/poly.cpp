@@ -68,6 +68,26 @@ static int ceil_log2(int x) {
 int cheb_depth(int degree) { return ceil_log2(degree + 1) + 1; }
 
 // ---------------------------------------------------------------- evaluator
+u64* mask_plaintext(Context& c, const double* mask, int lv, double scale, bool* owned) {
+    const auto key = std::make_tuple(mask, lv, scale);
+    auto it = c.mask_pts.find(key);
+    *owned = false;
+    if (it != c.mask_pts.end()) return it->second;
+    const size_t bytes = sizeof(u64) * (size_t)(lv + 1) * c.N;
+    const bool keep = c.mask_pts_bytes + bytes <= Context::kMaskCacheBytes;
+    u64* pt = keep ? (u64*)c.persistent_alloc(bytes, "mask plaintext") : c.alloc_words((size_t)(lv + 1) * c.N);
+    Rows r = c.rows(pt, 1, lv + 1, (size_t)(lv + 1) * c.N);
+    k_encode_real(c.T, r, mask, 0, scale, c.stream);
+    k_ntt(c.T, r, false, c.stream);
+    if (keep) {
+        c.mask_pts[key] = pt;
+        c.mask_pts_bytes += bytes;
+    } else {
+        *owned = true;
+    }
+    return pt;
+}
+
 namespace {
 
 using cplx = std::complex<double>;
@@ -88,28 +108,7 @@ struct Evaluator {
     // whole polynomial by the mask since mask^2 = mask.
     const double* mask = nullptr;
 
-    // NTT-domain rows 0..lv of rint(scale * mask): from the context's cache
-    // (built on first use, kept; *owned = false), else in a pool buffer the
-    // caller frees (*owned = true)
-    u64* mask_pt(double scale, int lv, bool* owned) {
-        const auto key = std::make_tuple(mask, lv, scale);
-        auto it = c.mask_pts.find(key);
-        *owned = false;
-        if (it != c.mask_pts.end()) return it->second;
-        const size_t bytes = sizeof(u64) * (size_t)(lv + 1) * c.N;
-        const bool keep = c.mask_pts_bytes + bytes <= Context::kMaskCacheBytes;
-        u64* pt = keep ? (u64*)c.persistent_alloc(bytes, "mask plaintext") : c.alloc_words((size_t)(lv + 1) * c.N);
-        Rows r = c.rows(pt, 1, lv + 1, (size_t)(lv + 1) * c.N);
-        k_encode_real(c.T, r, mask, 0, scale, c.stream);
-        k_ntt(c.T, r, false, c.stream);
-        if (keep) {
-            c.mask_pts[key] = pt;
-            c.mask_pts_bytes += bytes;
-        } else {
-            *owned = true;
-        }
-        return pt;
-    }
+    u64* mask_pt(double scale, int lv, bool* owned) { return mask_plaintext(c, mask, lv, scale, owned); }
 
     // a (level lv) * (value * mask) with the product at scale a.scale * pscale
     Ct mul_mask(const Ct& a, double value, double pscale) {

@@ -26,6 +26,11 @@ int cheb_depth(int degree);   // levels used by eval_cheb (plus 1 if the affine 
 // laid out as encode_to lays out w), the result is p(x) * mask at no extra
 // level: every leaf constant becomes a masked plaintext.
 Ct eval_cheb(Context& c, const Ct& x, const ChebPoly& p, double target_scale, const double* mask = nullptr);
+// NTT-domain rows 0..lv of rint(scale * w), w = `mask` (device coefficients of
+// a slot vector, laid out as encode_to lays them out): from the context's
+// cache (built on first use and kept, *owned = false), else in a pool buffer
+// the caller frees (*owned = true)
+u64* mask_plaintext(Context& c, const double* mask, int lv, double scale, bool* owned);
 // re(x) + i im(x) for two polynomials on [-1, 1], as one polynomial with
 // complex coefficients (the imaginary parts through a product by X^(N/2),
 // which multiplies every slot by i): half the products of evaluating both.

@@ -62,6 +62,43 @@ int theorem_k(int n, double M) {
     return std::max(1, (int)v);
 }
 
+// iterations of the t-th power variant: M / t^k ~ ln n (the appendix on other
+// normalisations); t = 2 is the Theorem's k
+static int power_k(int n, double M, int t) {
+    if (t == 2) return theorem_k(n, M);
+    const double v = std::ceil((std::log2(M) - std::log2(std::log((double)n))) / std::log2((double)t));
+    return std::max(1, (int)v);
+}
+
+// y^t for t in {2, 3, 4} (ceil(log2 t) levels)
+static Ct op_power(Context& c, const Ct& y, int t) {
+    Ct y2 = op_mult(c, y, y);
+    if (t == 2) return y2;
+    Ct o = op_mult(c, y2, t == 3 ? y : y2);
+    ct_free(c, y2);
+    return o;
+}
+
+// per job, the sum of its m ciphertexts (a.m = jobs m)
+static Ct op_sum_jobs(Context& c, const Ct& a, int jobs) {
+    const int m = a.m / jobs;
+    Ct o = ct_alloc(c, jobs, a.ncomp, a.level);
+    o.scale = a.scale;
+    const size_t w = a.ct_words(c.N);
+    const int rows = a.ncomp * (a.level + 1);
+    for (int j = 0; j < jobs; j++) {
+        Rows dst{o.d + (size_t)j * w, 1, rows, w, a.level + 1, 0, c.nq};
+        Rows first{a.d + (size_t)j * m * w, 1, rows, w, a.level + 1, 0, c.nq};
+        k_copy_rows(c.T, dst, first, c.stream);
+        for (int i = 1; i < m; i++) {
+            Rows src{a.d + (size_t)(j * m + i) * w, 1, rows, w, a.level + 1, 0, c.nq};
+            c.count(OC_ADD, a.level, a.ncomp / 2.0);
+            k_add(c.T, dst, dst, src, c.stream);
+        }
+    }
+    return o;
+}
+
 static int ilog2(int x) {
     int l = 0;
     while ((1 << l) < x) l++;
@@ -122,6 +159,36 @@ static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxS
     return b;
 }
 
+// Padded dimension (n below the power of two np2 it is packed in): y0 times
+// the 0/1 indicator of the real coordinates.  Ciphertext j of a job holds
+// coordinates j per .. (j + 1) per - 1 on slot blocks of L, so its indicator
+// keeps slots [0, R_j), R_j = (n - j per) L clamped to [0, N/2]: a plaintext
+// product at scale q_l and one rescale (scale unchanged).
+static Ct mask_padding(Context& c, const Ct& y0, int n, int per, int L, int m) {
+    const int N0 = c.N / 2;
+    const int lv = y0.level;
+    HS_REQUIRE(lv >= 1, E_LEVEL, "Softmax: no level for the padding mask");
+    const double ql = (double)c.primes[lv];
+    Ct o = ct_alloc(c, y0.m, 2, lv);
+    o.scale = y0.scale * ql;
+    const size_t cw = y0.ct_words(c.N), pw = y0.comp_words(c.N);
+    for (int g = 0; g < y0.m; g++) {
+        const long long R = std::min<long long>(std::max<long long>((long long)(n - (g % m) * per) * L, 0), N0);
+        bool owned;
+        u64* pt = mask_plaintext(c, mask_coeffs(c, (int)R), lv, ql, &owned);
+        Rows ra{y0.d + (size_t)g * cw, 2, lv + 1, pw, lv + 1, 0, c.nq};
+        Rows ro{o.d + (size_t)g * cw, 2, lv + 1, pw, lv + 1, 0, c.nq};
+        Rows rp{pt, 2, lv + 1, 0, lv + 1, 0, c.nq};
+        c.count(OC_PTMUL, lv, 1.0);
+        k_mul(c.T, ro, ra, rp, c.stream);
+        if (owned) c.free_words(pt);
+    }
+    Ct r = op_rescale(c, o);
+    ct_free(c, o);
+    r.scale = y0.scale;
+    return r;
+}
+
 // rotate-and-add with strides +L 2^t: slots [0, L) copied to all n/m blocks
 static void broadcast(Context& c, Ct& a, int L, int nrot) {
     for (int t = 0; t < nrot; t++) {
@@ -152,17 +219,26 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     HS_REQUIRE(jobs >= 1 && x.m % jobs == 0, E_ARG, "Softmax: batch not divisible into jobs");
     const int J = jobs;
     const int m = x.m / J;
-    HS_REQUIRE(n >= 2 && (n & (n - 1)) == 0, E_PARAM, "Softmax dimension must be a power of two >= 2");
-    HS_REQUIRE(n <= N0 && m >= 1 && n % m == 0, E_ARG, "need m | n <= N/2");
+    HS_REQUIRE(n >= 2, E_PARAM, "Softmax dimension must be >= 2");
+    // a dimension that is not a power of two is packed as the next power of
+    // two, its extra coordinates removed by a mask after the exponential
+    const int np2 = 1 << ilog2(n);
+    HS_REQUIRE(np2 <= N0 && m >= 1 && np2 % m == 0, E_ARG, "need m | n <= N/2 (n rounded up to a power of two)");
     HS_REQUIRE(M > 0, E_ARG, "range M must be positive");
     HS_REQUIRE(x.ncomp == 2, E_ARG, "degree-1 ciphertexts expected");
-    const int L = (int)((long long)m * N0 / n);
-    // Theorem "th:prec_softmax"'s k; from n = 4096 one more iteration, which
-    // narrows the first normalisation interval [e^(-2M/2^k), 1]
-    const int k = o.k > 0 ? o.k : theorem_k(n, M) + (n >= 4096 ? 1 : 0);
-    const int per = n / m;
-    const int nrot = ilog2(per);
     const bool smb = o.variant == 1;
+    // normalize-and-t-th-power (t = 2: normalize-and-square)
+    const int t = o.power > 0 ? o.power : 2;
+    HS_REQUIRE(t >= 2 && t <= 4, E_PARAM, "power must be 2, 3 or 4");
+    HS_REQUIRE(t == 2 || !smb, E_PARAM, "version B normalizes with squares (power 2)");
+    const int tl = t == 2 ? 1 : 2;          // levels of y^t
+    const int L = (int)((long long)m * N0 / np2);
+    // Theorem "th:prec_softmax"'s k (M / t^k ~ ln n for the t-th power
+    // variant); from n = 4096 one more iteration, which narrows the first
+    // normalisation interval [e^(-t M / t^k), 1]
+    const int k = o.k > 0 ? o.k : power_k(n, M, t) + (n >= 4096 ? 1 : 0);
+    const int per = np2 / m;
+    const int nrot = ilog2(per);
     const double Delta = std::ldexp(1.0, c.prm.log_scale);
     // rotation keys for the rotate-and-add loops (strides +-L 2^t)
     for (int t = 0; t < nrot; t++) {
@@ -179,14 +255,20 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     } else {
         v = op_mul_const(c, x, 2.0 / M, Delta);
     }
-    // y0 = exp(x / 2^k) / sqrt(n)  (the 1/sqrt(n) keeps sum y0^2 in [e^(-2M/2^k), 1])
-    const double isn = 1.0 / std::sqrt((double)n);
+    // y0 = exp(x / t^k) / n^(1/t)  (the prescale keeps sum y0^t in
+    // [e^(-t M / t^k), 1])
+    const double isn = t == 2 ? 1.0 / std::sqrt((double)n) : std::pow((double)n, -1.0 / t);
     const quad Mq = M;
     const int kk = k;
-    ChebPoly pexp = cheb_fit([&](quad t) { return expq(Mq * t / ldexpq(1, kk + 1)) * (quad)isn; }, -2.0, 0.0,
-                             o.exp_degree);
+    const quad tk2 = t == 2 ? ldexpq(1, kk + 1) : 2 * powq((quad)t, (quad)kk);
+    ChebPoly pexp = cheb_fit([&](quad u) { return expq(Mq * u / tk2) * (quad)isn; }, -2.0, 0.0, o.exp_degree);
     Ct y0 = eval_cheb(c, v, pexp, Delta);
     ct_free(c, v);
+    if (np2 != n) {
+        Ct ym = mask_padding(c, y0, n, per, L, m);
+        ct_free(c, y0);
+        y0 = ym;
+    }
     if (o.debug_stop == 0) return y0;
     const double* mask = mask_coeffs(c, L);
 
@@ -194,12 +276,13 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     Ct big;                     // Lambda (version B), on slots [0, L) only
     bool have_big = false;
     double ybound = isn * 1.05; // bound on |y^(j-1)| for its bootstrapping
-    double lo = std::exp(-2.0 * M / std::ldexp(1.0, k)) * 0.98, hi = 1.0;
+    double lo = (t == 2 ? std::exp(-2.0 * M / std::ldexp(1.0, k)) : std::exp(-t * M / std::pow((double)t, k))) * 0.98;
+    double hi = 1.0;
     for (int j = 1; j <= k; j++) {
         const bool last = j == k;
         const bool smb_step = smb && !last;
-        // exponent of the normalisation: 1/2 (SM, and the last step of B) or 2^-j
-        const double e = smb_step ? std::ldexp(1.0, -j) : 0.5;
+        // exponent of the normalisation: 1/t (SM, and the last step of B) or 2^-j
+        const double e = smb_step ? std::ldexp(1.0, -j) : (t == 2 ? 0.5 : 1.0 / t);
         int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
         if (deg <= 0) {
             // the paper's depths at n = 256 (6, 5, 7) for n <= 256 (its
@@ -219,21 +302,30 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         ChebPoly pinv = cheb_fit([&](quad s) { return powq(s, -(quad)ee); }, a, b, deg);
         const double delta = rel_error(pinv, lo, hi, e);
         const double lam_bound = max_abs(pinv, lo, hi) * 1.05;
-        // main thread must keep one level for the square feeding S
+        // main thread: this iteration's z = lambda y and z^t (1 + tl levels),
+        // then the levels of the next y^t feeding S
         if (!smb) {
             bool rep;
-            Ct y2 = ensure_level(c, y, last ? 2 : 3, ybound, st, rep, "y", j);
+            Ct y2 = ensure_level(c, y, last ? 1 + tl : 1 + 2 * tl, ybound, st, rep, "y", j);
             if (rep) {
                 ct_free(c, y);
                 y = y2;
             }
         }
-        // auxiliary thread, squaring: S = sum over the m ciphertexts of y^2 (one relinearisation)
-        Ct d = op_square_sum_jobs(c, y, J);
-        Ct r = op_relin(c, d);
-        ct_free(c, d);
-        Ct S = op_rescale(c, r);
-        ct_free(c, r);
+        // auxiliary thread, powering: S = sum over the m ciphertexts of y^t
+        // (squares: one relinearisation for the whole sum)
+        Ct S;
+        if (t == 2) {
+            Ct d = op_square_sum_jobs(c, y, J);
+            Ct r = op_relin(c, d);
+            ct_free(c, d);
+            S = op_rescale(c, r);
+            ct_free(c, r);
+        } else {
+            Ct yt = op_power(c, y, t);
+            S = op_sum_jobs(c, yt, J);
+            ct_free(c, yt);
+        }
         // auxiliary thread, summation: rotate-and-add with strides -L 2^t
         for (int t = 0; t < nrot; t++) {
             Ct rr = op_rotate(c, S, -(L << t));
@@ -253,12 +345,13 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         Ct lam = eval_cheb(c, S, pinv, Delta, mask);
         ct_free(c, S);
         if (!smb_step) {
-            // SM step (and the last step of version B): z = lambda y, y = z^2.
-            // y ends at min(y, lambda) - 2; bootstrap lambda (masked, before
-            // its broadcast) only when it is the ciphertext that leaves y
-            // short of the next iteration's need (3, or 2 before the last step).
-            const int need_next = (j + 1 == k) ? 2 : 3;
-            if (!last && can_bootstrap(c) && lam.level < y.level && lam.level - 2 < need_next) {
+            // SM step (and the last step of version B): z = lambda y, y = z^t.
+            // y ends at min(y, lambda) - 1 - tl; bootstrap lambda (masked,
+            // before its broadcast) only when it is the ciphertext that leaves
+            // y short of the next iteration's need (1 + 2 tl, or 1 + tl
+            // before the last step).
+            const int need_next = (j + 1 == k) ? 1 + tl : 1 + 2 * tl;
+            if (!last && can_bootstrap(c) && lam.level < y.level && lam.level - 1 - tl < need_next) {
                 bool rep;
                 Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep, "lambda", j, L);
                 if (rep) {
@@ -272,10 +365,17 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             Ct z = op_mult(c, y, lj);
             ct_free(c, lj);
             ct_free(c, y);
-            y = op_mult(c, z, z);
+            y = op_power(c, z, t);
             ct_free(c, z);
-            lo = std::pow(1.0 - delta, 4.0) / n * 0.98;
-            hi = std::pow(1.0 + delta, 4.0) * 1.0001;
+            // sum y^(j) in [(1 - delta)^t, (1 + delta)^t], so by the power-mean
+            // inequality sum (y^(j))^t in [(1 - delta)^(t^2) / n^(t-1), (1 + delta)^(t^2)]
+            if (t == 2) {
+                lo = std::pow(1.0 - delta, 4.0) / n * 0.98;
+                hi = std::pow(1.0 + delta, 4.0) * 1.0001;
+            } else {
+                lo = std::pow(1.0 - delta, (double)(t * t)) / std::pow((double)n, t - 1.0) * 0.98;
+                hi = std::pow(1.0 + delta, (double)(t * t)) * 1.0001;
+            }
             ybound = hi * 1.05;
         } else {
             // version B: Lambda = Lambda * lambda_j (both on slots [0, L));

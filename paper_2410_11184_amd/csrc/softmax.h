@@ -14,6 +14,9 @@ struct SoftmaxOpts {
     int inv_degree_mid = 0;
     int inv_degree_last = 0;
     int debug_stop = -1;      // >= 0: return y after that iteration (0 = after exp)
+    int power = 2;            // t of normalize-and-t-th-power (2, 3, 4; version B: 2)
+    int newton_steps = 0;     // > 0: inverse roots by that many Newton steps from the polynomial
+    int mask_mode = 0;        // 0: indicator of slots [0, L); 1: averaging (m / n on every slot)
 };
 
 struct SoftmaxStats {

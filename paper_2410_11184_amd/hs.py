@@ -52,7 +52,8 @@ class hs_softmax_opts(ctypes.Structure):
         ("variant", ctypes.c_int), ("k", ctypes.c_int), ("exp_degree", ctypes.c_int),
         ("inv_degree_first", ctypes.c_int), ("inv_degree_mid", ctypes.c_int),
         ("inv_degree_last", ctypes.c_int), ("alpha", ctypes.c_double),
-        ("plain_per_ct", ctypes.c_int), ("debug_stop", ctypes.c_int),
+        ("power", ctypes.c_int), ("debug_stop", ctypes.c_int), ("newton_steps", ctypes.c_int),
+        ("mask_mode", ctypes.c_int),
     ]
 
 
@@ -76,6 +77,7 @@ def lib():
     L.hs_last_error.restype = ctypes.c_char_p
     sig = {
         "hs_ctx_create": [ctypes.POINTER(hs_params), S, _vp, ctypes.POINTER(_vp)],
+        "hs_ctx_create_ex": [ctypes.POINTER(hs_params), S, _vp, _ALLOC_FN, _FREE_FN, _vp, ctypes.POINTER(_vp)],
         "hs_ctx_get_info": [_vp, ctypes.POINTER(hs_ctx_info)],
         "hs_ctx_primes": [_vp, _u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "hs_sync": [_vp],
@@ -192,7 +194,9 @@ class Ciphertext:
         self.h = handle
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib is not None:
+        # after its context was closed the handle is left alone (its device
+        # block went back with the context)
+        if getattr(self, "h", None) and _lib is not None and getattr(self.ctx, "h", None):
             _lib.hs_ct_destroy(self.h)
             self.h = None
 
@@ -280,11 +284,67 @@ class SoftmaxPlan:
         self.close()
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
+class DeviceAllocator:
+    """Allocator callbacks of a context (hs_ctx_create_ex): ``get(nbytes,
+    stream)`` returns a device address or None, ``put(ptr, nbytes)`` takes it
+    back.  ``live`` maps the addresses handed out to their sizes."""
+
+    def __init__(self):
+        self.live = {}
+        self.alloc_cb = _ALLOC_FN(self._alloc)
+        self.free_cb = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, stream, user):
+        try:
+            p = self.get(int(nbytes), int(stream or 0))
+        except Exception:           # no memory (or any failure): the library raises HS_E_OOM
+            return None
+        if p:
+            self.live[int(p)] = int(nbytes)
+        return p or None
+
+    def _free(self, ptr, nbytes, user):
+        self.live.pop(int(ptr), None)
+        try:
+            self.put(int(ptr), int(nbytes))
+        except Exception:           # e.g. torch already torn down at interpreter exit
+            pass
+
+    def get(self, nbytes, stream):
+        raise NotImplementedError
+
+    def put(self, ptr, nbytes):
+        raise NotImplementedError
+
+
+class TorchAllocator(DeviceAllocator):
+    """Device memory from torch's caching allocator, in stream order on the
+    context's stream."""
+
+    def __init__(self, device):
+        super().__init__()
+        self.device = device
+
+    def get(self, nbytes, stream):
+        import torch
+        return torch.cuda.caching_allocator_alloc(nbytes, self.device, stream)
+
+    def put(self, ptr, nbytes):
+        import torch
+        torch.cuda.caching_allocator_delete(ptr)
+
+
 class Context:
     """One parameter set on one device.  ``params`` is a dict like the
-    presets in ``synthetic.PRESETS``."""
+    presets in ``synthetic.PRESETS``.  Device memory comes from ``allocator``:
+    "torch" (torch's caching allocator, the default), None (the library's
+    own hipMalloc) or a DeviceAllocator."""
 
-    def __init__(self, params, device=0, stream=None):
+    def __init__(self, params, device=0, stream=None, allocator="torch"):
         L = lib()
         self._keep = []
         qb = (ctypes.c_int * len(params["q_bits"]))(*params["q_bits"])
@@ -301,7 +361,14 @@ class Context:
             boot_log_scale=boot.get("log_boot_scale", 0))
         h = _vp()
         st = stream if stream is not None else None
-        _check(L.hs_ctx_create(ctypes.byref(p), device, st, ctypes.byref(h)))
+        if isinstance(allocator, str) and allocator == "torch":
+            allocator = TorchAllocator(device)
+        self.allocator = allocator          # the callbacks must outlive the context
+        if allocator is None:
+            _check(L.hs_ctx_create(ctypes.byref(p), device, st, ctypes.byref(h)))
+        else:
+            _check(L.hs_ctx_create_ex(ctypes.byref(p), device, st, allocator.alloc_cb, allocator.free_cb, None,
+                                      ctypes.byref(h)))
         self.h = h
         info = hs_ctx_info()
         _check(L.hs_ctx_get_info(h, ctypes.byref(info)))
@@ -314,10 +381,15 @@ class Context:
         self.dnum = info.dnum
         self.delta = float(2 ** params["log_scale"])
 
-    def __del__(self):
+    def close(self):
+        """hs_ctx_destroy now (every device block back to the allocator);
+        ciphertexts of this context must not be used afterwards."""
         if getattr(self, "h", None) and _lib is not None:
             _lib.hs_ctx_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        self.close()
 
     def primes(self):
         out = np.zeros(self.nq + self.np, dtype=np.uint64)
@@ -484,7 +556,8 @@ class Context:
     def bootstrap_stage(self, a, stage):
         return self._op("hs_dbg_bootstrap_stage", a.h, stage)
 
-    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), debug_stop=-1, jobs=1):
+    def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), debug_stop=-1, jobs=1,
+                power=0, newton_steps=0, mask_mode=0):
         """hs_softmax (jobs = 1) or hs_softmax_jobs over the packed ciphertexts
         `cts` (jobs consecutive groups of len(cts) / jobs); returns new handles."""
         m = len(cts)
@@ -492,14 +565,15 @@ class Context:
         out = (_vp * m)()
         o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
                             inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
-                            plain_per_ct=0, debug_stop=debug_stop)
+                            power=power, debug_stop=debug_stop, newton_steps=newton_steps, mask_mode=mask_mode)
         if jobs == 1:
             _check(lib().hs_softmax(self.h, arr, m, n, M, ctypes.byref(o), out))
         else:
             _check(lib().hs_softmax_jobs(self.h, arr, m, jobs, n, M, ctypes.byref(o), out))
         return [Ciphertext(self, _vp(out[i])) for i in range(m)]
 
-    def softmax_plan(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), jobs=1):
+    def softmax_plan(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), jobs=1, power=0,
+                     newton_steps=0, mask_mode=0):
         """hs_softmax_plan_create: capture the schedule of softmax(cts, ...)
         once (after one eager warm-up run on `cts`) for replays on new inputs
         of the same shape, level and scale."""
@@ -507,7 +581,7 @@ class Context:
         arr = (_vp * m)(*[c.h for c in cts])
         o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
                             inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
-                            plain_per_ct=0, debug_stop=-1)
+                            power=power, debug_stop=-1, newton_steps=newton_steps, mask_mode=mask_mode)
         h = _vp()
         _check(lib().hs_softmax_plan_create(self.h, arr, m, jobs, n, M, ctypes.byref(o), ctypes.byref(h)))
         return SoftmaxPlan(self, h, m)
@@ -577,6 +651,7 @@ def pack_softmax(logits, slots, M):
 def unpack_softmax(slot_vecs, n):
     slot_vecs = np.ascontiguousarray(slot_vecs, dtype=np.float64)
     m, slots = slot_vecs.shape
-    out = np.zeros((m * slots // n, n))
+    n2 = 1 << (int(n) - 1).bit_length()          # packed as the next power of two
+    out = np.zeros((m * slots // n2, n))
     _check(lib().hs_unpack_softmax(slot_vecs.reshape(-1), m, n, slots, out))
     return out

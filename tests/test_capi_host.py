@@ -47,16 +47,32 @@ def test_pack_range_check():
     with pytest.raises(hs.HSError) as e:
         hs.pack_softmax(x, 1024, 10.0)
     assert e.value.name == "HS_E_RANGE"
-    with pytest.raises(hs.HSError):
-        hs.pack_softmax(np.zeros((16, 48)), 1024, 10.0)    # n not a power of two
+    with pytest.raises(hs.HSError) as e:
+        hs.pack_softmax(np.zeros((8, 48)), 1024, 10.0)      # 8 x 64 padded slots < 1024
+    assert e.value.name == "HS_E_ARG"
+
+
+def test_pack_pads_a_dimension_that_is_not_a_power_of_two():
+    from paper_2410_11184_amd import hs
+    rng = np.random.default_rng(4)
+    x = -10.0 * rng.random((32, 48))                       # 32 vectors, padded to 64 coordinates
+    p = hs.pack_softmax(x, 1024, 10.0)
+    assert p.shape == (2, 1024)                            # m = 32 * 64 / 1024 ciphertexts
+    L, per = 32, 32
+    for j in range(2):
+        for c in range(per):
+            coord = j * per + c
+            want = x[:, coord] if coord < 48 else np.full(L, -10.0)
+            assert np.array_equal(p[j, c * L:(c + 1) * L], want), (j, c)
+    assert np.array_equal(hs.unpack_softmax(p, 48), x)
 
 
 def test_last_error_is_thread_local_string():
     from paper_2410_11184_amd import hs
     L = hs.lib()
-    st = L.hs_pack_softmax(np.zeros(4), 1, 3, 8, 1.0, None, ctypes.byref(ctypes.c_size_t()))
+    st = L.hs_pack_softmax(np.zeros(9), 1, 9, 8, 1.0, None, ctypes.byref(ctypes.c_size_t()))
     assert st == -2
-    assert b"power of two" in L.hs_last_error()
+    assert b"n must be <= slots" in L.hs_last_error()
 
 
 def test_tune_decisions_round_trip(tmp_path):
