@@ -47,6 +47,23 @@ def theorem_k(n, M):
     return max(1, int(v))
 
 
+def power_k(n, M, t):
+    """Iterations of the normalize-and-t-th-power variant (the appendix on
+    other normalisations): M / t^k ~ ln n; t = 2 is the Theorem's k."""
+    if t == 2:
+        return theorem_k(n, M)
+    v = math.ceil((math.log2(M) - math.log2(math.log(float(n)))) / math.log2(float(t)))
+    return max(1, int(v))
+
+
+def power_of(ctx, y, t):
+    """y^t, t in {2, 3, 4}: y^2 = y y, then y^2 y or y^2 y^2."""
+    y2 = P.mult(ctx, y, y)
+    if t == 2:
+        return y2
+    return P.mult(ctx, y2, y if t == 3 else y2)
+
+
 def ilog2(x):
     l = 0
     while (1 << l) < x:
@@ -81,8 +98,10 @@ def free_interval(lo, hi):
     return lo, lo + w
 
 
-def default_degree(n, j, last):
-    if n <= 256:
+def default_degree(n, j, last, t=2):
+    if t != 2:
+        d = (7 if last else 6) if n <= 16 else 7
+    elif n <= 256:
         d = 6 if j == 1 else (7 if last else 5)
     elif n <= 1024:
         d = 8 if last else 6
@@ -91,18 +110,74 @@ def default_degree(n, j, last):
     return (1 << d) - 1
 
 
+def newton_delta(delta, steps):
+    """Newton's error map for the inverse square root: y sqrt(s) = 1 + e
+    becomes 1 - e^2 (3 + e) / 2, so a bound delta becomes delta^2 (3 + delta) / 2."""
+    for _ in range(steps):
+        delta = delta * delta * (3.0 + delta) / 2.0
+    return delta
+
+
+def newton_invsqrt(ctx, S, y, steps, mask=None, avg=1):
+    """Newton's inverse square root iteration (Appendix A, the lemma on
+    computing inverse square roots) from the first guess y ~ S^(-1/2):
+    y <- 3/2 y - (S/2 y)(y y), two levels per step, S/2 being S with its
+    declared scale doubled.  The last step also applies the mask (S/2 times
+    the mask first, 3/2 y as the masked plaintext product) or, with avg > 1,
+    the averaging factor 1/avg (S / (2 avg) and 3/(2 avg) y by constant
+    products, so the integers, not only the declared scales, shrink); S has
+    levels above y, so neither costs a level of y's."""
+    for i in range(steps):
+        lastn = i + 1 == steps
+        if lastn and mask is not None:
+            ql = float(ctx.q[S.level])
+            h = ctx.rescale(ctx.mul_plain(S, mask.plaintext(ql, S.level), ql))
+            h.scale = S.scale * 2.0
+        elif lastn and avg > 1:
+            h = P.mul_const(ctx, S, 0.5 / avg, S.scale)
+        else:
+            h = S.copy()
+            h.scale = S.scale * 2.0
+        z1 = P.mult(ctx, h, y)
+        z2 = P.mult(ctx, y, y)
+        w = P.mult(ctx, z1, z2)
+        if lastn and mask is not None:
+            ql = float(ctx.q[y.level])
+            ps = w.scale * ql / y.scale
+            z3 = ctx.rescale(ctx.mul_plain(y, mask.plaintext(1.5 * ps, y.level), ps))
+            z3.scale = w.scale
+        else:
+            z3 = P.mul_const(ctx, y, 1.5 / avg if lastn else 1.5, w.scale)
+        y = ctx.sub_ct(P.drop(ctx, z3, w.level), w)
+    return y
+
+
 def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0), bootstrap=None,
-            debug_stop=-1, stats=None):
-    """Softmax of the L = m N0 / n vectors packed in the oracle ciphertexts
-    xs (m of them, one level and scale, inputs in [-M, 0]); returns the m
-    output ciphertexts.  The context must hold the relinearisation key; the
-    rotation keys of strides +-L 2^t are added here."""
+            debug_stop=-1, stats=None, power=2, newton_steps=0, mask_mode=0):
+    """Softmax of the L = m N0 / n2 vectors packed in the oracle ciphertexts
+    xs (m of them, one level and scale, inputs in [-M, 0]); n2 is n rounded
+    up to a power of two (the packing's dimension; the extra coordinates are
+    masked out after the exponential).  power: normalize-and-t-th-power (the
+    appendix on other normalisations; 2 is normalize-and-square).
+    Returns the m output ciphertexts.  The context must hold the
+    relinearisation key; the rotation keys of strides +-L 2^t are added
+    here.  newton_steps > 0: each inverse square root is the polynomial's
+    first guess refined by that many Newton steps (Algorithm SM with squares
+    only).  mask_mode 1: the averaging mask, the factor divided by n2/m on
+    every slot instead of the indicator of slots [0, L)."""
     N0 = ctx.slots
     m = len(xs)
-    assert n >= 2 and n & (n - 1) == 0 and n <= N0 and n % m == 0
-    L = m * N0 // n
-    k = k if k > 0 else theorem_k(n, M) + (1 if n >= 4096 else 0)
-    nrot = ilog2(n // m)
+    n2 = 1 << ilog2(n)
+    assert n >= 2 and n2 <= N0 and n2 % m == 0
+    tp = power
+    assert tp in (2, 3, 4) and (tp == 2 or variant == 0)
+    assert newton_steps == 0 or (tp == 2 and variant == 0)
+    avg = mask_mode == 1
+    tl = 1 if tp == 2 else 2         # levels of y^tp
+    L = m * N0 // n2
+    k = k if k > 0 else power_k(n, M, tp) + (1 if n >= 4096 else 0)
+    per = n2 // m
+    nrot = ilog2(per)
     smb = variant == 1
     log_scale = int(round(math.log2(ctx.delta)))
     Delta = math.ldexp(1.0, log_scale)
@@ -135,11 +210,25 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             v.append(c)
     else:
         v = [P.mul_const(ctx, x, 2.0 / M, Delta) for x in xs]
-    isn = 1.0 / math.sqrt(n)
+    # y0 = exp(x / tp^k) / n^(1/tp): sum y0^tp in [e^(-tp M / tp^k), 1]
+    isn = 1.0 / math.sqrt(n) if tp == 2 else math.pow(float(n), -1.0 / tp)
     Mm, kk = mpmath.mpf(M), k
-    pexp = P.cheb_interp(lambda t: mpmath.exp(Mm * t / mpmath.mpf(2) ** (kk + 1)) * mpmath.mpf(isn),
-                         -2.0, 0.0, exp_degree)
+    tk2 = mpmath.mpf(2) ** (kk + 1) if tp == 2 else 2 * mpmath.mpf(tp) ** kk
+    pexp = P.cheb_interp(lambda u: mpmath.exp(Mm * u / tk2) * mpmath.mpf(isn), -2.0, 0.0, exp_degree)
     y0 = [P.eval_cheb(ctx, c, pexp, -2.0, 0.0, Delta, log_scale) for c in v]
+    if n2 != n:
+        # padded dimension: ciphertext j keeps slots [0, R_j), R_j = (n - j
+        # per) L in [0, N0] (its real coordinates), by a 0/1 plaintext at
+        # scale q_l and one rescale; the scale stays y0's
+        out = []
+        for j, c in enumerate(y0):
+            R = min(max((n - j * per) * L, 0), N0)
+            ql = float(ctx.q[c.level])
+            pt = P.Mask(ctx, [1.0] * R + [0.0] * (N0 - R)).plaintext(ql, c.level)
+            r = ctx.rescale(ctx.mul_plain(c, pt, ql))
+            r.scale = c.scale
+            out.append(r)
+        y0 = out
     if debug_stop == 0:
         return y0
     mask = P.Mask(ctx, [1.0] * L + [0.0] * (N0 - L))
@@ -147,49 +236,76 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     y = list(y0)
     big = None
     ybound = isn * 1.05
-    lo = math.exp(-2.0 * M / math.ldexp(1.0, k)) * 0.98
+    lo = (math.exp(-2.0 * M / math.ldexp(1.0, k)) if tp == 2 else math.exp(-tp * M / math.pow(float(tp), k))) * 0.98
     hi = 1.0
     for j in range(1, k + 1):
         last = j == k
         smb_step = smb and not last
-        e = math.ldexp(1.0, -j) if smb_step else 0.5
+        e = math.ldexp(1.0, -j) if smb_step else (0.5 if tp == 2 else 1.0 / tp)
         deg = inv_degrees[0] if j == 1 else (inv_degrees[2] if last else inv_degrees[1])
         if deg <= 0:
-            deg = default_degree(n, j, last)
+            deg = default_degree(n, j, last, tp)
         a, b = free_interval(lo, hi)
         ee = mpmath.mpf(e)
         pinv = P.cheb_interp(lambda s: mpmath.power(s, -ee), a, b, deg)
-        delta = rel_error(pinv, a, b, lo, hi, e)
-        lam_bound = max_abs(pinv, a, b, lo, hi) * 1.05
+        delta = newton_delta(rel_error(pinv, a, b, lo, hi, e), newton_steps)
+        lam_bound = ((1.0 + delta) / math.sqrt(lo) if newton_steps else max_abs(pinv, a, b, lo, hi)) * 1.05
+        pe = [cf / per for cf in pinv] if avg and not newton_steps else pinv
+        if avg:
+            lam_bound /= per
         if not smb:
-            y = [ensure(c, 2 if last else 3, ybound) for c in y]
-        # auxiliary thread: S = sum of the squares, rotate-and-add
-        d = ctx.tensor(y[0], y[0])
-        for c in y[1:]:
-            d = ctx.add_ct(d, ctx.tensor(c, c))
-        S = ctx.rescale(ctx.relinearize(d))
+            y = [ensure(c, 1 + tl if last else 1 + 2 * tl, ybound) for c in y]
+        # auxiliary thread: S = sum of the t-th powers (squares: the tensors
+        # summed, one relinearisation), rotate-and-add
+        if tp == 2:
+            d = ctx.tensor(y[0], y[0])
+            for c in y[1:]:
+                d = ctx.add_ct(d, ctx.tensor(c, c))
+            S = ctx.rescale(ctx.relinearize(d))
+        else:
+            yt = [power_of(ctx, c, tp) for c in y]
+            S = yt[0]
+            for c in yt[1:]:
+                S = ctx.add_ct(S, c)
         for t in range(nrot):
             S = ctx.add_ct(S, ctx.rotate(S, -(L << t)))
-        S = ensure(S, P.depth(deg) + 1, hi * 1.1)
-        lam = P.eval_cheb(ctx, S, pinv, a, b, Delta, log_scale, mask)
+        # lambda lands depth (+ 1 when the affine map takes a level) + 2
+        # newton_steps below S; the cube and fourth power variants and
+        # Newton's steps also keep 1 + tl levels in lambda
+        keep = 2 + tl if (tp != 2 or newton_steps) else 1
+        S = ensure(S, P.depth(deg) + 2 * newton_steps + keep, hi * 1.1)
+        if not newton_steps:
+            lam = P.eval_cheb(ctx, S, pe, a, b, Delta, log_scale, None if avg else mask)
+        else:
+            g = P.eval_cheb(ctx, S, pinv, a, b, Delta, log_scale)
+            lam = newton_invsqrt(ctx, S, g, newton_steps, None if avg else mask, per if avg else 1)
         if not smb_step:
-            need_next = 2 if j + 1 == k else 3
-            if not last and bootstrap is not None and lam.level < y[0].level and lam.level - 2 < need_next:
-                lam = ensure(lam, y[0].level, lam_bound, L)
+            need_next = 1 + tl if j + 1 == k else 1 + 2 * tl
+            if not last and bootstrap is not None and lam.level < y[0].level and lam.level - 1 - tl < need_next:
+                lam = ensure(lam, y[0].level, lam_bound, 0 if avg else L)
             lam = broadcast(lam)
             z = [P.mult(ctx, c, lam) for c in y]
-            y = [P.mult(ctx, c, c) for c in z]
-            lo = math.pow(1.0 - delta, 4.0) / n * 0.98
-            hi = math.pow(1.0 + delta, 4.0) * 1.0001
+            y = [power_of(ctx, c, tp) for c in z]
+            # sum y in [(1 - delta)^tp, (1 + delta)^tp]; by the power-mean
+            # inequality sum y^tp in [(1 - delta)^(tp^2) / n^(tp-1), (1 + delta)^(tp^2)]
+            if tp == 2:
+                lo = math.pow(1.0 - delta, 4.0) / n * 0.98
+                hi = math.pow(1.0 + delta, 4.0) * 1.0001
+            else:
+                lo = math.pow(1.0 - delta, float(tp * tp)) / math.pow(float(n), tp - 1.0) * 0.98
+                hi = math.pow(1.0 + delta, float(tp * tp)) * 1.0001
             ybound = hi * 1.05
         else:
+            if avg:
+                lam = broadcast(lam)
             big = lam if big is None else P.mult(ctx, big, lam)
             r = 2 if j == k - 1 else 1
             want = j + 1 + r
             assert y0[0].level >= want, "version B: main-thread level budget exhausted"
             if big.level < want:
-                big = ensure(big, want, max(64.0, lam_bound, 4.0 * math.sqrt(n)), L)
-            bb = broadcast(big)
+                big = ensure(big, want, max(64.0, lam_bound * per if avg else lam_bound, 4.0 * math.sqrt(n)),
+                             0 if avg else L)
+            bb = big if avg else broadcast(big)
             y = [P.mult(ctx, c, bb) for c in y0]
             for _ in range(j):
                 y = [P.mult(ctx, c, c) for c in y]

@@ -91,6 +91,21 @@ def main_loop(x, k, exp_fn=None, norm_fns=None, rng=None, eps=0.0):
     return y
 
 
+def power_loop(x, k, t, exp_fn=None, norm_fns=None):
+    """Normalize-and-t-th-power (the appendix on other normalisation
+    strategies): y0 = exp(x / t^k); k times lambda = (sum y^t)^(-1/t),
+    y = (lambda y)^t.  With exact functions it returns SM(x), since
+    SM(x) = normalize(SM(x / t)^t); norm_fns[j-1](s) approximates s^(-1/t)."""
+    x = np.asarray(x, dtype=np.float64)
+    exp_fn = exp_fn or np.exp
+    y = exp_fn(x / float(t) ** k)
+    for j in range(1, k + 1):
+        f = norm_fns[j - 1] if norm_fns else (lambda s: s ** (-1.0 / t))
+        s = (y ** t).sum(axis=-1, keepdims=True)
+        y = (f(s) * y) ** t
+    return y
+
+
 def softmax_b(x, k, exp_fn=None, pow_fns=None):
     """Algorithm SM version B: Lambda = 1; y0 = exp(x/2^k); for j = 1..k:
     lambda_j = (sum y^(j-1)^2)^(-2^-j), Lambda *= lambda_j, z = Lambda y0,
@@ -112,29 +127,41 @@ def softmax_b(x, k, exp_fn=None, pow_fns=None):
 
 
 # --------------------------------------------------------------- packing
-def pack(logits, m, slots):
-    """(L, n) logits -> (m, slots) slot vectors; L must equal m*slots/n."""
+def padded(n):
+    """The power of two at or above n (a dimension's packing width)."""
+    return 1 << (int(n) - 1).bit_length()
+
+
+def pack(logits, m, slots, pad_value=None):
+    """(L, n) logits -> (m, slots) slot vectors; L must equal m*slots/n2 with
+    n2 = padded(n); coordinates n..n2-1 take pad_value (default: the row
+    minimum's floor, i.e. any value in range; they are masked out)."""
     logits = np.asarray(logits, dtype=np.float64)
     L, n = logits.shape
-    if n & (n - 1) or n > slots or m < 1 or n % m or L * n != m * slots:
+    n2 = padded(n)
+    if n2 > slots or m < 1 or n2 % m or L * n2 != m * slots:
         raise ValueError("bad packing shape")
-    per = n // m
+    pv = float(np.min(logits)) if pad_value is None else pad_value
+    per = n2 // m
     out = np.zeros((m, slots))
     for j in range(m):
         for c in range(per):
-            out[j, c * L:(c + 1) * L] = logits[:, j * per + c]
+            coord = j * per + c
+            out[j, c * L:(c + 1) * L] = logits[:, coord] if coord < n else pv
     return out
 
 
 def unpack(slots_m, n):
     slots_m = np.asarray(slots_m)
     m, slots = slots_m.shape
-    L = m * slots // n
-    per = n // m
+    n2 = padded(n)
+    L = m * slots // n2
+    per = n2 // m
     out = np.zeros((L, n), dtype=slots_m.dtype)
     for j in range(m):
         for c in range(per):
-            out[:, j * per + c] = slots_m[j, c * L:(c + 1) * L]
+            if j * per + c < n:
+                out[:, j * per + c] = slots_m[j, c * L:(c + 1) * L]
     return out
 
 

@@ -189,6 +189,70 @@ static Ct mask_padding(Context& c, const Ct& y0, int n, int per, int L, int m) {
     return r;
 }
 
+// Inverse square root by Newton's iteration (Appendix A, the lemma on
+// computing inverse square roots): from the first guess y ~ S^(-1/2),
+// `steps` times y <- 1.5 y - (S/2 y)(y y), two levels per step; S/2 is S
+// with its declared scale doubled (no level).  The last step also applies
+// the factor `fac` to the result: the 0/1 mask (`mask` given: S/2 taken
+// times the mask first, at S's higher level, and 1.5 y as the masked
+// plaintext product) or the averaging factor 1/avg (S/(2 avg) and 1.5/avg y by
+// constant products, so the integers shrink, not only the declared scales);
+// S has levels above y, so neither costs one of y's levels.
+static Ct newton_invsqrt(Context& c, const Ct& S, const Ct& y0, int steps, const double* mask, int avg) {
+    Ct y = ct_copy(c, y0);
+    for (int i = 0; i < steps; i++) {
+        const bool lastn = i + 1 == steps;
+        Ct h;
+        if (lastn && mask) {
+            const double ql = (double)c.primes[S.level];
+            bool owned;
+            u64* pt = mask_plaintext(c, mask, S.level, ql, &owned);
+            h = op_mul_plain(c, S, pt, ql, true);
+            if (owned) c.free_words(pt);
+            h.scale = S.scale * 2.0;
+        } else if (lastn && avg > 1) {
+            h = op_mul_const(c, S, 0.5 / avg, S.scale);
+        } else {
+            h = ct_copy(c, S);
+            h.scale = S.scale * 2.0;
+        }
+        Ct z1 = op_mult(c, h, y);
+        ct_free(c, h);
+        Ct z2 = op_mult(c, y, y);
+        Ct w = op_mult(c, z1, z2);
+        ct_free(c, z1);
+        ct_free(c, z2);
+        Ct z3;
+        if (lastn && mask) {
+            // 1.5 mask y at w's scale: plaintext scale ps with y.scale ps / q_l = w.scale
+            const double ql = (double)c.primes[y.level];
+            const double ps = w.scale * ql / y.scale;
+            bool owned;
+            u64* pt = mask_plaintext(c, mask, y.level, 1.5 * ps, &owned);
+            z3 = op_mul_plain(c, y, pt, ps, true);
+            if (owned) c.free_words(pt);
+            z3.scale = w.scale;
+        } else {
+            z3 = op_mul_const(c, y, lastn ? 1.5 / avg : 1.5, w.scale);
+        }
+        Ct z3d = ct_drop(c, z3, w.level);
+        ct_free(c, z3);
+        op_sub_inplace(c, z3d, w);
+        ct_free(c, w);
+        ct_free(c, y);
+        y = z3d;
+    }
+    return y;
+}
+
+// Newton's error map for the inverse square root: y sqrt(s) = 1 + e gives
+// 1 - e^2 (3 + e) / 2 after one step; a relative error bound delta becomes
+// delta^2 (3 + delta) / 2
+static double newton_delta(double delta, int steps) {
+    for (int i = 0; i < steps; i++) delta = delta * delta * (3.0 + delta) / 2.0;
+    return delta;
+}
+
 // rotate-and-add with strides +L 2^t: slots [0, L) copied to all n/m blocks
 static void broadcast(Context& c, Ct& a, int L, int nrot) {
     for (int t = 0; t < nrot; t++) {
@@ -227,16 +291,21 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     HS_REQUIRE(M > 0, E_ARG, "range M must be positive");
     HS_REQUIRE(x.ncomp == 2, E_ARG, "degree-1 ciphertexts expected");
     const bool smb = o.variant == 1;
+    HS_REQUIRE(o.newton_steps >= 0 && o.newton_steps <= 8, E_PARAM, "Newton steps must be in 0..8");
+    HS_REQUIRE(o.mask_mode == 0 || o.mask_mode == 1, E_PARAM, "mask mode must be 0 or 1");
+    const bool avg = o.mask_mode == 1;
     // normalize-and-t-th-power (t = 2: normalize-and-square)
-    const int t = o.power > 0 ? o.power : 2;
-    HS_REQUIRE(t >= 2 && t <= 4, E_PARAM, "power must be 2, 3 or 4");
-    HS_REQUIRE(t == 2 || !smb, E_PARAM, "version B normalizes with squares (power 2)");
-    const int tl = t == 2 ? 1 : 2;          // levels of y^t
+    const int tp = o.power > 0 ? o.power : 2;
+    HS_REQUIRE(tp >= 2 && tp <= 4, E_PARAM, "power must be 2, 3 or 4");
+    HS_REQUIRE(tp == 2 || !smb, E_PARAM, "version B normalizes with squares (power 2)");
+    HS_REQUIRE(o.newton_steps == 0 || (tp == 2 && !smb), E_PARAM,
+               "Newton's iteration computes inverse square roots: Algorithm SM with squares");
+    const int tl = tp == 2 ? 1 : 2;         // levels of y^tp
     const int L = (int)((long long)m * N0 / np2);
     // Theorem "th:prec_softmax"'s k (M / t^k ~ ln n for the t-th power
     // variant); from n = 4096 one more iteration, which narrows the first
     // normalisation interval [e^(-t M / t^k), 1]
-    const int k = o.k > 0 ? o.k : power_k(n, M, t) + (n >= 4096 ? 1 : 0);
+    const int k = o.k > 0 ? o.k : power_k(n, M, tp) + (n >= 4096 ? 1 : 0);
     const int per = np2 / m;
     const int nrot = ilog2(per);
     const double Delta = std::ldexp(1.0, c.prm.log_scale);
@@ -257,10 +326,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     }
     // y0 = exp(x / t^k) / n^(1/t)  (the prescale keeps sum y0^t in
     // [e^(-t M / t^k), 1])
-    const double isn = t == 2 ? 1.0 / std::sqrt((double)n) : std::pow((double)n, -1.0 / t);
+    const double isn = tp == 2 ? 1.0 / std::sqrt((double)n) : std::pow((double)n, -1.0 / tp);
     const quad Mq = M;
     const int kk = k;
-    const quad tk2 = t == 2 ? ldexpq(1, kk + 1) : 2 * powq((quad)t, (quad)kk);
+    const quad tk2 = tp == 2 ? ldexpq(1, kk + 1) : 2 * powq((quad)tp, (quad)kk);
     ChebPoly pexp = cheb_fit([&](quad u) { return expq(Mq * u / tk2) * (quad)isn; }, -2.0, 0.0, o.exp_degree);
     Ct y0 = eval_cheb(c, v, pexp, Delta);
     ct_free(c, v);
@@ -276,13 +345,13 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     Ct big;                     // Lambda (version B), on slots [0, L) only
     bool have_big = false;
     double ybound = isn * 1.05; // bound on |y^(j-1)| for its bootstrapping
-    double lo = (t == 2 ? std::exp(-2.0 * M / std::ldexp(1.0, k)) : std::exp(-t * M / std::pow((double)t, k))) * 0.98;
+    double lo = (tp == 2 ? std::exp(-2.0 * M / std::ldexp(1.0, k)) : std::exp(-tp * M / std::pow((double)tp, k))) * 0.98;
     double hi = 1.0;
     for (int j = 1; j <= k; j++) {
         const bool last = j == k;
         const bool smb_step = smb && !last;
         // exponent of the normalisation: 1/t (SM, and the last step of B) or 2^-j
-        const double e = smb_step ? std::ldexp(1.0, -j) : (t == 2 ? 0.5 : 1.0 / t);
+        const double e = smb_step ? std::ldexp(1.0, -j) : (tp == 2 ? 0.5 : 1.0 / tp);
         int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
         if (deg <= 0) {
             // the paper's depths at n = 256 (6, 5, 7) for n <= 256 (its
@@ -290,8 +359,11 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             // interpolants do not); above, one more level for the first and
             // middle steps (the interpolants' relative error at the low end of
             // [~1/n, 1] would otherwise widen every later interval)
+            // t-th powers: the later intervals [~n^-(t-1), 1] are far wider,
+            // so depth 6 / 7 up to n = 16 and 7 above
             int d;
-            if (n <= 256) d = j == 1 ? 6 : (last ? 7 : 5);
+            if (tp != 2) d = n <= 16 ? (last ? 7 : 6) : 7;
+            else if (n <= 256) d = j == 1 ? 6 : (last ? 7 : 5);
             else if (n <= 1024) d = last ? 8 : 6;
             else d = last ? 8 : 7;
             deg = (1 << d) - 1;
@@ -300,8 +372,16 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         free_interval(lo, hi, a, b);
         const double ee = e;
         ChebPoly pinv = cheb_fit([&](quad s) { return powq(s, -(quad)ee); }, a, b, deg);
-        const double delta = rel_error(pinv, lo, hi, e);
-        const double lam_bound = max_abs(pinv, lo, hi) * 1.05;
+        const int nsteps = o.newton_steps;
+        const double delta = newton_delta(rel_error(pinv, lo, hi, e), nsteps);
+        double lam_bound = (nsteps ? (1.0 + delta) / std::sqrt(lo) : max_abs(pinv, lo, hi)) * 1.05;
+        // the averaging mask: per copies of the factor, each divided by per,
+        // summed by the broadcast (the division folded into the coefficients
+        // when there is no Newton step, exact since per is a power of two)
+        ChebPoly pe = pinv;
+        if (avg && !nsteps)
+            for (double& cf : pe.c) cf /= per;
+        if (avg) lam_bound /= per;
         // main thread: this iteration's z = lambda y and z^t (1 + tl levels),
         // then the levels of the next y^t feeding S
         if (!smb) {
@@ -315,14 +395,14 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // auxiliary thread, powering: S = sum over the m ciphertexts of y^t
         // (squares: one relinearisation for the whole sum)
         Ct S;
-        if (t == 2) {
+        if (tp == 2) {
             Ct d = op_square_sum_jobs(c, y, J);
             Ct r = op_relin(c, d);
             ct_free(c, d);
             S = op_rescale(c, r);
             ct_free(c, r);
         } else {
-            Ct yt = op_power(c, y, t);
+            Ct yt = op_power(c, y, tp);
             S = op_sum_jobs(c, yt, J);
             ct_free(c, yt);
         }
@@ -332,17 +412,31 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             op_add_inplace(c, S, rr);
             ct_free(c, rr);
         }
-        // budget of the normalisation polynomial (mask folded into its leaves)
+        // budget of the normalisation polynomial (mask folded into its leaves,
+        // or into the last Newton step)
         {
+            // lambda lands cheb_depth (+ 1 when the affine map takes a
+            // level) + 2 nsteps below S; the cube and fourth power variants
+            // and Newton's steps also keep 1 + tl levels in lambda for
+            // z = lambda y and z^t
+            const int keep = (tp != 2 || nsteps) ? 2 + tl : 1;
             bool rep;
-            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 1, hi * 1.1, st, rep, "S", j);
+            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 2 * nsteps + keep, hi * 1.1, st, rep, "S", j);
             if (rep) {
                 ct_free(c, S);
                 S = S2;
             }
         }
         // normalisation and mask: lambda = P(S) * mask, on slots [0, L)
-        Ct lam = eval_cheb(c, S, pinv, Delta, mask);
+        // (averaging: P(S) / per on every slot)
+        Ct lam;
+        if (!nsteps) {
+            lam = eval_cheb(c, S, pe, Delta, avg ? nullptr : mask);
+        } else {
+            Ct g = eval_cheb(c, S, pinv, Delta);
+            lam = newton_invsqrt(c, S, g, nsteps, avg ? nullptr : mask, avg ? per : 1);
+            ct_free(c, g);
+        }
         ct_free(c, S);
         if (!smb_step) {
             // SM step (and the last step of version B): z = lambda y, y = z^t.
@@ -353,7 +447,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             const int need_next = (j + 1 == k) ? 1 + tl : 1 + 2 * tl;
             if (!last && can_bootstrap(c) && lam.level < y.level && lam.level - 1 - tl < need_next) {
                 bool rep;
-                Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep, "lambda", j, L);
+                Ct l2 = ensure_level(c, lam, y.level, lam_bound, st, rep, "lambda", j, avg ? 0 : L);
                 if (rep) {
                     ct_free(c, lam);
                     lam = l2;
@@ -365,21 +459,24 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             Ct z = op_mult(c, y, lj);
             ct_free(c, lj);
             ct_free(c, y);
-            y = op_power(c, z, t);
+            y = op_power(c, z, tp);
             ct_free(c, z);
             // sum y^(j) in [(1 - delta)^t, (1 + delta)^t], so by the power-mean
             // inequality sum (y^(j))^t in [(1 - delta)^(t^2) / n^(t-1), (1 + delta)^(t^2)]
-            if (t == 2) {
+            if (tp == 2) {
                 lo = std::pow(1.0 - delta, 4.0) / n * 0.98;
                 hi = std::pow(1.0 + delta, 4.0) * 1.0001;
             } else {
-                lo = std::pow(1.0 - delta, (double)(t * t)) / std::pow((double)n, t - 1.0) * 0.98;
-                hi = std::pow(1.0 + delta, (double)(t * t)) * 1.0001;
+                lo = std::pow(1.0 - delta, (double)(tp * tp)) / std::pow((double)n, tp - 1.0) * 0.98;
+                hi = std::pow(1.0 + delta, (double)(tp * tp)) * 1.0001;
             }
             ybound = hi * 1.05;
         } else {
             // version B: Lambda = Lambda * lambda_j (both on slots [0, L));
-            // z = broadcast(Lambda) y0; y = z^(2^j)
+            // z = broadcast(Lambda) y0; y = z^(2^j).  Averaging mask: lambda_j
+            // broadcast first (the average of its copies on every slot), so
+            // Lambda is kept on every slot and needs no broadcast
+            if (avg) broadcast(c, lam, L, nrot);
             if (!have_big) {
                 big = lam;
                 have_big = true;
@@ -396,14 +493,15 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             HS_REQUIRE(y0.level >= want, E_LEVEL, "Softmax version B: main-thread level budget exhausted");
             if (big.level < want) {
                 bool rep;
-                Ct b2 = ensure_level(c, big, want, lam_bound_big(n, lam_bound), st, rep, "Lambda", j, L);
+                Ct b2 = ensure_level(c, big, want, lam_bound_big(n, avg ? lam_bound * per : lam_bound), st, rep,
+                                     "Lambda", j, avg ? 0 : L);
                 if (rep) {
                     ct_free(c, big);
                     big = b2;
                 }
             }
             Ct bb = ct_copy(c, big);
-            broadcast(c, bb, L, nrot);
+            if (!avg) broadcast(c, bb, L, nrot);
             Ct bj = per_job(c, bb, J, m);
             ct_free(c, bb);
             Ct z = op_mult(c, y0, bj);

@@ -30,6 +30,28 @@ CASES = [
     # bootstrapping at N = 2^16
     (1, 4, 64, 8.0, 2, 7, (15, 15, 31), 10.0),
 ]
+# (variant, m, n, M, k, exp degree, normalisation degrees, bits, power):
+# normalize-and-cube (the appendix on other normalisations; k = 1 from
+# M / 3^k ~ ln n), and dimensions that are not powers of two (12 packed as 16,
+# the 4 extra coordinates masked after the exponential)
+# then (Newton steps, mask mode): the inverse square roots refined by one
+# Newton step from degree-7 first guesses (Appendix A), with the indicator
+# mask folded into that step or with the averaging mask (the toy ring's
+# levels allow no more: about 8 bits, 3.4 without the Newton step), and
+# version B with the averaging mask
+MORE = [
+    (0, 1, 8, 4.0, 0, 7, (31, 31, 31), 14.0, 3, 0, 0),
+    (1, 2, 12, 8.0, 0, 7, (15, 15, 31), 16.0, 2, 0, 0),
+    (0, 1, 12, 8.0, 0, 7, (15, 15, 15), 13.0, 2, 0, 0),
+    (0, 1, 16, 8.0, 0, 7, (7, 7, 7), 8.0, 2, 1, 0),
+    (0, 2, 16, 8.0, 0, 7, (7, 7, 7), 8.0, 2, 1, 1),
+    (1, 2, 16, 8.0, 0, 7, (15, 15, 31), 16.0, 2, 0, 1),
+]
+
+
+def _case_id(c):
+    c = c + (2, 0, 0)[len(c) - 8:]
+    return "v%d-m%d-n%d-t%d-nw%d-avg%d" % (c[0], c[1], c[2], c[8], c[9], c[10])
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +68,7 @@ def pair():
 
 def _inputs(g, o, n, M, m, seed):
     from oracle import softmax as S
-    L = m * o.slots // n
+    L = m * o.slots // S.padded(n)
     x = synthetic.logits_uniform(L, n, M, seed=seed)
     packed = S.pack(x, m, o.slots)
     scale = o.delta * 2.0 / M
@@ -73,19 +95,21 @@ def _compare(g, o, gy, oy, what):
                             "decrypted max difference %.3g" % (what, i, k, len(bad), bad[0], diff))
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "v%d-m%d-n%d" % (c[0], c[1], c[2]))
+@pytest.mark.parametrize("case", CASES + MORE, ids=_case_id)
 def test_schedule_matches_oracle(pair, case):
     from oracle import schedule, softmax as S
     g, o = pair
-    variant, m, n, M, k, dexp, dinv, want_bits = case
+    variant, m, n, M, k, dexp, dinv, want_bits, t, nw, mm = case + (2, 0, 0)[len(case) - 8:]
+    opt = dict(power=t, newton_steps=nw, mask_mode=mm)
     x, gx, ox = _inputs(g, o, n, M, m, seed=700 + 10 * variant + m)
     # first polynomial alone
-    gy0 = g.softmax(gx, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv, debug_stop=0)
-    oy0 = schedule.softmax(o, ox, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv, debug_stop=0)
+    gy0 = g.softmax(gx, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv, debug_stop=0, **opt)
+    oy0 = schedule.softmax(o, ox, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv, debug_stop=0,
+                           **opt)
     _compare(g, o, gy0, oy0, "y0")
     # the whole schedule
-    gy = g.softmax(gx, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv)
-    oy = schedule.softmax(o, ox, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv)
+    gy = g.softmax(gx, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv, **opt)
+    oy = schedule.softmax(o, ox, n, M, variant=variant, k=k, exp_degree=dexp, inv_degrees=dinv, **opt)
     _compare(g, o, gy, oy, "output")
     y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy]), n)
     bits = S.precision_bits(S.softmax(x), y)

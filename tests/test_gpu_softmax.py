@@ -71,9 +71,20 @@ def test_out_of_range_rejected_at_pack_time(ctx):
 
 
 def test_bad_dimension(ctx):
+    # a dimension below 2 or one whose padded width exceeds the slots is
+    # refused; 12 is accepted (packed as 16)
     from paper_2410_11184_amd import hs
     x = np.zeros((1, ctx.slots))
     cts = [ctx.encrypt(x[0], ctx.user_top, ctx.delta, 1)]
     with pytest.raises(hs.HSError) as e:
-        ctx.softmax(cts, 12, 8.0)
+        ctx.softmax(cts, 1, 8.0)
+    assert e.value.name == "HS_E_PARAM"
+    with pytest.raises(hs.HSError) as e:
+        ctx.softmax(cts, ctx.slots + 1, 8.0)
+    assert e.value.name == "HS_E_ARG"
+    with pytest.raises(hs.HSError) as e:
+        ctx.softmax(cts, 16, 8.0, power=5)
+    assert e.value.name == "HS_E_PARAM"
+    with pytest.raises(hs.HSError) as e:
+        ctx.softmax(cts, 16, 8.0, variant=1, newton_steps=1)
     assert e.value.name == "HS_E_PARAM"

@@ -68,7 +68,42 @@ def test_packed_twin(m):
         y = S.unpack(S.sm_packed(packed, n, 5, variant=variant), n)
         assert np.max(np.abs(y - S.softmax(x))) < 1e-12
     with pytest.raises(ValueError):
-        S.pack(x[:, :255], m, slots)
+        S.pack(x[:L // 2], m, slots)             # too few vectors for m ciphertexts
+
+
+def test_padded_packing_round_trip():
+    # n = 200 packed as 256: coordinates 200..255 hold the pad value
+    n, slots, m = 200, 1 << 12, 4
+    L = m * slots // 256
+    x = np.random.default_rng(9).uniform(-64, 0, (L, n))
+    p = S.pack(x, m, slots, pad_value=-64.0)
+    per = 256 // m
+    assert np.all(p[3, (200 - 3 * per) * L:] == -64.0) and np.all(p[:3] > -64.0 - 1e-9)
+    assert np.array_equal(S.unpack(p, n), x)
+
+
+@pytest.mark.parametrize("t", [2, 3, 4])
+def test_power_loop_identity(t):
+    # SM(x) = normalize(SM(x / t)^t) applied k times: exact functions give SM(x)
+    rng = np.random.default_rng(t)
+    x = rng.uniform(-32, 0, (500, 24))
+    for k in (1, 2, 3):
+        assert np.max(np.abs(S.power_loop(x, k, t) - S.softmax(x))) < 1e-12
+    # one step from SM(x / t) is the appendix's identity itself
+    y = S.softmax(x / t) ** t
+    assert np.max(np.abs(y / y.sum(axis=-1, keepdims=True) - S.softmax(x))) < 1e-12
+
+
+@pytest.mark.parametrize("t", [2, 3, 4])
+def test_power_sum_range(t):
+    # after a t-th power normalisation sum y = 1, so by the power-mean
+    # inequality sum y^t lies in [n^-(t-1), 1], with both ends reached
+    n = 16
+    rng = np.random.default_rng(10 + t)
+    y = S.softmax(rng.uniform(-20, 0, (2000, n)))
+    s = (y ** t).sum(axis=-1)
+    assert np.all(s >= n ** -(t - 1.0) * (1 - 1e-12)) and np.all(s <= 1.0 + 1e-12)
+    assert abs((np.full(n, 1.0 / n) ** t).sum() - n ** -(t - 1.0)) < 1e-15
 
 
 def test_theorem_bound_under_fixed_point_noise():
@@ -135,6 +170,42 @@ def test_cheb_interp_reproduces_polynomials():
     assert np.max(np.abs(P.cheb_eval(e, g, -128.0, 0.0) - np.exp(g / 32))) < 2 ** -40
 
 
+@pytest.mark.parametrize("case", [(0, 1, 8, 4.0, 3, (31, 31, 31), 14.0, 0, 0),
+                                  (1, 2, 12, 8.0, 2, (15, 15, 31), 16.0, 0, 0),
+                                  (0, 2, 16, 8.0, 2, (7, 7, 7), 8.0, 1, 1)],
+                         ids=["cube-n8", "padded-n12", "newton-averaging"])
+def test_encrypted_schedule_variants_on_toy_ring(case):
+    # normalize-and-cube, a padded dimension, and Newton's inverse square root
+    # with the averaging mask through the oracle's encrypted schedule: after
+    # the exponential the padding coordinates hold 0 and the
+    # real ones exp(x / t^k) / n^(1/t) (closed form); the output is the FP64
+    # Softmax of the n real coordinates to the bits these degrees reach
+    import synthetic
+    from oracle import ckks, schedule
+    variant, m, n, M, t, dinv, bits_min, nw, mm = case
+    opt = dict(power=t, newton_steps=nw, mask_mode=mm)
+    p = synthetic.preset("toy12")
+    o = ckks.Context(**p)
+    o.keygen(98)
+    n2 = S.padded(n)
+    L = m * o.slots // n2
+    x = synthetic.logits_uniform(L, n, M, seed=321)
+    packed = S.pack(x, m, o.slots)
+    xs = [o.encode_encrypt(packed[j], o.delta * 2.0 / M, p["user_top"], 7 + j) for j in range(m)]
+    k = schedule.power_k(n, M, t)
+    y0 = schedule.softmax(o, xs, n, M, variant=variant, exp_degree=7, inv_degrees=dinv, debug_stop=0, **opt)
+    raw = np.stack([o.decrypt_decode(c).real for c in y0])
+    got0 = S.unpack(raw, n2)
+    want0 = np.zeros((L, n2))
+    want0[:, :n] = np.exp(x / float(t) ** k) * float(n) ** (-1.0 / t)
+    assert np.max(np.abs(got0 - want0)) < 2.0 ** -14
+    ys = schedule.softmax(o, xs, n, M, variant=variant, exp_degree=7, inv_degrees=dinv, **opt)
+    y = S.unpack(np.stack([o.decrypt_decode(c).real for c in ys]), n)
+    bits = S.precision_bits(S.softmax(x), y)
+    assert bits["worst"] >= bits_min, bits
+    assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2.0 ** -(bits_min - 2)
+
+
 @pytest.mark.parametrize("variant", [0, 1])
 def test_encrypted_schedule_on_toy_ring(variant):
     # The oracle's encrypted schedule (Algorithm SM / version B with the
@@ -160,3 +231,20 @@ def test_encrypted_schedule_on_toy_ring(variant):
     bits = S.precision_bits(S.softmax(x), y)
     assert bits["worst"] >= 16.0, bits
     assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2.0 ** -14
+
+
+def test_newton_inverse_sqrt_error_map():
+    # Appendix A: with y sqrt(x) = 1 + e, one step y (3 - x y^2) / 2 leaves
+    # 1 - e^2 (3 + e) / 2; the schedule's bound delta -> delta^2 (3 + delta)/2
+    # is that map at its worst sign, and two steps from 1/2 stay below the
+    # lemma's (4/7) (7/8)^(2^n)
+    from oracle import schedule
+    x = np.linspace(0.01, 4.0, 1001)
+    for e in (-0.4, -0.1, 0.05, 0.3):
+        y = (1 + e) / np.sqrt(x)
+        y1 = y * (3 - x * y * y) / 2
+        assert np.allclose(y1 * np.sqrt(x) - 1, -e * e * (3 + e) / 2, atol=1e-14)
+        assert abs(e * e * (3 + e) / 2) <= schedule.newton_delta(abs(e), 1) + 1e-17
+    d = 0.5
+    for steps in (1, 2, 3):
+        assert schedule.newton_delta(d, steps) <= 4 / 7 * (7 / 8) ** (2 ** steps)
