@@ -352,6 +352,8 @@ def main():
                     help="also time version-B jobs of 1, 2, 4, ..., 64 ciphertexts")
     ap.add_argument("--sm-many", action="store_true",
                     help="also time version SM on the same 64 ciphertexts (bootstraps the main ciphertexts)")
+    ap.add_argument("--trade", action="store_true",
+                    help="also time the Softmax variants (SM / SM-B, averaging mask, Newton) at the metric's shape")
     ap.add_argument("--tune", action="store_true",
                     help="time interchangeable kernels during the warm-up and save the decisions")
     ap.add_argument("--tune-file", default="tune_decisions.json",
@@ -566,6 +568,36 @@ def main():
         _log("SM many-ciphertext: %.2fs per job, %.1f calls/s, %d bootstraps, worst %.2f bits" %
              (tsm, L / tsm, st_sm["bootstraps"], bsm["worst"]))
 
+    trade = None
+    if args.trade:
+        # trade study at the metric's shape (eager, each variant warmed once
+        # then timed once): version B against Algorithm SM, the averaging
+        # mask, Newton's inverse square root (Algorithm SM only)
+        def row(name, cs, Lr, xr, **kw):
+            ctx.softmax(cs, n, M, **kw)
+            ctx.sync()
+            t0 = time.perf_counter()
+            o_ = ctx.softmax(cs, n, M, **kw)
+            ctx.sync()
+            tr = time.perf_counter() - t0
+            st_ = ctx.softmax_stats()
+            b_ = S.precision_bits(S.softmax(xr), decrypt_outputs(ctx, o_, n))
+            r = dict(variant=name, ciphertexts=len(cs), calls=Lr, s_per_job=tr, calls_per_s=Lr / tr,
+                     bootstraps=st_["bootstraps"], k=st_["k"], worst_bits=b_["worst"], mean_bits=b_["mean"])
+            _log("trade %s: %.3fs, %.1f calls/s, %d bootstraps, worst %.2f bits" %
+                 (name, tr, Lr / tr, st_["bootstraps"], b_["worst"]))
+            return r
+        xp1 = synthetic.logits_uniform(p["slots"] // n, n, M, seed=9101)
+        cp1 = encrypt_logits(ctx, xp1, M, seed=9102)
+        trade = [row("SM-B, indicator mask", cts, L, x, variant=1),
+                 row("SM-B, averaging mask", cts, L, x, variant=1, mask_mode=1),
+                 row("SM, indicator mask", cts, L, x, variant=0),
+                 row("SM, 1 ciphertext", cp1, p["slots"] // n, xp1, variant=0),
+                 row("SM, 1 ciphertext, Newton x1", cp1, p["slots"] // n, xp1, variant=0, newton_steps=1),
+                 row("SM, 1 ciphertext, Newton x2 from degrees 15/15/31", cp1, p["slots"] // n, xp1, variant=0,
+                     newton_steps=2, inv_degrees=(15, 15, 31)),
+                 row("SM, 1 ciphertext, averaging mask", cp1, p["slots"] // n, xp1, variant=0, mask_mode=1)]
+
     plain = None
     if not args.no_plain:
         wp = synthetic.WORKLOADS["fgb16_sm"]
@@ -636,6 +668,7 @@ def main():
         "plain": plain,
         "speedup_vs_plain": (value / plain["calls_per_s"]) if plain else None,
         "sm_many_ciphertext": sm_many,
+        "trade_study": trade,
         "lockstep_jobs": lockstep,
         "smb_scaling": sweep,
         # not the metric: the client side (pack, encode, PCIe upload, encrypt) and decryption

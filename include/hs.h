@@ -413,6 +413,15 @@ hs_status hs_op_counts(hs_ctx* ctx, double* out, size_t n, int clear);
  * after its first / second level. */
 hs_status hs_dbg_bootstrap_stage(hs_ctx* ctx, const hs_ct* a, int stage, hs_ct** out);
 
+/* Device time of the NTT kernels (not an operation of the paper; for kernel
+ * measurements): `groups` groups of level+1 rows of pseudo-random residues
+ * (the layout of one ciphertext component per group, row i modulo q_i) are
+ * transformed `reps` times (forward, or inverse when inverse != 0) on the
+ * context's stream; *us receives the average microseconds per transform
+ * launch over all groups.  HS_E_ARG for groups outside 1..4096 or reps
+ * outside 1..1000, HS_E_LEVEL for a level outside 0..top. */
+hs_status hs_dbg_ntt_time(hs_ctx* ctx, int groups, int level, int reps, int inverse, double* us);
+
 /* Raw negacyclic NTT (forward or inverse) of `nrows` rows of N residues
  * modulo prime index `prime` (host buffer, in place); for parity tests. */
 hs_status hs_dbg_ntt(hs_ctx* ctx, int prime, uint64_t* rows, size_t nrows, int inverse);

@@ -118,36 +118,37 @@ def newton_delta(delta, steps):
     return delta
 
 
-def newton_invsqrt(ctx, S, y, steps, mask=None, avg=1):
+def newton_invsqrt(ctx, S, y, steps, mask=None, avg=1, tgt=None):
     """Newton's inverse square root iteration (Appendix A, the lemma on
     computing inverse square roots) from the first guess y ~ S^(-1/2):
-    y <- 3/2 y - (S/2 y)(y y), two levels per step, S/2 being S with its
-    declared scale doubled.  The last step also applies the mask (S/2 times
-    the mask first, 3/2 y as the masked plaintext product) or, with avg > 1,
-    the averaging factor 1/avg (S / (2 avg) and 3/(2 avg) y by constant
-    products, so the integers, not only the declared scales, shrink); S has
-    levels above y, so neither costs a level of y's."""
+    y <- 3/2 y - (S/2 y)(y y), two levels per step, each step landing at
+    scale tgt exactly: S/2 by a constant product at the scale T1 that puts
+    (S/2 y)(y y) at tgt, 3/2 y by a constant product at tgt.  The last step
+    also applies the mask (S/2 and 3/2 y as masked plaintext products) or,
+    with avg > 1, the averaging factor 1/avg (in both constants); S has levels
+    above y, so S/2 costs none of y's."""
     for i in range(steps):
         lastn = i + 1 == steps
+        l = y.level
+        assert l >= 2 and S.level > l, "Newton step: levels"
+        ql, ql1 = float(ctx.q[l]), float(ctx.q[l - 1])
+        T1 = tgt * ql * ql * ql1 / (y.scale * y.scale * y.scale)
         if lastn and mask is not None:
-            ql = float(ctx.q[S.level])
-            h = ctx.rescale(ctx.mul_plain(S, mask.plaintext(ql, S.level), ql))
-            h.scale = S.scale * 2.0
-        elif lastn and avg > 1:
-            h = P.mul_const(ctx, S, 0.5 / avg, S.scale)
+            qs = float(ctx.q[S.level])
+            ps = T1 * qs / S.scale
+            h = ctx.rescale(ctx.mul_plain(S, mask.plaintext(0.5 * ps, S.level), ps))
+            h.scale = T1
         else:
-            h = S.copy()
-            h.scale = S.scale * 2.0
+            h = P.mul_const(ctx, S, 0.5 / avg if lastn else 0.5, T1)
         z1 = P.mult(ctx, h, y)
         z2 = P.mult(ctx, y, y)
         w = P.mult(ctx, z1, z2)
         if lastn and mask is not None:
-            ql = float(ctx.q[y.level])
-            ps = w.scale * ql / y.scale
-            z3 = ctx.rescale(ctx.mul_plain(y, mask.plaintext(1.5 * ps, y.level), ps))
-            z3.scale = w.scale
+            ps = tgt * ql / y.scale
+            z3 = ctx.rescale(ctx.mul_plain(y, mask.plaintext(1.5 * ps, l), ps))
+            z3.scale = tgt
         else:
-            z3 = P.mul_const(ctx, y, 1.5 / avg if lastn else 1.5, w.scale)
+            z3 = P.mul_const(ctx, y, 1.5 / avg if lastn else 1.5, tgt)
         y = ctx.sub_ct(P.drop(ctx, z3, w.level), w)
     return y
 
@@ -278,7 +279,7 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             lam = P.eval_cheb(ctx, S, pe, a, b, Delta, log_scale, None if avg else mask)
         else:
             g = P.eval_cheb(ctx, S, pinv, a, b, Delta, log_scale)
-            lam = newton_invsqrt(ctx, S, g, newton_steps, None if avg else mask, per if avg else 1)
+            lam = newton_invsqrt(ctx, S, g, newton_steps, None if avg else mask, per if avg else 1, Delta)
         if not smb_step:
             need_next = 1 + tl if j + 1 == k else 1 + 2 * tl
             if not last and bootstrap is not None and lam.level < y[0].level and lam.level - 1 - tl < need_next:

@@ -47,6 +47,8 @@ static hs_ct* wrap(hs::Context* c, const hs::Ct& ct) {
 
 #define NEED(x) HS_REQUIRE((x), hs::E_ARG, "null argument: " #x)
 
+static void check_ev(hipError_t e) { HS_REQUIRE(e == hipSuccess, hs::E_DEVICE, "hipEventCreate failed"); }
+
 extern "C" {
 
 const char* hs_version(void) { return "hs 0.1 (gfx950)"; }
@@ -657,6 +659,36 @@ hs_status hs_dbg_mul_rate(hs_ctx* ctx, double* tops) {
         NEED(tops);
         *tops = hs::k_mul_rate(ctx->c->stream);
         HS_REQUIRE(*tops > 0, hs::E_DEVICE, "multiplier probe failed");
+    });
+}
+
+hs_status hs_dbg_ntt_time(hs_ctx* ctx, int groups, int level, int reps, int inverse, double* us) {
+    return guard([&] {
+        NEED(ctx);
+        NEED(us);
+        hs::Context& c = *ctx->c;
+        HS_REQUIRE(level >= 0 && level <= c.L, hs::E_LEVEL, "level out of range");
+        HS_REQUIRE(groups >= 1 && groups <= 4096 && reps >= 1 && reps <= 1000, hs::E_ARG, "groups or reps");
+        HS_REQUIRE(!c.capturing, hs::E_STATE, "not while capturing");
+        const int rpg = level + 1;
+        const size_t w = (size_t)groups * rpg * c.N;
+        u64* d = c.alloc_words(w);
+        hs::Rows r{d, groups, rpg, (size_t)rpg * c.N, rpg, 0, c.nq};
+        hs::k_sample_uniform(c.T, r, 0x5eedull, 0x7000000000000000ull, c.stream);
+        hs::k_ntt(c.T, r, inverse != 0, c.stream);                    // warm
+        hipEvent_t e0, e1;
+        check_ev(hipEventCreate(&e0));
+        check_ev(hipEventCreate(&e1));
+        (void)hipEventRecord(e0, (hipStream_t)c.stream);
+        for (int i = 0; i < reps; i++) hs::k_ntt(c.T, r, inverse != 0, c.stream);
+        (void)hipEventRecord(e1, (hipStream_t)c.stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c.free_words(d);
+        *us = 1e3 * ms / reps;
     });
 }
 

@@ -191,30 +191,33 @@ static Ct mask_padding(Context& c, const Ct& y0, int n, int per, int L, int m) {
 
 // Inverse square root by Newton's iteration (Appendix A, the lemma on
 // computing inverse square roots): from the first guess y ~ S^(-1/2),
-// `steps` times y <- 1.5 y - (S/2 y)(y y), two levels per step; S/2 is S
-// with its declared scale doubled (no level).  The last step also applies
-// the factor `fac` to the result: the 0/1 mask (`mask` given: S/2 taken
-// times the mask first, at S's higher level, and 1.5 y as the masked
-// plaintext product) or the averaging factor 1/avg (S/(2 avg) and 1.5/avg y by
-// constant products, so the integers shrink, not only the declared scales);
-// S has levels above y, so neither costs one of y's levels.
-static Ct newton_invsqrt(Context& c, const Ct& S, const Ct& y0, int steps, const double* mask, int avg) {
+// `steps` times y <- 3/2 y - (S/2 y)(y y), two levels per step.  Every step
+// lands at scale tgt exactly, as the polynomial evaluator's results do: S/2
+// is taken by a constant product at the scale T1 that makes (S/2 y)(y y)
+// come out at tgt, and 3/2 y by a constant product at tgt (S has levels
+// above y, so S/2 costs none of y's).  The last step also applies the mask
+// (`mask` given: S/2 and 3/2 y as masked plaintext products) or the
+// averaging factor 1/avg (in both constants).
+static Ct newton_invsqrt(Context& c, const Ct& S, const Ct& y0, int steps, const double* mask, int avg,
+                         double tgt) {
     Ct y = ct_copy(c, y0);
     for (int i = 0; i < steps; i++) {
         const bool lastn = i + 1 == steps;
+        const int l = y.level;
+        HS_REQUIRE(l >= 2 && S.level > l, E_LEVEL, "Newton step: levels");
+        const double ql = (double)c.primes[l], ql1 = (double)c.primes[l - 1];
+        const double T1 = tgt * ql * ql * ql1 / (y.scale * y.scale * y.scale);
         Ct h;
         if (lastn && mask) {
-            const double ql = (double)c.primes[S.level];
+            const double qs = (double)c.primes[S.level];
+            const double ps = T1 * qs / S.scale;
             bool owned;
-            u64* pt = mask_plaintext(c, mask, S.level, ql, &owned);
-            h = op_mul_plain(c, S, pt, ql, true);
+            u64* pt = mask_plaintext(c, mask, S.level, 0.5 * ps, &owned);
+            h = op_mul_plain(c, S, pt, ps, true);
             if (owned) c.free_words(pt);
-            h.scale = S.scale * 2.0;
-        } else if (lastn && avg > 1) {
-            h = op_mul_const(c, S, 0.5 / avg, S.scale);
+            h.scale = T1;
         } else {
-            h = ct_copy(c, S);
-            h.scale = S.scale * 2.0;
+            h = op_mul_const(c, S, lastn ? 0.5 / avg : 0.5, T1);
         }
         Ct z1 = op_mult(c, h, y);
         ct_free(c, h);
@@ -224,16 +227,14 @@ static Ct newton_invsqrt(Context& c, const Ct& S, const Ct& y0, int steps, const
         ct_free(c, z2);
         Ct z3;
         if (lastn && mask) {
-            // 1.5 mask y at w's scale: plaintext scale ps with y.scale ps / q_l = w.scale
-            const double ql = (double)c.primes[y.level];
-            const double ps = w.scale * ql / y.scale;
+            const double ps = tgt * ql / y.scale;
             bool owned;
-            u64* pt = mask_plaintext(c, mask, y.level, 1.5 * ps, &owned);
+            u64* pt = mask_plaintext(c, mask, l, 1.5 * ps, &owned);
             z3 = op_mul_plain(c, y, pt, ps, true);
             if (owned) c.free_words(pt);
-            z3.scale = w.scale;
+            z3.scale = tgt;
         } else {
-            z3 = op_mul_const(c, y, lastn ? 1.5 / avg : 1.5, w.scale);
+            z3 = op_mul_const(c, y, lastn ? 1.5 / avg : 1.5, tgt);
         }
         Ct z3d = ct_drop(c, z3, w.level);
         ct_free(c, z3);
@@ -434,7 +435,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             lam = eval_cheb(c, S, pe, Delta, avg ? nullptr : mask);
         } else {
             Ct g = eval_cheb(c, S, pinv, Delta);
-            lam = newton_invsqrt(c, S, g, nsteps, avg ? nullptr : mask, avg ? per : 1);
+            lam = newton_invsqrt(c, S, g, nsteps, avg ? nullptr : mask, avg ? per : 1, Delta);
             ct_free(c, g);
         }
         ct_free(c, S);

@@ -116,6 +116,7 @@ def lib():
         "hs_mul_monomial": [_vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_dbg_ntt": [_vp, S, _u64p, ctypes.c_size_t, S],
         "hs_dbg_mul_rate": [_vp, ctypes.POINTER(ctypes.c_double)],
+        "hs_dbg_ntt_time": [_vp, S, S, S, S, ctypes.POINTER(ctypes.c_double)],
         "hs_dbg_ring": [_vp, S, S, S, _u64p, ctypes.c_size_t, _u64p, ctypes.c_size_t,
                         ctypes.POINTER(ctypes.c_size_t)],
         "hs_ctx_memory": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
@@ -611,6 +612,13 @@ class Context:
         r = ctypes.c_size_t()
         _check(lib().hs_ctx_trim(self.h, ctypes.byref(r)))
         return r.value
+
+    def ntt_time(self, groups, level, reps=20, inverse=False):
+        """hs_dbg_ntt_time: average microseconds per NTT launch over `groups`
+        groups of level+1 rows."""
+        us = ctypes.c_double()
+        _check(lib().hs_dbg_ntt_time(self.h, groups, level, reps, 1 if inverse else 0, ctypes.byref(us)))
+        return us.value
 
     def mul_rate(self):
         """Measured v_mad_u64_u32 throughput of the device (10^12 ops/s)."""

@@ -35,7 +35,13 @@ PRESETS = {
     ),
     # N = 2^16, scale 2^40, sparse ternary secret of weight 192, digits of 8
     # primes (dnum = 4, P 2^60 above the largest digit), twelve user levels
-    # above q0, full-slot bootstrapping.
+    # above q0, full-slot bootstrapping.  K = 30 bounds the overflow I of
+    # ModRaise (a sum of 193 centred uniforms, standard deviation 4.0):
+    # |I| >= 31 has probability below 2^-30 per bootstrap over 2^16
+    # coefficients.  The modular reduction approximates exp(2 pi i (K+1) u /
+    # 2^3) with degree 63 and squares three times (the same 11 levels as
+    # degree 31 and four squarings, whose approximation error at this K
+    # would cost about 5 bits of bootstrapping precision).
     "fgb16": dict(
         logN=16,
         q_bits=[53] + [40] * 12 + [40] * 3 + [60] * 11 + [60] * 3,
@@ -45,7 +51,7 @@ PRESETS = {
         log_scale=40,
         user_top=12,
         boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
-                  K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
+                  K=30, double_angle=3, cos_degree=63, log_boot_scale=60),
     ),
     # Small ring with the same bootstrapping structure, for fast tests.
     "boot10": dict(
@@ -57,7 +63,7 @@ PRESETS = {
         log_scale=40,
         user_top=4,
         boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
-                  K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
+                  K=30, double_angle=3, cos_degree=63, log_boot_scale=60),
     ),
     # the same bootstrapping ring with 10 user levels: room for a whole
     # Softmax schedule (with bootstraps) at test size
@@ -70,7 +76,7 @@ PRESETS = {
         log_scale=40,
         user_top=10,
         boot=dict(stc_levels=3, evalmod_levels=11, cts_levels=3,
-                  K=24, double_angle=4, cos_degree=31, log_boot_scale=60),
+                  K=30, double_angle=3, cos_degree=63, log_boot_scale=60),
     ),
 }
 

@@ -72,7 +72,7 @@ def test_stages_match_the_oracle(pair, level):
     assert np.max(np.abs(g.decrypt(gy) - z)) < 2.0 ** -22
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, "newton"])
 def test_softmax_with_bootstraps_matches_the_oracle(variant):
     from paper_2410_11184_amd import hs
     from oracle import ckks, schedule, softmax as S
@@ -83,18 +83,23 @@ def test_softmax_with_bootstraps_matches_the_oracle(variant):
     g.keygen(SEED + 1)
     o.keygen(SEED + 1)
     bs = Bootstrapper(o, p["boot"], p["user_top"], p["log_scale"])
-    n, M, m = 16, 8.0, 1
+    # "newton": Algorithm SM at n = 32, M = 32, degree-15 first guesses and one
+    # Newton step per inverse square root, bootstraps between
+    kw = dict(inv_degrees=(15, 15, 15), newton_steps=1) if variant == "newton" else {}
+    n, M, m = (32, 32.0, 1) if variant == "newton" else (16, 8.0, 1)
+    seed_off = 2 if variant == "newton" else variant
+    variant = 0 if variant == "newton" else variant
     L = m * o.slots // n
-    x = synthetic.logits_uniform(L, n, M, seed=61 + variant)
+    x = synthetic.logits_uniform(L, n, M, seed=61 + seed_off)
     packed = S.pack(x, m, o.slots)
     scale = o.delta * 2.0 / M
     gx = [g.encrypt(packed[0], p["user_top"], scale, 90)]
     ox = [o.encode_encrypt(packed[0], scale, p["user_top"], 90)]
-    gy = g.softmax(gx, n, M, variant=variant)
+    gy = g.softmax(gx, n, M, variant=variant, **kw)
     gst = g.softmax_stats()
     st = {}
     oy = schedule.softmax(o, ox, n, M, variant=variant,
-                          bootstrap=lambda c, bound, mask_L: bs.bootstrap(c, bound, mask_L), stats=st)
+                          bootstrap=lambda c, bound, mask_L: bs.bootstrap(c, bound, mask_L), stats=st, **kw)
     assert gst["bootstraps"] == st["bootstraps"] > 0, (gst, st)
     _close(g, o, gy[0], oy[0], "softmax output", tol=2.0 ** -24)
     y = S.unpack(np.stack([g.decrypt(gy[0]).real]), n)

@@ -102,21 +102,23 @@ def test_serving_at_full_size():
     assert worst[4096] >= 12.0 and worst[32768] >= 7.0, worst
 
 
-@pytest.mark.parametrize("case", [(200, 128.0, 2), (16, 32.0, 3)], ids=["padded-n200", "cube-n16"])
+@pytest.mark.parametrize("case", [(200, 128.0, 2, 0), (16, 32.0, 3, 0), (256, 128.0, 2, 1)],
+                         ids=["padded-n200", "cube-n16", "newton-n256"])
 def test_variants_at_full_size(ctx, case):
-    # a dimension that is not a power of two (200, packed as 256) and
+    # a dimension that is not a power of two (200, packed as 256),
     # normalize-and-cube (n = 16, where the appendix expects t-th powers to
-    # pay: their later intervals [~n^-(t-1), 1] widen with n), both with
-    # Algorithm SM and bootstrapping on the benchmark's ring: one ciphertext
-    # each, precision against FP64
+    # pay: their later intervals [~n^-(t-1), 1] widen with n) and one Newton
+    # step per inverse square root (n = 256), all with Algorithm SM and
+    # bootstrapping on the benchmark's ring: one ciphertext each, precision
+    # against FP64
     from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
-    n, M, t = case
+    n, M, t, nw = case
     n2 = 1 << (n - 1).bit_length()
     L = ctx.slots // n2
     x = synthetic.logits_uniform(L, n, M, seed=1200 + n)
     cts = encrypt_logits(ctx, x, M, seed=5200 + n)
     print("variant: n=%d (packed as %d), M=%g, power %d" % (n, n2, M, t), flush=True)
-    y = decrypt_outputs(ctx, ctx.softmax(cts, n, M, variant=0, power=t), n)
+    y = decrypt_outputs(ctx, ctx.softmax(cts, n, M, variant=0, power=t, newton_steps=nw), n)
     bits = S.precision_bits(S.softmax(x), y)
     print("n=%d power %d: %s, stats %s" % (n, t, bits, ctx.softmax_stats()))
     assert y.shape == (L, n)
