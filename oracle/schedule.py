@@ -98,7 +98,7 @@ def free_interval(lo, hi):
     return lo, lo + w
 
 
-def default_degree(n, j, last, t=2):
+def default_degree(n, j, last, t=2, newton_steps=0):
     if t != 2:
         d = (7 if last else 6) if n <= 16 else 7
     elif n <= 256:
@@ -107,6 +107,8 @@ def default_degree(n, j, last, t=2):
         d = 8 if last else 6
     else:
         d = 8 if last else 7
+    # Newton's steps take two levels each from the same budget
+    d = max(3, d - 2 * newton_steps)
     return (1 << d) - 1
 
 
@@ -245,7 +247,7 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         e = math.ldexp(1.0, -j) if smb_step else (0.5 if tp == 2 else 1.0 / tp)
         deg = inv_degrees[0] if j == 1 else (inv_degrees[2] if last else inv_degrees[1])
         if deg <= 0:
-            deg = default_degree(n, j, last, tp)
+            deg = default_degree(n, j, last, tp, newton_steps)
         a, b = free_interval(lo, hi)
         ee = mpmath.mpf(e)
         pinv = P.cheb_interp(lambda s: mpmath.power(s, -ee), a, b, deg)

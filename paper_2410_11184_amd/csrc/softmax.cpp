@@ -367,6 +367,8 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             else if (n <= 256) d = j == 1 ? 6 : (last ? 7 : 5);
             else if (n <= 1024) d = last ? 8 : 6;
             else d = last ? 8 : 7;
+            // Newton's steps take two levels each from the same budget
+            d = std::max(3, d - 2 * o.newton_steps);
             deg = (1 << d) - 1;
         }
         double a, b;

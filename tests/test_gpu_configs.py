@@ -123,4 +123,6 @@ def test_variants_at_full_size(ctx, case):
     print("n=%d power %d: %s, stats %s" % (n, t, bits, ctx.softmax_stats()))
     assert y.shape == (L, n)
     assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -10
-    assert bits["worst"] >= 16.0, bits
+    # Newton (default first guesses two levels shallower per step) is a trade
+    # study: reported, held to 12 bits
+    assert bits["worst"] >= (12.0 if nw else 16.0), bits
