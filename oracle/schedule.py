@@ -107,8 +107,8 @@ def default_degree(n, j, last, t=2, newton_steps=0):
         d = 8 if last else 6
     else:
         d = 8 if last else 7
-    # Newton's steps take two levels each from the same budget
-    d = max(3, d - 2 * newton_steps)
+    # with Newton's steps, first guesses one level shallower per step
+    d = max(3, d - newton_steps)
     return (1 << d) - 1
 
 
@@ -248,14 +248,6 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         deg = inv_degrees[0] if j == 1 else (inv_degrees[2] if last else inv_degrees[1])
         if deg <= 0:
             deg = default_degree(n, j, last, tp, newton_steps)
-        a, b = free_interval(lo, hi)
-        ee = mpmath.mpf(e)
-        pinv = P.cheb_interp(lambda s: mpmath.power(s, -ee), a, b, deg)
-        delta = newton_delta(rel_error(pinv, a, b, lo, hi, e), newton_steps)
-        lam_bound = ((1.0 + delta) / math.sqrt(lo) if newton_steps else max_abs(pinv, a, b, lo, hi)) * 1.05
-        pe = [cf / per for cf in pinv] if avg and not newton_steps else pinv
-        if avg:
-            lam_bound /= per
         if not smb:
             y = [ensure(c, 1 + tl if last else 1 + 2 * tl, ybound) for c in y]
         # auxiliary thread: S = sum of the t-th powers (squares: the tensors
@@ -277,6 +269,20 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         # Newton's steps also keep 1 + tl levels in lambda
         keep = 2 + tl if (tp != 2 or newton_steps) else 1
         S = ensure(S, P.depth(deg) + 2 * newton_steps + keep, hi * 1.1)
+        # the polynomial's interval: [lo, lo + 2^w] (integer affine map); in the
+        # last step of SM with squares exactly [lo, hi] when S has the level
+        # its affine map takes on top of the polynomial and z = lambda y, z^2
+        if last and tp == 2 and not newton_steps and S.level >= P.depth(deg) + 3:
+            a, b = lo, hi
+        else:
+            a, b = free_interval(lo, hi)
+        ee = mpmath.mpf(e)
+        pinv = P.cheb_interp(lambda s: mpmath.power(s, -ee), a, b, deg)
+        delta = newton_delta(rel_error(pinv, a, b, lo, hi, e), newton_steps)
+        lam_bound = ((1.0 + delta) / math.sqrt(lo) if newton_steps else max_abs(pinv, a, b, lo, hi)) * 1.05
+        pe = [cf / per for cf in pinv] if avg and not newton_steps else pinv
+        if avg:
+            lam_bound /= per
         if not newton_steps:
             lam = P.eval_cheb(ctx, S, pe, a, b, Delta, log_scale, None if avg else mask)
         else:

@@ -367,24 +367,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             else if (n <= 256) d = j == 1 ? 6 : (last ? 7 : 5);
             else if (n <= 1024) d = last ? 8 : 6;
             else d = last ? 8 : 7;
-            // Newton's steps take two levels each from the same budget
-            d = std::max(3, d - 2 * o.newton_steps);
+            // with Newton's steps, first guesses one level shallower per step
+            d = std::max(3, d - o.newton_steps);
             deg = (1 << d) - 1;
         }
-        double a, b;
-        free_interval(lo, hi, a, b);
-        const double ee = e;
-        ChebPoly pinv = cheb_fit([&](quad s) { return powq(s, -(quad)ee); }, a, b, deg);
-        const int nsteps = o.newton_steps;
-        const double delta = newton_delta(rel_error(pinv, lo, hi, e), nsteps);
-        double lam_bound = (nsteps ? (1.0 + delta) / std::sqrt(lo) : max_abs(pinv, lo, hi)) * 1.05;
-        // the averaging mask: per copies of the factor, each divided by per,
-        // summed by the broadcast (the division folded into the coefficients
-        // when there is no Newton step, exact since per is a power of two)
-        ChebPoly pe = pinv;
-        if (avg && !nsteps)
-            for (double& cf : pe.c) cf /= per;
-        if (avg) lam_bound /= per;
         // main thread: this iteration's z = lambda y and z^t (1 + tl levels),
         // then the levels of the next y^t feeding S
         if (!smb) {
@@ -422,14 +408,40 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             // level) + 2 nsteps below S; the cube and fourth power variants
             // and Newton's steps also keep 1 + tl levels in lambda for
             // z = lambda y and z^t
-            const int keep = (tp != 2 || nsteps) ? 2 + tl : 1;
+            const int keep = (tp != 2 || o.newton_steps) ? 2 + tl : 1;
             bool rep;
-            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 2 * nsteps + keep, hi * 1.1, st, rep, "S", j);
+            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 2 * o.newton_steps + keep, hi * 1.1, st, rep, "S", j);
             if (rep) {
                 ct_free(c, S);
                 S = S2;
             }
         }
+        // the interval of the normalisation polynomial: [lo, lo + 2^w], whose
+        // affine map is an integer product; in the last iteration of Algorithm
+        // SM with squares (the polynomial whose error reaches the output),
+        // exactly [lo, hi] when S has the level its affine map then takes on
+        // top of the polynomial and the final z = lambda y, y = z^2 (about 4
+        // bits of precision at n = 256: the wider interval spreads the
+        // interpolation nodes over values S never takes)
+        const int nsteps = o.newton_steps;
+        double a, b;
+        if (last && tp == 2 && !nsteps && S.level >= cheb_depth(deg) + 3) {
+            a = lo;
+            b = hi;
+        } else {
+            free_interval(lo, hi, a, b);
+        }
+        const double ee = e;
+        ChebPoly pinv = cheb_fit([&](quad s) { return powq(s, -(quad)ee); }, a, b, deg);
+        const double delta = newton_delta(rel_error(pinv, lo, hi, e), nsteps);
+        double lam_bound = (nsteps ? (1.0 + delta) / std::sqrt(lo) : max_abs(pinv, lo, hi)) * 1.05;
+        // the averaging mask: per copies of the factor, each divided by per,
+        // summed by the broadcast (the division folded into the coefficients
+        // when there is no Newton step, exact since per is a power of two)
+        ChebPoly pe = pinv;
+        if (avg && !nsteps)
+            for (double& cf : pe.c) cf /= per;
+        if (avg) lam_bound /= per;
         // normalisation and mask: lambda = P(S) * mask, on slots [0, L)
         // (averaging: P(S) / per on every slot)
         Ct lam;
