@@ -595,8 +595,6 @@ def main():
                  row("SM, 1 ciphertext", cp1, p["slots"] // n, xp1, variant=0),
                  row("SM, 1 ciphertext, Newton x1 from degrees 31/31/63", cp1, p["slots"] // n, xp1, variant=0,
                      newton_steps=1, inv_degrees=(31, 31, 63)),
-                 row("SM, 1 ciphertext, Newton x2 from degrees 15/15/15", cp1, p["slots"] // n, xp1, variant=0,
-                     newton_steps=2, inv_degrees=(15, 15, 15)),
                  row("SM, 1 ciphertext, averaging mask", cp1, p["slots"] // n, xp1, variant=0, mask_mode=1)]
 
     plain = None
