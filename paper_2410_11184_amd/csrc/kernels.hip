@@ -437,12 +437,10 @@ __device__ __forceinline__ u64 reduce4q(u64 x, u64 q) {
     return x >= q ? x - q : x;
 }
 
-// Tiles of C columns (pass 1) or C chunks of 256 (pass 2) per workgroup of
-// 16 C threads: C = 16, or 8 for launches too small to fill the GPU (a
-// single ciphertext's rows), which doubles their workgroups; every element
-// sees the same butterflies either way.  LDS layouts (u64 units):
-// pass 1 element (hi, lo, column c) at hi*17C + lo*C + c,
+// LDS tile layouts (u64 units), conflict-free for both access patterns:
+// pass 1 element (hi, lo, column c) at hi*272 + lo*16 + c,
 // pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
+#define NTT16_LDS (16 * 272)
 
 // centred lift of x (mod q_s) to the prime of P: x if x <= (q_s - 1) / 2,
 // else x - q_s, reduced
@@ -452,18 +450,16 @@ __device__ __forceinline__ u64 lift_centred(u64 x, u64 qs, const PrimeInfo& P) {
     return mag ? P.q - mag : 0;
 }
 
-template <int C>
-__global__ void __launch_bounds__(16 * C) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
-                                                         NttSkip sk, int g0, NttLift lf) {
-    constexpr int S1 = 17 * C;
-    __shared__ u64 sm[16 * S1];
+__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+                                                       NttSkip sk, int g0, NttLift lf) {
+    __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row(x, blockIdx.y, order, sk, g0);
     if (row < 0) return;   // whole workgroup
-    u64* p = row_ptr(x, row, 65536) + blockIdx.x * C;
-    const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * C;
+    u64* p = row_ptr(x, row, 65536) + blockIdx.x * 16;
+    const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * 16;
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
-    const int t = threadIdx.x, c = t % C, hl = t / C;
+    const int t = threadIdx.x, c = t & 15, hl = t >> 4;
     u64 E[16];
     if (!inverse) {
         const ulonglong2* tw = (const ulonglong2*)T.tw2 + (size_t)pi * 65536;
@@ -471,7 +467,7 @@ __global__ void __launch_bounds__(16 * C) ntt16_p1_kernel(DevTables T, Rows x, R
         if (lf.base) {
             const PrimeInfo P = T.prime[pi];
             const u64 qs = T.prime[lf.src_prime].q;
-            const u64* pl = lf.base + (size_t)(row / x.rpg) * lf.gs + blockIdx.x * C;
+            const u64* pl = lf.base + (size_t)(row / x.rpg) * lf.gs + blockIdx.x * 16;
 #pragma unroll
             for (int hi = 0; hi < 16; hi++) E[hi] = lift_centred(pl[(size_t)(hi * 16 + hl) * 256 + c], qs, P);
         } else {
@@ -480,11 +476,11 @@ __global__ void __launch_bounds__(16 * C) ntt16_p1_kernel(DevTables T, Rows x, R
         }
         fwd16(E, tw, 1, q);
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) sm[hi * S1 + hl * C + c] = E[hi];
+        for (int hi = 0; hi < 16; hi++) sm[hi * 272 + hl * 16 + c] = E[hi];
         __syncthreads();
         // thread (hi = hl, c): lo = 0..15, stages 4..7
 #pragma unroll
-        for (int lo = 0; lo < 16; lo++) E[lo] = sm[hl * S1 + lo * C + c];
+        for (int lo = 0; lo < 16; lo++) E[lo] = sm[hl * 272 + lo * 16 + c];
         fwd16(E, tw, 16 + hl, q);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) p[(size_t)(hl * 16 + lo) * 256 + c] = E[lo];
@@ -495,11 +491,11 @@ __global__ void __launch_bounds__(16 * C) ntt16_p1_kernel(DevTables T, Rows x, R
         for (int lo = 0; lo < 16; lo++) E[lo] = ps[(size_t)(hl * 16 + lo) * 256 + c];
         inv16(E, tw, 16 + hl, q);
 #pragma unroll
-        for (int lo = 0; lo < 16; lo++) sm[hl * S1 + lo * C + c] = E[lo];
+        for (int lo = 0; lo < 16; lo++) sm[hl * 272 + lo * 16 + c] = E[lo];
         __syncthreads();
         // thread (lo = hl, c): hi = 0..15, stages 3..0, then N^-1
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) E[hi] = sm[hi * S1 + hl * C + c];
+        for (int hi = 0; hi < 16; hi++) E[hi] = sm[hi * 272 + hl * 16 + c];
         inv16(E, tw, 1, q);
         const u64 ni = T.ninv[2 * pi], nis = T.ninv[2 * pi + 1];
 #pragma unroll
@@ -507,18 +503,18 @@ __global__ void __launch_bounds__(16 * C) ntt16_p1_kernel(DevTables T, Rows x, R
     }
 }
 
-// four waves per SIMD: the LDS tile (35 KB per 256-thread workgroup) allows
-// four workgroups per CU, and 128 VGPRs (no spills) lets the registers follow
-template <bool EPI, int C>
-__global__ void __launch_bounds__(16 * C) __attribute__((amdgpu_waves_per_eu(4, 8))) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+// four waves per SIMD: the LDS tile (35 KB per workgroup) allows four
+// workgroups per CU, and 128 VGPRs (no spills) lets the registers follow
+template <bool EPI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
                                                        NttEpilogue Ep, NttSkip sk) {
-    __shared__ u64 sm[C * 272];
+    __shared__ u64 sm[NTT16_LDS];
     const int row = ntt_row(x, blockIdx.y, order, sk, Ep.g0);
     if (row < 0) return;   // whole workgroup
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
     const int t = threadIdx.x, w = t >> 4, l = t & 15;
-    const u32 R = blockIdx.x * C + w;              // chunk index
+    const u32 R = blockIdx.x * 16 + w;             // chunk index
     u64* p = row_ptr(x, row, 65536) + (size_t)R * 256;
     const u64* ps = row_ptr(src, row, 65536) + (size_t)R * 256;
     const ulonglong2* tw = (const ulonglong2*)(inverse ? T.itw2 : T.tw2) + (size_t)pi * 65536;
@@ -604,33 +600,16 @@ static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, boo
             lf = *lift;
             lf.base = lift->base + (size_t)g0 * lift->gs;
         }
-        // below ~2048 workgroups of 256 threads the GPU is under-filled:
-        // tiles of 8 give twice the workgroups
-        const int rows = xs.ngroups * vrows;
-        if (rows * 16 >= 2048) {
-            const dim3 g(16, rows);
-            if (!inverse) {
-                hipLaunchKernelGGL(ntt16_p1_kernel<16>, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0, lf);
-                if (epi)
-                    hipLaunchKernelGGL((ntt16_p2_kernel<true, 16>), g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
-                else
-                    hipLaunchKernelGGL((ntt16_p2_kernel<false, 16>), g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
-            } else {
-                hipLaunchKernelGGL((ntt16_p2_kernel<false, 16>), g, dim3(256), 0, st, T, xs, ss, 1, order, e, sk);
-                hipLaunchKernelGGL(ntt16_p1_kernel<16>, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
-            }
+        const dim3 g(16, xs.ngroups * vrows);
+        if (!inverse) {
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0, lf);
+            if (epi)
+                hipLaunchKernelGGL(ntt16_p2_kernel<true>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
+            else
+                hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
         } else {
-            const dim3 g(32, rows);
-            if (!inverse) {
-                hipLaunchKernelGGL(ntt16_p1_kernel<8>, g, dim3(128), 0, st, T, xs, ss, 0, order, sk, g0, lf);
-                if (epi)
-                    hipLaunchKernelGGL((ntt16_p2_kernel<true, 8>), g, dim3(128), 0, st, T, xs, xs, 0, order, e, sk);
-                else
-                    hipLaunchKernelGGL((ntt16_p2_kernel<false, 8>), g, dim3(128), 0, st, T, xs, xs, 0, order, e, sk);
-            } else {
-                hipLaunchKernelGGL((ntt16_p2_kernel<false, 8>), g, dim3(128), 0, st, T, xs, ss, 1, order, e, sk);
-                hipLaunchKernelGGL(ntt16_p1_kernel<8>, g, dim3(128), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
-            }
+            hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, ss, 1, order, e, sk);
+            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
         }
     }
 }
