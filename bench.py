@@ -203,6 +203,13 @@ def oracle_toy_runs(procs):
                            "worst_bits": min(r["worst_bits"] for r in runs)}}
 
 
+def ring_desc(p):
+    """The ring as the bench record names it: degree, log2(QP), dnum."""
+    logqp = sum(p["q_bits"]) + sum(p["p_bits"])
+    dnum = -(-len(p["q_bits"]) // p["digit"])
+    return "N=2^%d RNS-CKKS (logQP %d, dnum %d, h %d)" % (p["logN"], logqp, dnum, p["hamming"])
+
+
 def calibrate_copy(nbytes=1 << 30, reps=3):
     """A plain copy kernel of known size: each repetition reads and writes
     exactly `nbytes`; the counters it produces give the scale of FETCH_SIZE
@@ -279,7 +286,7 @@ def run_uneven(args):
            "value": value if gated else 0.0, "unit": "Softmax calls/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-           "config": {"workload": "N=2^16 RNS-CKKS; 32 jobs x 16 ciphertexts x 4096 Softmax of dim 128 "
+           "config": {"workload": ring_desc(p) + "; 32 jobs x 16 ciphertexts x 4096 Softmax of dim 128 "
                                   "(N(0,4^2) clipped to [-64,0]) in lockstep + 1 Softmax of dim 32768 (U[-256,0])",
                       "global_batch": calls, "parallelism": "single-gpu"},
            "groups": prec,
@@ -659,7 +666,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "N=2^16 RNS-CKKS, m=64 ciphertexts, 8192 Softmax of dim 256, logits U[-128,0], "
+        "config": {"workload": ring_desc(p) + ", m=64 ciphertexts, 8192 Softmax of dim 256, logits U[-128,0], "
                                "SM version B, k=%d, aux bootstraps per job=%d, %s schedule" %
                                (stats["k"], stats["bootstraps"], "HIP-graph" if graph else "eager"),
                    "global_batch": L, "seq_len": n, "parallelism": "single-gpu"},
