@@ -114,6 +114,18 @@ typedef void (*hs_free_fn)(void* ptr, size_t bytes, void* user);
  * during creation. */
 hs_status hs_ctx_create_ex(const hs_params* p, int device, void* hip_stream, hs_alloc_fn alloc_fn,
                            hs_free_fn free_fn, void* user, hs_ctx** out);
+/* A context on another HIP stream (hip_stream) that shares src's keys and
+ * device tables instead of holding its own copies (the serving loop's
+ * workers: one key set in HBM for all of them).  Same parameters, device and
+ * allocator callbacks as src; it computes the same words as src.  Keys it
+ * needs that src lacks are generated into its own memory.  src must have its
+ * keys (HS_E_STATE) and must not itself be a clone (HS_E_ARG).  Destroying
+ * src while clones live releases the handle at once and src's device memory
+ * when its last clone is destroyed.  hs_keygen is refused (HS_E_STATE) on a
+ * clone and on a context with live clones.  Each context is still
+ * single-stream and not thread-safe; a context and its clones may be used
+ * from different threads at once (they share only read-only key memory). */
+hs_status hs_ctx_clone(hs_ctx* src, void* hip_stream, hs_ctx** out);
 /* hs_ctx_create_ex without callbacks (hipMalloc / hipFree). */
 hs_status hs_ctx_create(const hs_params* p, int device, void* hip_stream, hs_ctx** out);
 void hs_ctx_destroy(hs_ctx* ctx);

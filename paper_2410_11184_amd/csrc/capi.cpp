@@ -99,13 +99,29 @@ hs_status hs_ctx_create_ex(const hs_params* p, int device, void* stream, hs_allo
     });
 }
 
+hs_status hs_ctx_clone(hs_ctx* src, void* stream, hs_ctx** out) {
+    if (out) *out = nullptr;
+    return guard([&] {
+        NEED(src);
+        NEED(out);
+        hs_ctx* h = new hs_ctx;
+        try {
+            h->c = new hs::Context(*src->c, stream);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
 hs_status hs_ctx_create(const hs_params* p, int device, void* stream, hs_ctx** out) {
     return hs_ctx_create_ex(p, device, stream, nullptr, nullptr, nullptr, out);
 }
 
 void hs_ctx_destroy(hs_ctx* ctx) {
     if (!ctx) return;
-    delete ctx->c;
+    hs::destroy_context(ctx->c);
     delete ctx;
 }
 

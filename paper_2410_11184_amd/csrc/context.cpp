@@ -357,6 +357,63 @@ Context::Context(const Params& p, int dev, void* st, const DevAllocator* alloc) 
     }
 }
 
+Context::Context(Context& p, void* st) : prm(p.prm), device(p.device) {
+    HS_REQUIRE(p.have_keys, E_STATE, "clone: the parent context has no keys yet");
+    HS_REQUIRE(!p.parent_ctx, E_ARG, "clone: the parent is itself a clone");
+    check_hip(hipSetDevice(device), "hipSetDevice");
+    da = p.da;
+    da.stream = st;
+    pool.set_source(&da);
+    stream = st;
+    N = p.N;
+    logN = p.logN;
+    primes = p.primes;
+    nq = p.nq;
+    np = p.np;
+    L = p.L;
+    dnum = p.dnum;
+    psi = p.psi;
+    pinfo = p.pinfo;
+    for (int i = 0; i < kMaxRows; i++) P_mod[i] = p.P_mod[i];
+    T = p.T;
+    T.prof = prof_create();
+    tw_cos = p.tw_cos;
+    tw_sin = p.tw_sin;
+    cdt = p.cdt;
+    ncdt = p.ncdt;
+    cdt_host = p.cdt_host;
+    have_keys = true;
+    key_seed = p.key_seed;
+    s_coeff = p.s_coeff;
+    s_ntt = p.s_ntt;
+    pk = p.pk;
+    for (auto& kv : p.keys) {
+        keys[kv.first] = kv.second;
+        borrowed_keys.push_back(kv.first);
+    }
+    std::lock_guard<std::mutex> g(clone_mutex());
+    HS_REQUIRE(!p.destroy_pending, E_STATE, "clone: the parent context has been destroyed");
+    parent_ctx = &p;
+    p.live_clones++;
+}
+
+std::mutex& clone_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+void destroy_context(Context* c) {
+    if (!c) return;
+    {
+        std::lock_guard<std::mutex> g(clone_mutex());
+        if (c->live_clones > 0) {
+            c->destroy_pending = true;
+            return;
+        }
+    }
+    delete c;
+}
+
 void Context::init() {
     const Params& p = prm;
     const int dev = device;
@@ -524,11 +581,25 @@ void Context::release() {
     boot_release(this);
     prof_destroy(T.prof);
     T.prof = nullptr;
-    for (auto& kv : keys) pool.free(kv.second);
+    for (auto& kv : keys)
+        if (std::find(borrowed_keys.begin(), borrowed_keys.end(), kv.first) == borrowed_keys.end())
+            pool.free(kv.second);
     keys.clear();
-    if (s_ntt) pool.free(s_ntt);
-    if (pk) pool.free(pk);
+    borrowed_keys.clear();
+    if (!parent_ctx) {
+        if (s_ntt) pool.free(s_ntt);
+        if (pk) pool.free(pk);
+    }
     s_ntt = pk = nullptr;
+    if (parent_ctx) {
+        Context* orphan = nullptr;
+        {
+            std::lock_guard<std::mutex> g(clone_mutex());
+            if (--parent_ctx->live_clones == 0 && parent_ctx->destroy_pending) orphan = parent_ctx;
+        }
+        parent_ctx = nullptr;
+        delete orphan;   // its owner destroyed it while this clone lived
+    }
     pool.release_all();
     for (void* p : owned) raw_free(p);
     owned.clear();
@@ -889,6 +960,8 @@ static u64* make_switch_key(Context& c, int key_id, const u64* s_target) {
 }
 
 void keygen(Context& c, u64 seed) {
+    HS_REQUIRE(!c.parent_ctx, E_STATE, "keygen: a clone uses its parent's keys");
+    HS_REQUIRE(c.live_clones == 0, E_STATE, "keygen: contexts cloned from this one still use its keys");
     ContextArena arena(c);
     const int nt = c.nq + c.np;
     const size_t rows_words = (size_t)nt * c.N;

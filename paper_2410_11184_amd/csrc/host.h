@@ -4,6 +4,7 @@
 #pragma once
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <memory>
 #include <stdexcept>
@@ -207,6 +208,16 @@ struct Context {
     }
 
     Context(const Params& p, int device, void* stream, const DevAllocator* alloc = nullptr);
+    // A context on another stream that reads the key material and device
+    // tables of `parent` (borrowed, never freed here); it builds its own
+    // conversion tables, permutations, bootstrap plaintexts and any key it
+    // adds (the same words as the parent's: the same seed).  The parent must
+    // outlive it; key generation is refused on both while it lives.
+    Context(Context& parent, void* stream);
+    Context* parent_ctx = nullptr;
+    int live_clones = 0;             // guarded by clone_mutex()
+    bool destroy_pending = false;    // destroyed by its owner while clones lived
+    std::vector<int> borrowed_keys;  // key ids whose device memory belongs to the parent
     ~Context();
     void release();   // returns every device block (destructor; failed construction)
     void init();      // the constructor's work
@@ -249,6 +260,12 @@ struct Context {
 
 // Key material lives as long as the context: while in scope, allocations come
 // from the context's own arena even when a captured schedule's arena is active.
+// Bookkeeping of clones (live_clones, destroy_pending) across threads.
+std::mutex& clone_mutex();
+// Delete a context, or only mark it when clones still read its keys: then
+// the last clone's release deletes it.
+void destroy_context(Context* c);
+
 struct ContextArena {
     Context& c;
     Pool* prev;

@@ -78,6 +78,7 @@ def lib():
     sig = {
         "hs_ctx_create": [ctypes.POINTER(hs_params), S, _vp, ctypes.POINTER(_vp)],
         "hs_ctx_create_ex": [ctypes.POINTER(hs_params), S, _vp, _ALLOC_FN, _FREE_FN, _vp, ctypes.POINTER(_vp)],
+        "hs_ctx_clone": [_vp, _vp, ctypes.POINTER(_vp)],
         "hs_ctx_get_info": [_vp, ctypes.POINTER(hs_ctx_info)],
         "hs_ctx_primes": [_vp, _u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "hs_sync": [_vp],
@@ -381,6 +382,16 @@ class Context:
         self.user_top = info.user_top
         self.dnum = info.dnum
         self.delta = float(2 ** params["log_scale"])
+
+    def clone(self, stream=None):
+        """hs_ctx_clone: a context on `stream` sharing this one's keys."""
+        c = Context.__new__(Context)
+        h = _vp()
+        _check(lib().hs_ctx_clone(self.h, stream, ctypes.byref(h)))
+        c.__dict__.update({k: v for k, v in self.__dict__.items() if k not in ("h",)})
+        c.h = h
+        c.parent = self            # the parent outlives its clones
+        return c
 
     def close(self):
         """hs_ctx_destroy now (every device block back to the allocator);

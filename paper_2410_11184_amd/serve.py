@@ -6,9 +6,10 @@ with m N0 / n >= V, vectors beyond V padded with zeros), and requests with the
 same (n, m, M) run as the jobs of one lockstep ``hs_softmax_jobs`` call, whose
 outputs are bit for bit those of each job alone.
 
-Each worker owns a context (keys generated from the same seed, so every
-worker computes the same ciphertexts) and its own HIP stream: batches of
-different workers overlap on the device.  A worker admits pending requests
+Each worker has a context and its own HIP stream: worker 0 generates the
+keys, the others are clones of its context (``hs_ctx_clone``) that read the
+same key memory, so one key set sits in HBM and every worker computes the
+same ciphertexts; batches of different workers overlap on the device.  A worker admits pending requests
 (oldest first, same shape) while the estimated device memory of everything in
 flight stays within the HBM budget, so requests that arrive while others run
 are taken as soon as a worker and memory are free.
@@ -82,7 +83,8 @@ class SoftmaxServer:
         self.contexts, self.streams = [], []
         for w in range(workers):
             self.streams.append(hs.stream_create(device))
-            self.contexts.append(self._make_context(w))
+            # worker 0 holds the key set, the others share it (one copy in HBM)
+            self.contexts.append(self._make_context(w) if w == 0 else self.contexts[0].clone(self.streams[w]))
         # one small Softmax per worker and warm dimension builds the bootstrap
         # tables and keys before the first request
         for w, ctx in enumerate(self.contexts):
@@ -187,10 +189,14 @@ class SoftmaxServer:
                     self.lock.wait(0.05)
             try:
                 self.contexts[w].sync()
-                self.contexts[w] = None
-                import gc
-                gc.collect()
-                self.contexts[w] = self._make_context(w)
+                if w > 0:
+                    # a fresh clone (the failed call may have left blocks of its own allocated)
+                    self.contexts[w] = None
+                    import gc
+                    gc.collect()
+                    self.contexts[w] = self.contexts[0].clone(self.streams[w])
+                else:
+                    self.contexts[0].trim()   # its clones share its keys: kept, trimmed
                 self._run(self.contexts[w], batch, w)
             finally:
                 with self.lock:
