@@ -293,13 +293,22 @@ typedef struct hs_softmax_opts {
     int mask_mode;        /* 0: mask = indicator of slots [0, L); 1: the      */
                           /* averaging mask (m / n on every slot, no          */
                           /* plaintext; bootstraps of the factors unmasked)   */
+    int refine;           /* the last normalisation's input S, when it is     */
+                          /* bootstrapped: 1 = bootstrapped twice (the second */
+                          /* pass refreshes the first one's error, scaled by  */
+                          /* 2^16, and subtracts it: S keeps its pre-         */
+                          /* bootstrapping precision); -1 = once; 0 = default */
 } hs_softmax_opts;
 
 /* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n
  * packed in the m ciphertexts in[0..m) (layout of hs_pack_softmax), all at
  * the same level and scale, inputs in [-M, 0] (the paper's assumption of
  * Section 3.1; values outside give unspecified results).  For the first step
- * to cost no level, encrypt the inputs at scale 2^(log_scale + 1) / M.
+ * to cost no level, encrypt the inputs at scale D = 2^(log_scale + 1) / M;
+ * inputs at level l >= 1 and scale D q_l take one rescale first, which
+ * divides their encryption noise by q_l (at scale D that noise limits the
+ * output to about 16.5 bits at N = 2^16: an absolute logit error becomes a
+ * relative output error); other scales take one constant product.
  * Writes m new handles to out[0..m).  A dimension n that is not a power of
  * two is packed (hs_pack_softmax) as the next power of two n2, and the
  * exponentials of the extra coordinates are removed by one plaintext mask

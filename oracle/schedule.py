@@ -203,13 +203,22 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             a = ctx.add_ct(a, ctx.rotate(a, L << t))
         return a
 
-    # v = 2x / M in [-2, 0]: a declared-scale change, or a constant product
+    # v = 2x / M in [-2, 0]: a declared-scale change; one rescale first for
+    # inputs encrypted at (2 Delta / M) q_l (the encryption noise divided by
+    # q_l); otherwise a constant product
     vs = xs[0].scale * M / 2.0
+    lx = xs[0].level
     if abs(math.log2(vs) - log_scale) <= 2.0:
         v = []
         for x in xs:
             c = x.copy()
             c.scale = vs
+            v.append(c)
+    elif lx >= 1 and abs(math.log2(vs / float(ctx.q[lx])) - log_scale) <= 2.0:
+        v = []
+        for x in xs:
+            c = ctx.rescale(x)
+            c.scale = c.scale * M / 2.0
             v.append(c)
     else:
         v = [P.mul_const(ctx, x, 2.0 / M, Delta) for x in xs]

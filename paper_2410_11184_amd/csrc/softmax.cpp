@@ -144,6 +144,27 @@ static double lam_bound_big(int n, double lam_bound) {
 // slots [0, L) and the refreshed value is masked the same way, so that its
 // bootstrapping error, once broadcast, is the same for every element of a
 // Softmax and is removed by the next renormalisation.
+// HS_TRACE >= 2 (eager runs only): decrypt a bootstrapping's input and
+// output (first ciphertext) and print the largest slot difference, absolute
+// and relative to the input's largest slot (masked: slots [0, L) against the
+// input, the rest against zero)
+static void trace_boot_error(Context& c, const Ct& x, const Ct& b, int mask_L) {
+    const int n = c.N / 2;
+    std::vector<double> xr(n), xi(n), br(n), bi(n);
+    decrypt_decode(c, x, 0, xr.data(), xi.data());
+    decrypt_decode(c, b, 0, br.data(), bi.data());
+    double err = 0, big = 0, small = 1e300;
+    for (int k = 0; k < n; k++) {
+        const bool keep = mask_L <= 0 || k < mask_L;
+        const double wr = keep ? xr[k] : 0.0, wi = keep ? xi[k] : 0.0;
+        err = std::max(err, std::hypot(br[k] - wr, bi[k] - wi));
+        big = std::max(big, std::fabs(wr));
+        if (keep) small = std::min(small, std::fabs(wr));
+    }
+    std::fprintf(stderr, "[hs]   bootstrap error 2^%.2f (input |x| in [%.3g, %.3g], level %d, scale 2^%.2f)\n",
+                 std::log2(err + 1e-300), small, big, x.level, std::log2(x.scale));
+}
+
 static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxStats& st, bool& replaced,
                        const char* what, int iter, int mask_L = 0) {
     replaced = false;
@@ -155,8 +176,36 @@ static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxS
     Ct b = bootstrap(c, x, bound, mask_L);
     st.bootstraps += x.m;
     replaced = true;
+    const char* tr = std::getenv("HS_TRACE");
+    if (tr && std::atoi(tr) >= 2 && !c.capturing) trace_boot_error(c, x, b, mask_L);
     HS_REQUIRE(b.level >= need, E_LEVEL, "Softmax: bootstrapping does not restore enough levels");
     return b;
+}
+
+// Bootstrapping b of x refined by a second bootstrapping of its own error:
+// d = (b - x) 2^16 at x's level (b brought to x's exact scale by a constant
+// product), E = bootstrap(d) (|d| <= 1 while b's error is below 2^-16 of
+// x's unit), and b - E 2^-16.  The result keeps x's precision instead of
+// the bootstrapping's (about 2^-24 of the value bound at N = 2^16); it sits
+// one level below b and has b's scale.
+static Ct refine_bootstrap(Context& c, const Ct& x, const Ct& b, SoftmaxStats& st) {
+    constexpr int r = 16;
+    HS_REQUIRE(b.level >= x.level + 2, E_LEVEL, "refined bootstrap: output level too low");
+    Ct bd = ct_drop(c, b, x.level + 1);
+    Ct bx = op_mul_const(c, bd, 1.0, x.scale);
+    ct_free(c, bd);
+    Ct d = op_sub(c, bx, x);
+    ct_free(c, bx);
+    op_mul_int_inplace(c, d, 1LL << r);
+    Ct e = bootstrap(c, d, 1.0, 0);
+    st.bootstraps += d.m;
+    ct_free(c, d);
+    Ct es = op_mul_const(c, e, std::ldexp(1.0, -r), b.scale);
+    ct_free(c, e);
+    Ct out = ct_drop(c, b, es.level);
+    op_sub_inplace(c, out, es);
+    ct_free(c, es);
+    return out;
 }
 
 // Padded dimension (n below the power of two np2 it is packed in): y0 times
@@ -316,12 +365,21 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         add_galois_key(c, galois_rot(L << t, c.N));
     }
     // v = 2x / M in [-2, 0]: a change of the declared scale when the input
-    // was encrypted at scale ~ 2 Delta / M, otherwise one constant product.
+    // was encrypted at scale ~ 2 Delta / M; one rescale first when it was
+    // encrypted at (2 Delta / M) q_l (its encryption noise, about 2^17 of
+    // the scale's unit in the slots at N = 2^16, then shrinks by q_l: at
+    // scale 2 Delta / M itself that noise, about 2^-16.6 in logit units, is
+    // the largest error of the output, since Softmax passes an absolute
+    // logit error on as a relative output error); otherwise one constant
+    // product.
     Ct v;
     const double vs = x.scale * M / 2.0;
     if (std::fabs(std::log2(vs) - c.prm.log_scale) <= 2.0) {
         v = ct_copy(c, x);
         v.scale = vs;
+    } else if (x.level >= 1 && std::fabs(std::log2(vs / (double)c.primes[x.level]) - c.prm.log_scale) <= 2.0) {
+        v = op_rescale(c, x);
+        v.scale = v.scale * M / 2.0;
     } else {
         v = op_mul_const(c, x, 2.0 / M, Delta);
     }
@@ -410,7 +468,15 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             // z = lambda y and z^t
             const int keep = (tp != 2 || o.newton_steps) ? 2 + tl : 1;
             bool rep;
-            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 2 * o.newton_steps + keep, hi * 1.1, st, rep, "S", j);
+            const int needS = cheb_depth(deg) + 2 * o.newton_steps + keep;
+            Ct S2 = ensure_level(c, S, needS + (last && o.refine ? 1 : 0), hi * 1.1, st, rep, "S", j);
+            if (rep && last && o.refine) {
+                Ct S3 = refine_bootstrap(c, S, S2, st);
+                ct_free(c, S2);
+                S2 = S3;
+                const char* tr = std::getenv("HS_TRACE");
+                if (tr && std::atoi(tr) >= 2 && !c.capturing) trace_boot_error(c, S, S2, 0);
+            }
             if (rep) {
                 ct_free(c, S);
                 S = S2;

@@ -1,17 +1,26 @@
 """Client-side helpers around ``hs_softmax``: pack logits (Section 4
-layout), encrypt them at the scale that makes the first step free, run the
-encrypted Softmax on the GPU, decrypt and unpack.  All arithmetic runs in
+layout), encrypt them at a scale that makes the first step a rescale or
+nothing, run the encrypted Softmax on the GPU, decrypt and unpack.  All arithmetic runs in
 ``libhs.so``."""
 import numpy as np
 
 from . import hs
 
 
-def encrypt_logits(ctx, logits, M, seed, level=None):
-    """Pack (L, n) logits into m ciphertexts at scale 2 Delta / M."""
+def encrypt_logits(ctx, logits, M, seed, level=None, headroom=True):
+    """Pack (L, n) logits into m ciphertexts.  With a level above the top
+    user level (rings with bootstrapping) and headroom set, they are encrypted
+    there at scale (2 Delta / M) q_l: the Softmax's first step is then one
+    rescale, which divides the encryption noise by q_l (at scale 2 Delta / M
+    that noise bounds the output's precision near 16.5 bits at N = 2^16).
+    Otherwise at the top user level (or `level`) and scale 2 Delta / M."""
     packed = hs.pack_softmax(logits, ctx.slots, M)
-    level = ctx.user_top if level is None else level
     scale = ctx.delta * 2.0 / M
+    if level is None:
+        level = ctx.user_top
+        if headroom and ctx.L > ctx.user_top:
+            level = ctx.user_top + 1
+            scale *= float(ctx.primes()[level])
     return [ctx.encrypt(packed[j], level, scale, seed + j) for j in range(packed.shape[0])]
 
 

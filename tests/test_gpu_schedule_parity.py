@@ -66,13 +66,15 @@ def pair():
     return g, o
 
 
-def _inputs(g, o, n, M, m, seed):
+def _inputs(g, o, n, M, m, seed, headroom=False):
     from oracle import softmax as S
     L = m * o.slots // S.padded(n)
     x = synthetic.logits_uniform(L, n, M, seed=seed)
     packed = S.pack(x, m, o.slots)
     scale = o.delta * 2.0 / M
     top = synthetic.preset("toy12")["user_top"]
+    if headroom:
+        scale *= float(o.q[top])
     gx = [g.encrypt(packed[j], top, scale, seed + 100 + j) for j in range(m)]
     ox = [o.encode_encrypt(packed[j], scale, top, seed + 100 + j) for j in range(m)]
     for a, b in zip(gx, ox):
@@ -115,3 +117,23 @@ def test_schedule_matches_oracle(pair, case):
     bits = S.precision_bits(S.softmax(x), y)
     print(case, bits)
     assert bits["worst"] >= want_bits
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_input_one_rescale_above_matches_oracle(pair, variant):
+    # inputs at scale (2 Delta / M) q_l: the schedule starts with one rescale
+    # (the encryption noise divided by q_l) instead of the declared-scale change
+    from oracle import schedule, softmax as S
+    g, o = pair
+    n, M, m = 16, 8.0, 2
+    x, gx, ox = _inputs(g, o, n, M, m, seed=760 + variant, headroom=True)
+    kw = dict(variant=variant, exp_degree=7, inv_degrees=(15, 15, 31))
+    gy0 = g.softmax(gx, n, M, debug_stop=0, **kw)
+    oy0 = schedule.softmax(o, ox, n, M, debug_stop=0, **kw)
+    _compare(g, o, gy0, oy0, "y0")
+    assert gy0[0].level == gx[0].level - 1 - 4           # one rescale, then the degree-7 polynomial
+    gy = g.softmax(gx, n, M, **kw)
+    oy = schedule.softmax(o, ox, n, M, **kw)
+    _compare(g, o, gy, oy, "output")
+    y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy]), n)
+    assert S.precision_bits(S.softmax(x), y)["worst"] >= 16.0
