@@ -293,11 +293,6 @@ typedef struct hs_softmax_opts {
     int mask_mode;        /* 0: mask = indicator of slots [0, L); 1: the      */
                           /* averaging mask (m / n on every slot, no          */
                           /* plaintext; bootstraps of the factors unmasked)   */
-    int refine;           /* the last normalisation's input S, when it is     */
-                          /* bootstrapped: 1 = bootstrapped twice (the second */
-                          /* pass refreshes the first one's error, scaled by  */
-                          /* 2^16, and subtracts it: S keeps its pre-         */
-                          /* bootstrapping precision); -1 = once; 0 = default */
 } hs_softmax_opts;
 
 /* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n

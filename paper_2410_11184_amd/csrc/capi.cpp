@@ -824,7 +824,6 @@ static hs::SoftmaxOpts softmax_opts(const hs_softmax_opts* opts) {
         if (opts->power > 0) o.power = opts->power;
         o.newton_steps = opts->newton_steps;
         o.mask_mode = opts->mask_mode;
-        if (opts->refine != 0) o.refine = opts->refine > 0 ? 1 : 0;
     }
     return o;
 }

@@ -182,32 +182,6 @@ static Ct ensure_level(Context& c, const Ct& x, int need, double bound, SoftmaxS
     return b;
 }
 
-// Bootstrapping b of x refined by a second bootstrapping of its own error:
-// d = (b - x) 2^16 at x's level (b brought to x's exact scale by a constant
-// product), E = bootstrap(d) (|d| <= 1 while b's error is below 2^-16 of
-// x's unit), and b - E 2^-16.  The result keeps x's precision instead of
-// the bootstrapping's (about 2^-24 of the value bound at N = 2^16); it sits
-// one level below b and has b's scale.
-static Ct refine_bootstrap(Context& c, const Ct& x, const Ct& b, SoftmaxStats& st) {
-    constexpr int r = 16;
-    HS_REQUIRE(b.level >= x.level + 2, E_LEVEL, "refined bootstrap: output level too low");
-    Ct bd = ct_drop(c, b, x.level + 1);
-    Ct bx = op_mul_const(c, bd, 1.0, x.scale);
-    ct_free(c, bd);
-    Ct d = op_sub(c, bx, x);
-    ct_free(c, bx);
-    op_mul_int_inplace(c, d, 1LL << r);
-    Ct e = bootstrap(c, d, 1.0, 0);
-    st.bootstraps += d.m;
-    ct_free(c, d);
-    Ct es = op_mul_const(c, e, std::ldexp(1.0, -r), b.scale);
-    ct_free(c, e);
-    Ct out = ct_drop(c, b, es.level);
-    op_sub_inplace(c, out, es);
-    ct_free(c, es);
-    return out;
-}
-
 // Padded dimension (n below the power of two np2 it is packed in): y0 times
 // the 0/1 indicator of the real coordinates.  Ciphertext j of a job holds
 // coordinates j per .. (j + 1) per - 1 on slot blocks of L, so its indicator
@@ -468,15 +442,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             // z = lambda y and z^t
             const int keep = (tp != 2 || o.newton_steps) ? 2 + tl : 1;
             bool rep;
-            const int needS = cheb_depth(deg) + 2 * o.newton_steps + keep;
-            Ct S2 = ensure_level(c, S, needS + (last && o.refine ? 1 : 0), hi * 1.1, st, rep, "S", j);
-            if (rep && last && o.refine) {
-                Ct S3 = refine_bootstrap(c, S, S2, st);
-                ct_free(c, S2);
-                S2 = S3;
-                const char* tr = std::getenv("HS_TRACE");
-                if (tr && std::atoi(tr) >= 2 && !c.capturing) trace_boot_error(c, S, S2, 0);
-            }
+            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 2 * o.newton_steps + keep, hi * 1.1, st, rep, "S", j);
             if (rep) {
                 ct_free(c, S);
                 S = S2;

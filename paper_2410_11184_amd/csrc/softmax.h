@@ -17,7 +17,6 @@ struct SoftmaxOpts {
     int power = 2;            // t of normalize-and-t-th-power (2, 3, 4; version B: 2)
     int newton_steps = 0;     // > 0: inverse roots by that many Newton steps from the polynomial
     int mask_mode = 0;        // 0: indicator of slots [0, L); 1: averaging (m / n on every slot)
-    int refine = 0;           // > 0: the last iteration's S bootstrapped twice (error refreshed and removed)
 };
 
 struct SoftmaxStats {

@@ -24,7 +24,7 @@ import time
 import numpy as np
 
 from . import hs
-from .softmax import decrypt_outputs
+from .softmax import decrypt_outputs, encrypt_logits
 
 
 class Request:
@@ -222,9 +222,7 @@ class SoftmaxServer:
             r.t_start = t0
             x = np.zeros((L, n))
             x[:r.V] = r.logits
-            packed = hs.pack_softmax(x, self.slots, M)
-            cts += [ctx.encrypt(packed[j], ctx.user_top, ctx.delta * 2.0 / M, 100003 * (r.rid + 1) + j)
-                    for j in range(m)]
+            cts += encrypt_logits(ctx, x, M, seed=100003 * (r.rid + 1))
         out = ctx.softmax(cts, n, M, variant=self._variant(n), jobs=len(batch), **self.softmax_kw)
         del cts
         for i, r in enumerate(batch):
