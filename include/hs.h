@@ -481,6 +481,14 @@ hs_status hs_dbg_ring(hs_ctx* ctx, int op, int level, int arg, const uint64_t* i
  * the context's device and stream).  HS_E_DEVICE if the probe fails. */
 hs_status hs_dbg_mul_rate(hs_ctx* ctx, double* tops);
 
+/* Host only: the coefficients c[0..degree] (Chebyshev basis of [a, b]) of the
+ * normalisation polynomial the Softmax evaluates for s^-e on [a, b]: the
+ * weighted minimax approximant minimising max |P(s) s^e - 1| (Section 5.1,
+ * "Designing auxiliary functions"), as the Remez exchange on the fixed grid
+ * u_i = -cos(pi i / (G - 1)), G = 16 (degree + 1) + 1, specified in
+ * csrc/poly.h.  0 < a < b, e > 0, degree 0..1023 (HS_E_ARG otherwise). */
+hs_status hs_dbg_minimax(double a, double b, int degree, double e, double* c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,9 +12,12 @@ coefficients nor the evaluation order, so this module states one and the
 HIP library implements the same one (scale-exact baby-step giant-step in
 the Chebyshev basis, Bossuat et al., EUROCRYPT 2021):
 
-* coefficients: the interpolant at the d+1 Chebyshev nodes of the first
-  kind of [a, b], computed in mpmath at 256 bits and rounded once to double
-  (``cheb_interp``);
+* coefficients: for the exponential, the interpolant at the d+1 Chebyshev
+  nodes of the first kind of [a, b], computed in mpmath at 256 bits and
+  rounded once to double (``cheb_interp``); for the inverse powers s^-e,
+  the paper's weighted minimax approximant (min max |P(s) s^e - 1|), as the
+  discrete minimax on a fixed grid by the Remez exchange
+  (``minimax_invpow``, steps stated there);
 * the argument u = alpha x + beta maps [a, b] to [-1, 1]: alpha = 2/(b-a) and
   beta = -(a+b)/(b-a) as doubles; when alpha is a power of two >= 1 it is an
   integer product (no level), else a constant product at scale 2^log_scale;
@@ -71,6 +74,100 @@ def cheb_interp(f, a, b, d, prec=256):
                 cj /= 2
             out.append(float(cj))
     return out
+
+
+_MINIMAX = {}
+
+
+def _solve_ld(A, y):
+    """Gaussian elimination with partial pivoting (numpy long double)."""
+    A = A.copy()
+    y = y.copy()
+    n = len(y)
+    for col in range(n):
+        piv = col + int(np.argmax(np.abs(A[col:, col])))
+        if piv != col:
+            A[[col, piv]] = A[[piv, col]]
+            y[[col, piv]] = y[[piv, col]]
+        f = A[col + 1:, col] / A[col, col]
+        A[col + 1:, col:] -= np.outer(f, A[col, col:])
+        y[col + 1:] -= f * y[col]
+    x = np.zeros(n, dtype=np.longdouble)
+    for r in range(n - 1, -1, -1):
+        x[r] = (y[r] - np.dot(A[r, r + 1:], x[r + 1:])) / A[r, r]
+    return x
+
+
+def minimax_invpow(a, b, d, e):
+    """Weighted minimax approximant of s^-e on [a, b] (Section 5.1, "Designing
+    auxiliary functions": the polynomial P of degree d with the smallest
+    max |P(s) s^e - 1|), coefficients in the Chebyshev basis of [a, b].
+
+    Computed as the minimax on the grid u_i = -cos(pi i / (G - 1)),
+    i = 0..G-1, G = 16 (d + 1) + 1, by the Remez exchange:
+    * reference: the grid indices 16 k, k = 0..d+1 (the extrema of T_(d+1));
+    * each round (at most 40, in 80-bit long double): solve
+      sum_j c_j T_j(u_k) + (-1)^k h / w_k = 1 / w_k at the reference
+      (w = s^e); with r = w P - 1 on the grid, take in every run of equal
+      sign (r >= 0 counting as positive) the index of the largest |r| (the
+      first on ties); while more than d + 2 remain, drop the end one with the
+      smaller |r| (the last on ties); stop when fewer remain or nothing
+      changed, else take them as the new reference;
+    * the coefficients: the reference system solved again at 50 decimal
+      digits (mpmath), rounded to double.
+    Test infrastructure: cached per (a, b, d, e)."""
+    key = (float(a), float(b), int(d), float(e))
+    if key in _MINIMAX:
+        return list(_MINIMAX[key])
+    G = 16 * (d + 1) + 1
+    pi = np.longdouble("3.14159265358979323846264338327950288")
+    al, bl, el = np.longdouble(a), np.longdouble(b), np.longdouble(e)
+    u = -np.cos(pi * np.arange(G, dtype=np.longdouble) / np.longdouble(G - 1))
+    s = (u * (bl - al) + al + bl) / 2
+    w = np.power(s, el)
+    T = np.empty((G, d + 1), dtype=np.longdouble)
+    T[:, 0] = 1
+    if d >= 1:
+        T[:, 1] = u
+    for j in range(2, d + 1):
+        T[:, j] = 2 * u * T[:, j - 1] - T[:, j - 2]
+    sgn = np.array([(-1) ** k for k in range(d + 2)], dtype=np.longdouble)
+    ref = [16 * k for k in range(d + 2)]
+    for _ in range(40):
+        A = np.concatenate([T[ref], (sgn / w[ref])[:, None]], axis=1)
+        c = _solve_ld(A, 1 / w[ref])[:d + 1]
+        r = w * (T @ c) - 1
+        pos = r >= 0
+        cand = []
+        start = 0
+        for i in range(1, G + 1):
+            if i == G or pos[i] != pos[start]:
+                cand.append(start + int(np.argmax(np.abs(r[start:i]))))
+                start = i
+        while len(cand) > d + 2:
+            if abs(r[cand[0]]) < abs(r[cand[-1]]):
+                cand.pop(0)
+            else:
+                cand.pop()
+        if len(cand) < d + 2 or cand == ref:
+            break
+        ref = cand
+    with mpmath.workdps(50):
+        a_, b_, e_ = mpmath.mpf(a), mpmath.mpf(b), mpmath.mpf(e)
+        rows, rhs = [], []
+        for k, i in enumerate(ref):
+            uk = -mpmath.cos(mpmath.pi * i / (G - 1))
+            sk = (uk * (b_ - a_) + a_ + b_) / 2
+            wk = mpmath.power(sk, e_)
+            t = [mpmath.mpf(1), uk]
+            while len(t) < d + 1:
+                t.append(2 * uk * t[-1] - t[-2])
+            rows.append(t[:d + 1] + [(-1) ** k / wk])
+            rhs.append(1 / wk)
+        sol = mpmath.lu_solve(mpmath.matrix(rows), mpmath.matrix(rhs))
+        out = [float(sol[j]) for j in range(d + 1)]
+    _MINIMAX[key] = out
+    return list(out)
 
 
 def cheb_eval_plain(coef, a, b, x):

@@ -23,8 +23,9 @@ Readings where the paper leaves a choice (the HIP library makes the same):
   n = 4096 on;
 * y0 is prescaled by 1/sqrt(n) (exp(M t / 2^(k+1)) / sqrt(n) on t = 2x/M in
   [-2, 0], degree 15 by default) so sum y0^2 lies in [e^(-2M/2^k), 1];
-* the normalisation polynomial of iteration j interpolates s^(-e) (e = 1/2,
-  or 2^-j for the non-final steps of version B) on [a, a + 2^w] covering the
+* the normalisation polynomial of iteration j is the weighted minimax
+  approximant of s^(-e) (polyeval.minimax_invpow; e = 1/2, or 2^-j for the
+  non-final steps of version B) on [a, a + 2^w] covering the
   interval [lo, hi] that the previous step's measured relative error gives
   (Section 5.1: [(1 - alpha)^2 / n, (1 + alpha)^2], with margins); degrees
   2^d - 1 with d from the paper's level table of the auxiliary thread;
@@ -285,8 +286,7 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             a, b = lo, hi
         else:
             a, b = free_interval(lo, hi)
-        ee = mpmath.mpf(e)
-        pinv = P.cheb_interp(lambda s: mpmath.power(s, -ee), a, b, deg)
+        pinv = P.minimax_invpow(a, b, deg, e)
         delta = newton_delta(rel_error(pinv, a, b, lo, hi, e), newton_steps)
         lam_bound = ((1.0 + delta) / math.sqrt(lo) if newton_steps else max_abs(pinv, a, b, lo, hi)) * 1.05
         pe = [cf / per for cf in pinv] if avg and not newton_steps else pinv

@@ -8,6 +8,7 @@
 
 #include "../../include/hs.h"
 #include "host.h"
+#include "poly.h"
 #include "softmax.h"
 #include <chrono>
 #include <memory>
@@ -666,6 +667,14 @@ hs_status hs_mul_monomial(hs_ctx* ctx, const hs_ct* a, int k, hs_ct** out) {
         NEED(a);
         NEED(out);
         *out = wrap(ctx->c, hs::op_mul_monomial(*ctx->c, a->ct, k));
+    });
+}
+
+hs_status hs_dbg_minimax(double a, double b, int degree, double e, double* c) {
+    return guard([&] {
+        NEED(c);
+        const hs::ChebPoly p = hs::minimax_invpow(a, b, degree, e);
+        for (int j = 0; j <= degree; j++) c[j] = p.c[j];
     });
 }
 

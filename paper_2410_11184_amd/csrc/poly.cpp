@@ -5,7 +5,9 @@
 // ceil(log(d+1)) levels and O(sqrt d) products (Section 2.2, "Functions as
 // polynomials", Paterson-Stockmeyer).  Here:
 //  * coefficients: Chebyshev interpolation at the d+1 first-kind nodes,
-//    computed in binary128 and rounded once to double;
+//    computed in binary128 and rounded once to double (the exponential); for
+//    the inverse powers s^-e, the paper's weighted minimax approximants
+//    (minimal max |P(s) s^e - 1|) by a Remez exchange on a fixed grid;
 //  * evaluation: baby-step giant-step in the Chebyshev basis.  Baby steps
 //    T_1..T_{B-1} by T_2k = 2 T_k^2 - 1 and T_2k+1 = 2 T_k T_k+1 - T_1; giant
 //    steps T_B, T_2B, ...; the polynomial splits as q_lo + q_hi T_n
@@ -18,6 +20,8 @@
 #include <complex>
 #include <functional>
 #include <map>
+#include <mutex>
+#include <tuple>
 
 #include <quadmath.h>
 
@@ -45,6 +49,143 @@ ChebPoly cheb_fit(const std::function<quad(quad)>& f, double a, double b, int d)
         if (j == 0) cj /= 2;
         p.c[j] = (double)cj;
     }
+    return p;
+}
+
+// ------------------------------------------------ weighted minimax (Remez)
+namespace {
+
+typedef long double ld;
+
+// Solve A x = y (n x n, row-major, destroyed) by Gaussian elimination with
+// partial pivoting.
+template <class T>
+std::vector<T> gauss_solve(std::vector<T>& A, std::vector<T> y, int n, T (*fab)(T)) {
+    for (int col = 0; col < n; col++) {
+        int piv = col;
+        for (int r = col + 1; r < n; r++)
+            if (fab(A[(size_t)r * n + col]) > fab(A[(size_t)piv * n + col])) piv = r;
+        HS_REQUIRE(A[(size_t)piv * n + col] != 0, E_ARG, "minimax: singular reference system");
+        if (piv != col) {
+            for (int j = 0; j < n; j++) std::swap(A[(size_t)piv * n + j], A[(size_t)col * n + j]);
+            std::swap(y[piv], y[col]);
+        }
+        const T inv = 1 / A[(size_t)col * n + col];
+        for (int r = col + 1; r < n; r++) {
+            const T f = A[(size_t)r * n + col] * inv;
+            if (f == 0) continue;
+            for (int j = col; j < n; j++) A[(size_t)r * n + j] -= f * A[(size_t)col * n + j];
+            y[r] -= f * y[col];
+        }
+    }
+    std::vector<T> x(n);
+    for (int r = n - 1; r >= 0; r--) {
+        T s = y[r];
+        for (int j = r + 1; j < n; j++) s -= A[(size_t)r * n + j] * x[j];
+        x[r] = s / A[(size_t)r * n + r];
+    }
+    return x;
+}
+
+ld fabs_ld(ld v) { return v < 0 ? -v : v; }
+quad fabs_q(quad v) { return v < 0 ? -v : v; }
+
+// The reference system at grid indices ref: sum_j c_j T_j(u_k) + (-1)^k h / w_k
+// = 1 / w_k, w = s^e; returns c_0..c_d, h.
+template <class T>
+std::vector<T> reference_solve(const std::vector<int>& ref, int d, int G, double a, double b, T e, T pi,
+                               T (*cosfn)(T), T (*powfn)(T, T), T (*fab)(T)) {
+    const int n = d + 2;
+    std::vector<T> A((size_t)n * n), y(n);
+    for (int k = 0; k < n; k++) {
+        const T u = -cosfn(pi * (T)ref[k] / (T)(G - 1));
+        const T s = (u * ((T)b - (T)a) + (T)a + (T)b) / 2;
+        const T w = powfn(s, e);
+        T t0 = 1, t1 = u;
+        A[(size_t)k * n] = 1;
+        if (d >= 1) A[(size_t)k * n + 1] = u;
+        for (int j = 2; j <= d; j++) {
+            const T t2 = 2 * u * t1 - t0;
+            A[(size_t)k * n + j] = t2;
+            t0 = t1;
+            t1 = t2;
+        }
+        A[(size_t)k * n + d + 1] = ((k & 1) ? -1 : 1) / w;
+        y[k] = 1 / w;
+    }
+    return gauss_solve<T>(A, y, n, fab);
+}
+
+ld cos_ld(ld v) { return cosl(v); }
+ld pow_ld(ld v, ld e) { return powl(v, e); }
+quad cos_q(quad v) { return cosq(v); }
+quad pow_q(quad v, quad e) { return powq(v, e); }
+
+}  // namespace
+
+ChebPoly minimax_invpow(double a, double b, int d, double e) {
+    static std::mutex mu;
+    static std::map<std::tuple<double, double, int, double>, ChebPoly> cache;
+    HS_REQUIRE(d >= 0 && d <= 1023 && a > 0 && b > a && e > 0, E_ARG, "minimax: bad interval, degree or power");
+    const auto key = std::make_tuple(a, b, d, e);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int G = 16 * (d + 1) + 1;
+    const ld pi = 3.141592653589793238462643383279502884L;
+    // grid, weights, and T_j on the grid (80-bit)
+    std::vector<ld> u(G), w(G);
+    for (int i = 0; i < G; i++) {
+        u[i] = -cosl(pi * (ld)i / (ld)(G - 1));
+        const ld s = (u[i] * ((ld)b - (ld)a) + (ld)a + (ld)b) / 2;
+        w[i] = powl(s, (ld)e);
+    }
+    std::vector<int> ref(d + 2);
+    for (int k = 0; k <= d + 1; k++) ref[k] = 16 * k;
+    std::vector<ld> r(G);
+    for (int it = 0; it < 40; it++) {
+        const std::vector<ld> c = reference_solve<ld>(ref, d, G, a, b, (ld)e, pi, cos_ld, pow_ld, fabs_ld);
+        for (int i = 0; i < G; i++) {
+            // Clenshaw
+            ld b1 = 0, b2 = 0;
+            for (int j = d; j >= 1; j--) {
+                const ld t = 2 * u[i] * b1 - b2 + c[j];
+                b2 = b1;
+                b1 = t;
+            }
+            r[i] = w[i] * (u[i] * b1 - b2 + c[0]) - 1;
+        }
+        // one candidate per run of equal sign: its largest |r| (first on ties)
+        std::vector<int> cand;
+        int start = 0;
+        for (int i = 1; i <= G; i++) {
+            if (i == G || (r[i] >= 0) != (r[start] >= 0)) {
+                int best = start;
+                for (int q = start + 1; q < i; q++)
+                    if (fabs_ld(r[q]) > fabs_ld(r[best])) best = q;
+                cand.push_back(best);
+                start = i;
+            }
+        }
+        // too many: drop the end candidate with the smaller |r| (the last on ties)
+        while ((int)cand.size() > d + 2) {
+            if (fabs_ld(r[cand.front()]) < fabs_ld(r[cand.back()])) cand.erase(cand.begin());
+            else cand.pop_back();
+        }
+        if ((int)cand.size() < d + 2 || cand == ref) break;
+        ref = cand;
+    }
+    // final solve at the reference in binary128
+    const std::vector<quad> cq = reference_solve<quad>(ref, d, G, a, b, (quad)e, M_PIq, cos_q, pow_q, fabs_q);
+    ChebPoly p;
+    p.a = a;
+    p.b = b;
+    p.c.resize(d + 1);
+    for (int j = 0; j <= d; j++) p.c[j] = (double)cq[j];
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = p;
     return p;
 }
 

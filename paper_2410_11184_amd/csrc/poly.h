@@ -19,6 +19,19 @@ struct ChebPoly {
 // computation of that interpolant gives.
 typedef __float128 quad;
 ChebPoly cheb_fit(const std::function<quad(quad)>& f, double a, double b, int degree);
+// The weighted minimax approximant of s^-e on [a, b] (Section 5.1,
+// "Designing auxiliary functions": P minimising max |P(s) s^e - 1|), degree
+// d, in the Chebyshev basis of [a, b], as the discrete minimax on the grid
+// u_i = -cos(pi i / (G - 1)), i < G = 16 (d + 1) + 1, by the Remez exchange:
+// reference = grid indices 16 k (the extrema of T_(d+1)), k = 0..d+1; each
+// round (at most 40, 80-bit arithmetic) solves the reference system
+// sum_j c_j T_j(u_k) + (-1)^k h / w_k = 1 / w_k (w = s^e), takes in every
+// run of equal sign of r = w P - 1 on the grid the index of the largest |r|
+// (the first on ties), drops end candidates (the one with the smaller |r|,
+// the last on ties) down to d + 2, and stops when fewer remain or the
+// reference repeats; the coefficients are those of the final reference
+// system solved in binary128, rounded to double.  Cached per (a, b, d, e).
+ChebPoly minimax_invpow(double a, double b, int d, double e);
 double cheb_eval_plain(const ChebPoly& p, double x);
 int cheb_depth(int degree);   // levels used by eval_cheb (plus 1 if the affine map needs one)
 // Evaluate p on every slot of the batch x; result at scale target_scale.

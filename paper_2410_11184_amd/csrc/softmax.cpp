@@ -387,10 +387,10 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         const double e = smb_step ? std::ldexp(1.0, -j) : (tp == 2 ? 0.5 : 1.0 / tp);
         int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);
         if (deg <= 0) {
-            // the paper's depths at n = 256 (6, 5, 7) for n <= 256 (its
-            // minimax polynomials allow depth 4 in the middle at n = 128; these
-            // interpolants do not); above, one more level for the first and
-            // middle steps (the interpolants' relative error at the low end of
+            // the paper's depths at n = 256 (6, 5, 7) for n <= 256 (its table
+            // has depth 4 in the middle at n = 128; 5 is kept here, on the
+            // power-of-two-wide intervals); above, one more level for the
+            // first and middle steps (the relative error at the low end of
             // [~1/n, 1] would otherwise widen every later interval)
             // t-th powers: the later intervals [~n^-(t-1), 1] are far wider,
             // so depth 6 / 7 up to n = 16 and 7 above
@@ -453,8 +453,8 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // SM with squares (the polynomial whose error reaches the output),
         // exactly [lo, hi] when S has the level its affine map then takes on
         // top of the polynomial and the final z = lambda y, y = z^2 (about 4
-        // bits of precision at n = 256: the wider interval spreads the
-        // interpolation nodes over values S never takes)
+        // bits of precision at n = 256: the wider interval spends the
+        // approximation on values S never takes)
         const int nsteps = o.newton_steps;
         double a, b;
         if (last && tp == 2 && !nsteps && S.level >= cheb_depth(deg) + 3) {
@@ -463,8 +463,8 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         } else {
             free_interval(lo, hi, a, b);
         }
-        const double ee = e;
-        ChebPoly pinv = cheb_fit([&](quad s) { return powq(s, -(quad)ee); }, a, b, deg);
+        // the paper's weighted minimax approximant: smallest max |P(s) s^e - 1|
+        ChebPoly pinv = minimax_invpow(a, b, deg, e);
         const double delta = newton_delta(rel_error(pinv, lo, hi, e), nsteps);
         double lam_bound = (nsteps ? (1.0 + delta) / std::sqrt(lo) : max_abs(pinv, lo, hi)) * 1.05;
         // the averaging mask: per copies of the factor, each divided by per,

@@ -117,6 +117,7 @@ def lib():
         "hs_mul_monomial": [_vp, _vp, S, ctypes.POINTER(_vp)],
         "hs_dbg_ntt": [_vp, S, _u64p, ctypes.c_size_t, S],
         "hs_dbg_mul_rate": [_vp, ctypes.POINTER(ctypes.c_double)],
+        "hs_dbg_minimax": [ctypes.c_double, ctypes.c_double, S, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
         "hs_dbg_ntt_time": [_vp, S, S, S, S, ctypes.POINTER(ctypes.c_double)],
         "hs_dbg_ring": [_vp, S, S, S, _u64p, ctypes.c_size_t, _u64p, ctypes.c_size_t,
                         ctypes.POINTER(ctypes.c_size_t)],
@@ -171,6 +172,14 @@ def lib():
 def _check(st):
     if st != 0:
         raise HSError(st, lib().hs_last_error().decode())
+
+
+def minimax(a, b, degree, e):
+    """hs_dbg_minimax (host only): Chebyshev coefficients on [a, b] of the
+    weighted minimax approximant of s^-e the Softmax uses."""
+    c = (ctypes.c_double * (degree + 1))()
+    _check(lib().hs_dbg_minimax(a, b, degree, e, c))
+    return np.array(c[:], dtype=np.float64)
 
 
 def stream_create(device=0):

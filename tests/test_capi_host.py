@@ -108,3 +108,16 @@ def test_prime_sizes_below_32_bits_refused():
         hs.Context(p)
     assert e.value.name == "HS_E_PARAM"
     assert "32, 61" in str(e.value)
+
+
+@pytest.mark.parametrize("case", [(0.98 / 256, 1.0001, 31, 0.5), (0.98 / 4096, 2.0, 15, 0.25),
+                                  (0.01, 1.0, 7, 1.0), (0.5, 1.5, 3, 1 / 3), (0.98 / 256, 1.0, 63, 0.5)])
+def test_minimax_coefficients_equal_the_oracle(case):
+    # the library's normalisation polynomials (binary128 final solve) and the
+    # oracle's (mpmath) follow one specification: the same doubles
+    from paper_2410_11184_amd import hs
+    from oracle import polyeval as PE
+    a, b, d, e = case
+    assert np.array_equal(hs.minimax(a, b, d, e), np.array(PE.minimax_invpow(a, b, d, e)))
+    with pytest.raises(hs.HSError):
+        hs.minimax(b, a, d, e)

@@ -65,10 +65,8 @@ def test_paper_input_law(ctx, M):
     print("M=%g: %s, stats %s" % (M, bits, ctx.softmax_stats()))
     assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -12
     # M = 128 carries the metric's 16-bit bar; at M = 256 the paper reports
-    # 16.6 bits worst case for Algorithm SM with weighted-minimax
-    # normalisation polynomials, and these Chebyshev interpolants reach about
-    # 15.8 (measured 15.77 on this input)
-    assert bits["worst"] >= (16.0 if M <= 128 else 15.5), bits
+    # 16.6 bits worst case for Algorithm SM (measured here: 18.3)
+    assert bits["worst"] >= 16.0, bits
 
 
 def test_serving_at_full_size():

@@ -248,3 +248,46 @@ def test_newton_inverse_sqrt_error_map():
     d = 0.5
     for steps in (1, 2, 3):
         assert schedule.newton_delta(d, steps) <= 4 / 7 * (7 / 8) ** (2 ** steps)
+
+
+def test_weighted_minimax_closed_forms():
+    # e = 1: min over degree-d P of max |s P(s) - 1| on [a, b] is
+    # 1 / T_(d+1)((b + a) / (b - a)) (the Chebyshev polynomial extremal
+    # property), reached on the grid up to its spacing
+    from oracle import polyeval as PE
+    a, b = 0.01, 1.0
+    g = np.linspace(a, b, 400001)
+    for d in (1, 3, 7, 15):
+        c = np.array(PE.minimax_invpow(a, b, d, 1.0))
+        err = np.max(np.abs(P.cheb_eval(c, g, a, b) * g - 1))
+        want = 1.0 / np.cosh((d + 1) * np.arccosh((b + a) / (b - a)))
+        assert abs(err / want - 1) < 1e-6, (d, err, want)
+    # degree 0, e = 1/2: the constant 2 / (sqrt(a) + sqrt(b)), relative error
+    # (sqrt(b) - sqrt(a)) / (sqrt(b) + sqrt(a)) at both ends
+    for a, b in ((1 / 256, 1.0), (0.3, 2.5)):
+        c = PE.minimax_invpow(a, b, 0, 0.5)
+        assert abs(c[0] - 2 / (math.sqrt(a) + math.sqrt(b))) < 1e-15
+
+
+def test_weighted_minimax_equioscillates_and_beats_interpolation():
+    from oracle import polyeval as PE
+    for (a, b, d, e) in ((0.98 / 256, 1.0001, 15, 0.5), (0.98 / 256, 2.0, 31, 0.25), (0.3, 1.3, 7, 1 / 3)):
+        c = np.array(PE.minimax_invpow(a, b, d, e))
+        g = a + (b - a) * (1 - np.cos(np.linspace(0, np.pi, 200001))) / 2
+        E = P.cheb_eval(c, g, a, b) * g ** e - 1
+        emax = np.max(np.abs(E))
+        # d + 2 alternating extrema of equal size (the minimax on the grid of
+        # 16 points per degree: its extrema between grid points exceed the
+        # levelled error by well under 1%)
+        ext = []
+        start = 0
+        s = E >= 0
+        for i in range(1, len(E) + 1):
+            if i == len(E) or s[i] != s[start]:
+                ext.append(np.max(np.abs(E[start:i])))
+                start = i
+        assert len(ext) >= d + 2, (d, len(ext))
+        assert min(sorted(ext)[-(d + 2):]) > emax * (1 - 1e-2), (d, e)
+        ci = P.cheb_interp(lambda x: x ** -e, a, b, d)
+        ei = np.max(np.abs(P.cheb_eval(ci, g, a, b) * g ** e - 1))
+        assert emax < ei, (d, e, emax, ei)
