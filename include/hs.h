@@ -289,10 +289,19 @@ typedef struct hs_softmax_opts {
                              (0 = after the exponential); -1 = off          */
     int newton_steps;     /* > 0: each inverse root by that many Newton steps */
                           /* (Appendix A, inverse square roots) from the      */
-                          /* normalisation polynomial as first guess; 0 off   */
+                          /* normalisation polynomial as first guess (the     */
+                          /* guess bootstrapped first when its depth and the  */
+                          /* steps exceed the levels a bootstrap restores);   */
+                          /* 0 = by dimension: none up to n = 2048, 2 above   */
+                          /* for variant 0 with squares; -1 = none            */
     int mask_mode;        /* 0: mask = indicator of slots [0, L); 1: the      */
                           /* averaging mask (m / n on every slot, no          */
                           /* plaintext; bootstraps of the factors unmasked)   */
+    int approx;           /* normalisation polynomials: 0 = the weighted      */
+                          /* minimax approximants (Section 5.1; smallest max  */
+                          /* relative error on the interval), 1 = Chebyshev   */
+                          /* interpolants (larger worst case, smaller error   */
+                          /* away from the interval's lower end)              */
 } hs_softmax_opts;
 
 /* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n

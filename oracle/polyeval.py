@@ -112,9 +112,15 @@ def minimax_invpow(a, b, d, e):
       sign (r >= 0 counting as positive) the index of the largest |r| (the
       first on ties); while more than d + 2 remain, drop the end one with the
       smaller |r| (the last on ties); stop when fewer remain or nothing
-      changed, else take them as the new reference;
+      changed, else take them as the new reference; stop before the exchange
+      when the levelled error |h| is below 2^-40 (far below any ciphertext's
+      precision, and near the rounding of r in long double, where the
+      exchange would follow noise);
     * the coefficients: the reference system solved again at 50 decimal
-      digits (mpmath), rounded to double.
+      digits (mpmath), each rounded to the nearest multiple of 2^(E - 52)
+      with 2^E <= max |c_j| < 2^(E+1) (the largest one's double ulp), so
+      that the small high-order coefficients of a near-exact fit are as
+      reproducible as the largest.
     Test infrastructure: cached per (a, b, d, e)."""
     key = (float(a), float(b), int(d), float(e))
     if key in _MINIMAX:
@@ -135,7 +141,10 @@ def minimax_invpow(a, b, d, e):
     ref = [16 * k for k in range(d + 2)]
     for _ in range(40):
         A = np.concatenate([T[ref], (sgn / w[ref])[:, None]], axis=1)
-        c = _solve_ld(A, 1 / w[ref])[:d + 1]
+        sol = _solve_ld(A, 1 / w[ref])
+        if abs(sol[d + 1]) < np.longdouble(2.0) ** -40:
+            break
+        c = sol[:d + 1]
         r = w * (T @ c) - 1
         pos = r >= 0
         cand = []
@@ -165,7 +174,14 @@ def minimax_invpow(a, b, d, e):
             rows.append(t[:d + 1] + [(-1) ** k / wk])
             rhs.append(1 / wk)
         sol = mpmath.lu_solve(mpmath.matrix(rows), mpmath.matrix(rhs))
-        out = [float(sol[j]) for j in range(d + 1)]
+        cmax = max(abs(sol[j]) for j in range(d + 1))
+        E = int(mpmath.floor(mpmath.log(cmax, 2)))
+        if mpmath.ldexp(1, E) > cmax:       # log rounding at a power of two
+            E -= 1
+        elif mpmath.ldexp(1, E + 1) <= cmax:
+            E += 1
+        unit = mpmath.ldexp(1, E - 52)
+        out = [float(mpmath.nint(sol[j] / unit) * unit) for j in range(d + 1)]
     _MINIMAX[key] = out
     return list(out)
 

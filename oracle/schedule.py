@@ -24,7 +24,8 @@ Readings where the paper leaves a choice (the HIP library makes the same):
 * y0 is prescaled by 1/sqrt(n) (exp(M t / 2^(k+1)) / sqrt(n) on t = 2x/M in
   [-2, 0], degree 15 by default) so sum y0^2 lies in [e^(-2M/2^k), 1];
 * the normalisation polynomial of iteration j is the weighted minimax
-  approximant of s^(-e) (polyeval.minimax_invpow; e = 1/2, or 2^-j for the
+  approximant of s^(-e) (polyeval.minimax_invpow; with approx = 1 the
+  Chebyshev interpolant instead; e = 1/2, or 2^-j for the
   non-final steps of version B) on [a, a + 2^w] covering the
   interval [lo, hi] that the previous step's measured relative error gives
   (Section 5.1: [(1 - alpha)^2 / n, (1 + alpha)^2], with margins); degrees
@@ -99,7 +100,7 @@ def free_interval(lo, hi):
     return lo, lo + w
 
 
-def default_degree(n, j, last, t=2, newton_steps=0):
+def default_degree(n, j, last, t=2):
     if t != 2:
         d = (7 if last else 6) if n <= 16 else 7
     elif n <= 256:
@@ -108,8 +109,6 @@ def default_degree(n, j, last, t=2, newton_steps=0):
         d = 8 if last else 6
     else:
         d = 8 if last else 7
-    # with Newton's steps, first guesses one level shallower per step
-    d = max(3, d - newton_steps)
     return (1 << d) - 1
 
 
@@ -157,7 +156,7 @@ def newton_invsqrt(ctx, S, y, steps, mask=None, avg=1, tgt=None):
 
 
 def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0), bootstrap=None,
-            debug_stop=-1, stats=None, power=2, newton_steps=0, mask_mode=0):
+            debug_stop=-1, stats=None, power=2, newton_steps=0, mask_mode=0, approx=0, boot_top=None):
     """Softmax of the L = m N0 / n2 vectors packed in the oracle ciphertexts
     xs (m of them, one level and scale, inputs in [-M, 0]); n2 is n rounded
     up to a power of two (the packing's dimension; the extra coordinates are
@@ -167,7 +166,8 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     relinearisation key; the rotation keys of strides +-L 2^t are added
     here.  newton_steps > 0: each inverse square root is the polynomial's
     first guess refined by that many Newton steps (Algorithm SM with squares
-    only).  mask_mode 1: the averaging mask, the factor divided by n2/m on
+    only); 0: by dimension, none up to n = 2048 and two above for Algorithm
+    SM with squares; -1: none.  mask_mode 1: the averaging mask, the factor divided by n2/m on
     every slot instead of the indicator of slots [0, L)."""
     N0 = ctx.slots
     m = len(xs)
@@ -175,7 +175,10 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     assert n >= 2 and n2 <= N0 and n2 % m == 0
     tp = power
     assert tp in (2, 3, 4) and (tp == 2 or variant == 0)
-    assert newton_steps == 0 or (tp == 2 and variant == 0)
+    assert newton_steps <= 0 or (tp == 2 and variant == 0)
+    if newton_steps == 0:
+        newton_steps = 2 if (variant == 0 and tp == 2 and n > 2048) else 0
+    newton_steps = max(newton_steps, 0)
     avg = mask_mode == 1
     tl = 1 if tp == 2 else 2         # levels of y^tp
     L = m * N0 // n2
@@ -257,7 +260,7 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         e = math.ldexp(1.0, -j) if smb_step else (0.5 if tp == 2 else 1.0 / tp)
         deg = inv_degrees[0] if j == 1 else (inv_degrees[2] if last else inv_degrees[1])
         if deg <= 0:
-            deg = default_degree(n, j, last, tp, newton_steps)
+            deg = default_degree(n, j, last, tp)
         if not smb:
             y = [ensure(c, 1 + tl if last else 1 + 2 * tl, ybound) for c in y]
         # auxiliary thread: S = sum of the t-th powers (squares: the tensors
@@ -278,7 +281,11 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         # newton_steps below S; the cube and fourth power variants and
         # Newton's steps also keep 1 + tl levels in lambda
         keep = 2 + tl if (tp != 2 or newton_steps) else 1
-        S = ensure(S, P.depth(deg) + 2 * newton_steps + keep, hi * 1.1)
+        # when that exceeds the level a bootstrapping restores (boot_top),
+        # Newton's first guess is bootstrapped before the steps
+        need_full = P.depth(deg) + 2 * newton_steps + keep
+        refresh = newton_steps > 0 and bootstrap is not None and boot_top is not None and need_full > boot_top
+        S = ensure(S, max(P.depth(deg), 2 * newton_steps + keep + 1) if refresh else need_full, hi * 1.1)
         # the polynomial's interval: [lo, lo + 2^w] (integer affine map); in the
         # last step of SM with squares exactly [lo, hi] when S has the level
         # its affine map takes on top of the polynomial and z = lambda y, z^2
@@ -286,8 +293,13 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             a, b = lo, hi
         else:
             a, b = free_interval(lo, hi)
-        pinv = P.minimax_invpow(a, b, deg, e)
-        delta = newton_delta(rel_error(pinv, a, b, lo, hi, e), newton_steps)
+        if approx == 0:
+            pinv = P.minimax_invpow(a, b, deg, e)
+        else:
+            ee = mpmath.mpf(e)
+            pinv = P.cheb_interp(lambda s: mpmath.power(s, -ee), a, b, deg)
+        delta0 = rel_error(pinv, a, b, lo, hi, e)
+        delta = newton_delta(delta0, newton_steps)
         lam_bound = ((1.0 + delta) / math.sqrt(lo) if newton_steps else max_abs(pinv, a, b, lo, hi)) * 1.05
         pe = [cf / per for cf in pinv] if avg and not newton_steps else pinv
         if avg:
@@ -296,6 +308,10 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             lam = P.eval_cheb(ctx, S, pe, a, b, Delta, log_scale, None if avg else mask)
         else:
             g = P.eval_cheb(ctx, S, pinv, a, b, Delta, log_scale)
+            if refresh:
+                g = ensure(g, 2 * newton_steps + keep, (1.0 + delta0) / math.sqrt(lo) * 1.05)
+                if g.level >= S.level:
+                    g = P.drop(ctx, g, S.level - 1)
             lam = newton_invsqrt(ctx, S, g, newton_steps, None if avg else mask, per if avg else 1, Delta)
         if not smb_step:
             need_next = 1 + tl if j + 1 == k else 1 + 2 * tl

@@ -833,6 +833,7 @@ static hs::SoftmaxOpts softmax_opts(const hs_softmax_opts* opts) {
         if (opts->power > 0) o.power = opts->power;
         o.newton_steps = opts->newton_steps;
         o.mask_mode = opts->mask_mode;
+        o.approx = opts->approx;
     }
     return o;
 }

@@ -147,6 +147,10 @@ ChebPoly minimax_invpow(double a, double b, int d, double e) {
     std::vector<ld> r(G);
     for (int it = 0; it < 40; it++) {
         const std::vector<ld> c = reference_solve<ld>(ref, d, G, a, b, (ld)e, pi, cos_ld, pow_ld, fabs_ld);
+        // levelled error below 2^-40: far below any ciphertext's precision,
+        // and near the 80-bit rounding of r, where the exchange would follow
+        // rounding noise
+        if (fabs_ld(c[d + 1]) < 0x1p-40L) break;
         for (int i = 0; i < G; i++) {
             // Clenshaw
             ld b1 = 0, b2 = 0;
@@ -179,11 +183,20 @@ ChebPoly minimax_invpow(double a, double b, int d, double e) {
     }
     // final solve at the reference in binary128
     const std::vector<quad> cq = reference_solve<quad>(ref, d, G, a, b, (quad)e, M_PIq, cos_q, pow_q, fabs_q);
+    // every coefficient to the nearest multiple of the largest one's double
+    // ulp 2^(E - 52), 2^E <= max |c_j| < 2^(E+1): coefficients far below the
+    // largest are then as reproducible as the largest (the high-order ones of
+    // a near-exact fit are otherwise at the solve's rounding level)
+    quad cmax = 0;
+    for (int j = 0; j <= d; j++) cmax = std::max(cmax, fabs_q(cq[j]));
+    int E = 0;
+    frexpq(cmax, &E);   // cmax = f 2^E, f in [0.5, 1)
+    const int sh = (E - 1) - 52;
     ChebPoly p;
     p.a = a;
     p.b = b;
     p.c.resize(d + 1);
-    for (int j = 0; j <= d; j++) p.c[j] = (double)cq[j];
+    for (int j = 0; j <= d; j++) p.c[j] = (double)(rintq(ldexpq(cq[j], -sh)) * ldexpq(1, sh));
     std::lock_guard<std::mutex> g(mu);
     cache[key] = p;
     return p;

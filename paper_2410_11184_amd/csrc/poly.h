@@ -28,9 +28,12 @@ ChebPoly cheb_fit(const std::function<quad(quad)>& f, double a, double b, int de
 // sum_j c_j T_j(u_k) + (-1)^k h / w_k = 1 / w_k (w = s^e), takes in every
 // run of equal sign of r = w P - 1 on the grid the index of the largest |r|
 // (the first on ties), drops end candidates (the one with the smaller |r|,
-// the last on ties) down to d + 2, and stops when fewer remain or the
-// reference repeats; the coefficients are those of the final reference
-// system solved in binary128, rounded to double.  Cached per (a, b, d, e).
+// the last on ties) down to d + 2, and stops when fewer remain, the
+// reference repeats, or the levelled error |h| of the round's system is
+// below 2^-40 (then before the exchange); the coefficients are those of the
+// final reference
+// system solved in binary128, each rounded to the nearest multiple of
+// 2^(E - 52), 2^E <= max_j |c_j| < 2^(E+1).  Cached per (a, b, d, e).
 ChebPoly minimax_invpow(double a, double b, int d, double e);
 double cheb_eval_plain(const ChebPoly& p, double x);
 int cheb_depth(int degree);   // levels used by eval_cheb (plus 1 if the affine map needs one)

@@ -315,15 +315,21 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     HS_REQUIRE(M > 0, E_ARG, "range M must be positive");
     HS_REQUIRE(x.ncomp == 2, E_ARG, "degree-1 ciphertexts expected");
     const bool smb = o.variant == 1;
-    HS_REQUIRE(o.newton_steps >= 0 && o.newton_steps <= 8, E_PARAM, "Newton steps must be in 0..8");
+    HS_REQUIRE(o.newton_steps >= -1 && o.newton_steps <= 8, E_PARAM, "Newton steps must be in -1..8");
     HS_REQUIRE(o.mask_mode == 0 || o.mask_mode == 1, E_PARAM, "mask mode must be 0 or 1");
     const bool avg = o.mask_mode == 1;
     // normalize-and-t-th-power (t = 2: normalize-and-square)
     const int tp = o.power > 0 ? o.power : 2;
     HS_REQUIRE(tp >= 2 && tp <= 4, E_PARAM, "power must be 2, 3 or 4");
+    HS_REQUIRE(o.approx == 0 || o.approx == 1, E_PARAM, "approx must be 0 (minimax) or 1 (interpolation)");
     HS_REQUIRE(tp == 2 || !smb, E_PARAM, "version B normalizes with squares (power 2)");
-    HS_REQUIRE(o.newton_steps == 0 || (tp == 2 && !smb), E_PARAM,
+    HS_REQUIRE(o.newton_steps <= 0 || (tp == 2 && !smb), E_PARAM,
                "Newton's iteration computes inverse square roots: Algorithm SM with squares");
+    // Newton's steps: as asked; by default none up to n = 2048 and, above,
+    // two for Algorithm SM with squares (where a degree-255 polynomial alone
+    // leaves a relative error near 2^-5 on [~1/n, 1], each step squares it)
+    const int nsteps = o.newton_steps > 0 ? o.newton_steps
+                       : (o.newton_steps == 0 && !smb && tp == 2 && n > 2048 ? 2 : 0);
     const int tl = tp == 2 ? 1 : 2;         // levels of y^tp
     const int L = (int)((long long)m * N0 / np2);
     // Theorem "th:prec_softmax"'s k (M / t^k ~ ln n for the t-th power
@@ -399,8 +405,6 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             else if (n <= 256) d = j == 1 ? 6 : (last ? 7 : 5);
             else if (n <= 1024) d = last ? 8 : 6;
             else d = last ? 8 : 7;
-            // with Newton's steps, first guesses one level shallower per step
-            d = std::max(3, d - o.newton_steps);
             deg = (1 << d) - 1;
         }
         // main thread: this iteration's z = lambda y and z^t (1 + tl levels),
@@ -434,15 +438,20 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             ct_free(c, rr);
         }
         // budget of the normalisation polynomial (mask folded into its leaves,
-        // or into the last Newton step)
+        // or into the last Newton step): lambda lands cheb_depth (+ 1 when
+        // the affine map takes a level) + 2 nsteps below S; the cube and
+        // fourth power variants and Newton's steps also keep 1 + tl levels in
+        // lambda for z = lambda y and z^t.  When that exceeds the level a
+        // bootstrapping restores, Newton's first guess P(S) is bootstrapped
+        // itself before the steps (S then needs the polynomial's depth and,
+        // one level above the guess, the steps' levels)
+        const int keep = (tp != 2 || nsteps) ? 2 + tl : 1;
+        const int need_full = cheb_depth(deg) + 2 * nsteps + keep;
+        const bool refresh = nsteps > 0 && can_bootstrap(c) && need_full > c.prm.user_top;
         {
-            // lambda lands cheb_depth (+ 1 when the affine map takes a
-            // level) + 2 nsteps below S; the cube and fourth power variants
-            // and Newton's steps also keep 1 + tl levels in lambda for
-            // z = lambda y and z^t
-            const int keep = (tp != 2 || o.newton_steps) ? 2 + tl : 1;
+            const int needS = refresh ? std::max(cheb_depth(deg), 2 * nsteps + keep + 1) : need_full;
             bool rep;
-            Ct S2 = ensure_level(c, S, cheb_depth(deg) + 2 * o.newton_steps + keep, hi * 1.1, st, rep, "S", j);
+            Ct S2 = ensure_level(c, S, needS, hi * 1.1, st, rep, "S", j);
             if (rep) {
                 ct_free(c, S);
                 S = S2;
@@ -455,7 +464,6 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // top of the polynomial and the final z = lambda y, y = z^2 (about 4
         // bits of precision at n = 256: the wider interval spends the
         // approximation on values S never takes)
-        const int nsteps = o.newton_steps;
         double a, b;
         if (last && tp == 2 && !nsteps && S.level >= cheb_depth(deg) + 3) {
             a = lo;
@@ -463,9 +471,13 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         } else {
             free_interval(lo, hi, a, b);
         }
-        // the paper's weighted minimax approximant: smallest max |P(s) s^e - 1|
-        ChebPoly pinv = minimax_invpow(a, b, deg, e);
-        const double delta = newton_delta(rel_error(pinv, lo, hi, e), nsteps);
+        // the paper's weighted minimax approximant (smallest max |P(s) s^e - 1|),
+        // or the Chebyshev interpolant
+        const quad eq = e;
+        ChebPoly pinv = o.approx == 0 ? minimax_invpow(a, b, deg, e)
+                                      : cheb_fit([&](quad s) { return powq(s, -eq); }, a, b, deg);
+        const double delta0 = rel_error(pinv, lo, hi, e);
+        const double delta = newton_delta(delta0, nsteps);
         double lam_bound = (nsteps ? (1.0 + delta) / std::sqrt(lo) : max_abs(pinv, lo, hi)) * 1.05;
         // the averaging mask: per copies of the factor, each divided by per,
         // summed by the broadcast (the division folded into the coefficients
@@ -481,6 +493,20 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             lam = eval_cheb(c, S, pe, Delta, avg ? nullptr : mask);
         } else {
             Ct g = eval_cheb(c, S, pinv, Delta);
+            if (refresh) {
+                bool rep;
+                Ct g2 = ensure_level(c, g, 2 * nsteps + keep, (1.0 + delta0) / std::sqrt(lo) * 1.05, st, rep,
+                                     "guess", j);
+                if (rep) {
+                    ct_free(c, g);
+                    g = g2;
+                }
+                if (g.level >= S.level) {
+                    Ct gd = ct_drop(c, g, S.level - 1);
+                    ct_free(c, g);
+                    g = gd;
+                }
+            }
             lam = newton_invsqrt(c, S, g, nsteps, avg ? nullptr : mask, avg ? per : 1, Delta);
             ct_free(c, g);
         }

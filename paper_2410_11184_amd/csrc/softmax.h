@@ -17,6 +17,7 @@ struct SoftmaxOpts {
     int power = 2;            // t of normalize-and-t-th-power (2, 3, 4; version B: 2)
     int newton_steps = 0;     // > 0: inverse roots by that many Newton steps from the polynomial
     int mask_mode = 0;        // 0: indicator of slots [0, L); 1: averaging (m / n on every slot)
+    int approx = 0;           // normalisation polynomials: 0 weighted minimax, 1 Chebyshev interpolants
 };
 
 struct SoftmaxStats {

@@ -72,7 +72,7 @@ def test_stages_match_the_oracle(pair, level):
     assert np.max(np.abs(g.decrypt(gy) - z)) < 2.0 ** -22
 
 
-@pytest.mark.parametrize("variant", [0, 1, "newton"])
+@pytest.mark.parametrize("variant", [0, 1, "newton", "newton-refresh"])
 def test_softmax_with_bootstraps_matches_the_oracle(variant):
     from paper_2410_11184_amd import hs
     from oracle import ckks, schedule, softmax as S
@@ -84,11 +84,15 @@ def test_softmax_with_bootstraps_matches_the_oracle(variant):
     o.keygen(SEED + 1)
     bs = Bootstrapper(o, p["boot"], p["user_top"], p["log_scale"])
     # "newton": Algorithm SM at n = 32, M = 32, degree-15 first guesses and one
-    # Newton step per inverse square root, bootstraps between
-    kw = dict(inv_degrees=(15, 15, 15), newton_steps=1) if variant == "newton" else {}
-    n, M, m = (32, 32.0, 1) if variant == "newton" else (16, 8.0, 1)
-    seed_off = 2 if variant == "newton" else variant
-    variant = 0 if variant == "newton" else variant
+    # Newton step per inverse square root, bootstraps between; "newton-refresh":
+    # degree-31 guesses, whose depth plus the step's levels exceed the 10
+    # levels a bootstrapping restores, so each guess is bootstrapped itself
+    # before its Newton step
+    nw = str(variant).startswith("newton")
+    kw = dict(inv_degrees=(31, 31, 31) if variant == "newton-refresh" else (15, 15, 15), newton_steps=1) if nw else {}
+    n, M, m = (32, 32.0, 1) if nw else (16, 8.0, 1)
+    seed_off = {"newton": 2, "newton-refresh": 3}.get(variant, variant)
+    variant = 0 if nw else variant
     L = m * o.slots // n
     x = synthetic.logits_uniform(L, n, M, seed=61 + seed_off)
     packed = S.pack(x, m, o.slots)
@@ -99,7 +103,8 @@ def test_softmax_with_bootstraps_matches_the_oracle(variant):
     gst = g.softmax_stats()
     st = {}
     oy = schedule.softmax(o, ox, n, M, variant=variant,
-                          bootstrap=lambda c, bound, mask_L: bs.bootstrap(c, bound, mask_L), stats=st, **kw)
+                          bootstrap=lambda c, bound, mask_L: bs.bootstrap(c, bound, mask_L), stats=st,
+                          boot_top=p["user_top"], **kw)
     assert gst["bootstraps"] == st["bootstraps"] > 0, (gst, st)
     _close(g, o, gy[0], oy[0], "softmax output", tol=2.0 ** -24)
     y = S.unpack(np.stack([g.decrypt(gy[0]).real]), n)

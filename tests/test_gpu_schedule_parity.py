@@ -137,3 +137,19 @@ def test_input_one_rescale_above_matches_oracle(pair, variant):
     _compare(g, o, gy, oy, "output")
     y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy]), n)
     assert S.precision_bits(S.softmax(x), y)["worst"] >= 16.0
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_interpolated_normalisation_matches_oracle(pair, variant):
+    # approx = 1: Chebyshev interpolants instead of the weighted minimax
+    # approximants for the normalisation polynomials
+    from oracle import schedule, softmax as S
+    g, o = pair
+    n, M, m = 16, 8.0, 2
+    x, gx, ox = _inputs(g, o, n, M, m, seed=780 + variant)
+    kw = dict(variant=variant, exp_degree=7, inv_degrees=(15, 15, 31), approx=1)
+    gy = g.softmax(gx, n, M, **kw)
+    oy = schedule.softmax(o, ox, n, M, **kw)
+    _compare(g, o, gy, oy, "output")
+    y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy]), n)
+    assert S.precision_bits(S.softmax(x), y)["worst"] >= 16.0
