@@ -598,10 +598,13 @@ def main():
         cp1 = encrypt_logits(ctx, xp1, M, seed=9102)
         trade = [row("SM-B, indicator mask", cts, L, x, variant=1),
                  row("SM-B, averaging mask", cts, L, x, variant=1, mask_mode=1),
+                 row("SM-B, Chebyshev interpolants", cts, L, x, variant=1, approx=1),
                  row("SM, indicator mask", cts, L, x, variant=0),
                  row("SM, 1 ciphertext", cp1, p["slots"] // n, xp1, variant=0),
                  row("SM, 1 ciphertext, Newton x1 from degrees 31/31/63", cp1, p["slots"] // n, xp1, variant=0,
                      newton_steps=1, inv_degrees=(31, 31, 63)),
+                 row("SM, 1 ciphertext, Newton x2 from the default degrees", cp1, p["slots"] // n, xp1, variant=0,
+                     newton_steps=2),
                  row("SM, 1 ciphertext, averaging mask", cp1, p["slots"] // n, xp1, variant=0, mask_mode=1)]
 
     plain = None
@@ -667,7 +670,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": ring_desc(p) + ", m=64 ciphertexts, 8192 Softmax of dim 256, logits U[-128,0], "
-                               "SM version B, k=%d, aux bootstraps per job=%d, %s schedule" %
+                               "SM version B (last iteration as an SM step), k=%d, aux bootstraps per job=%d, "
+                               "%s schedule" %
                                (stats["k"], stats["bootstraps"], "HIP-graph" if graph else "eager"),
                    "global_batch": L, "seq_len": n, "parallelism": "single-gpu"},
         "precision_bits": bits,
