@@ -467,6 +467,7 @@ void Context::init() {
         pinfo[t].q = qt;
         pinfo[t].bits = b;
         pinfo[t].mu = (u64)(((u128)1 << (2 * b)) / qt);
+        pinfo[t].nq = 0 - qt;
         psi[t] = smallest_psi(qt, N);
         const u64 pinv = invmod_h(psi[t], qt);
         // powers by bit-reversed exponent

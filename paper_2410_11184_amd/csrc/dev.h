@@ -17,6 +17,7 @@ struct PrimeInfo {
     u64 mu;
     int bits;
     int pad;
+    u64 nq;   // 2^64 - q: a w - h q = a w + h nq (mod 2^64), one multiply-add chain
 };
 
 // Per-launch timing with HIP events (off unless enabled): each profiled

@@ -376,11 +376,11 @@ __device__ __forceinline__ int ntt_row(const Rows& x, int y, int order, const Nt
 // any a < 2^64, so forward values are kept in [0, 4q) and inverse values in
 // [0, 2q) (4q < 2^63 for q < 2^61) and reduced once at the end of the
 // transform; between the two passes the rows hold these unreduced values.
-__device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
-    return a * w - __umul64hi(a, ws) * q;
+__device__ __forceinline__ u64 mul_shoup_lazy(u64 a, u64 w, u64 ws, u64 nq) {
+    return a * w + __umul64hi(a, ws) * nq;
 }
 
-__device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q) {
+__device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q, u64 nq) {
     ulonglong2 W[15];
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -398,7 +398,7 @@ __device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 ba
                 const int k = g * 2 * h + j;
                 u64 u = E[k];
                 u = u >= q2 ? u - q2 : u;
-                const u64 v = mul_shoup_lazy(E[k + h], w.x, w.y, q);
+                const u64 v = mul_shoup_lazy(E[k + h], w.x, w.y, nq);
                 E[k] = u + v;
                 E[k + h] = u - v + q2;
             }
@@ -406,7 +406,7 @@ __device__ __forceinline__ void fwd16(u64 (&E)[16], const ulonglong2* tw, u32 ba
     }
 }
 
-__device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q) {
+__device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 base, u64 q, u64 nq) {
     ulonglong2 W[15];
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -425,7 +425,7 @@ __device__ __forceinline__ void inv16(u64 (&E)[16], const ulonglong2* tw, u32 ba
                 const u64 u = E[k], v = E[k + h];
                 const u64 s = u + v;
                 E[k] = s >= q2 ? s - q2 : s;
-                E[k + h] = mul_shoup_lazy(u - v + q2, w.x, w.y, q);
+                E[k + h] = mul_shoup_lazy(u - v + q2, w.x, w.y, nq);
             }
         }
     }
@@ -459,6 +459,7 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
     const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * 16;
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
+    const u64 nq = T.prime[pi].nq;
     const int t = threadIdx.x, c = t & 15, hl = t >> 4;
     u64 E[16];
     if (!inverse) {
@@ -474,14 +475,14 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
 #pragma unroll
             for (int hi = 0; hi < 16; hi++) E[hi] = ps[(size_t)(hi * 16 + hl) * 256 + c];
         }
-        fwd16(E, tw, 1, q);
+        fwd16(E, tw, 1, q, nq);
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) sm[hi * 272 + hl * 16 + c] = E[hi];
         __syncthreads();
         // thread (hi = hl, c): lo = 0..15, stages 4..7
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) E[lo] = sm[hl * 272 + lo * 16 + c];
-        fwd16(E, tw, 16 + hl, q);
+        fwd16(E, tw, 16 + hl, q, nq);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) p[(size_t)(hl * 16 + lo) * 256 + c] = E[lo];
     } else {
@@ -489,14 +490,14 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
         // thread (hi = hl, c): lo = 0..15, stages 7..4
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) E[lo] = ps[(size_t)(hl * 16 + lo) * 256 + c];
-        inv16(E, tw, 16 + hl, q);
+        inv16(E, tw, 16 + hl, q, nq);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) sm[hl * 272 + lo * 16 + c] = E[lo];
         __syncthreads();
         // thread (lo = hl, c): hi = 0..15, stages 3..0, then N^-1
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) E[hi] = sm[hi * 272 + hl * 16 + c];
-        inv16(E, tw, 1, q);
+        inv16(E, tw, 1, q, nq);
         const u64 ni = T.ninv[2 * pi], nis = T.ninv[2 * pi + 1];
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) p[(size_t)(hi * 16 + hl) * 256 + c] = mul_shoup(E[hi], ni, nis, q);
@@ -513,6 +514,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     if (row < 0) return;   // whole workgroup
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
+    const u64 nq = T.prime[pi].nq;
     const int t = threadIdx.x, w = t >> 4, l = t & 15;
     const u32 R = blockIdx.x * 16 + w;             // chunk index
     u64* p = row_ptr(x, row, 65536) + (size_t)R * 256;
@@ -524,14 +526,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int hi = 0; hi < 16; hi++) E[hi] = ps[hi * 16 + l];
     if (!inverse) {
-        fwd16(E, tw, 256 + R, q);                   // stages 8..11
+        fwd16(E, tw, 256 + R, q, nq);                   // stages 8..11
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) s[hi * 17 + l] = E[hi];
         __syncthreads();
         // thread (w, hi = l): lo = 0..15, stages 12..15 (in place in LDS)
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) E[lo] = s[l * 17 + lo];
-        fwd16(E, tw, 4096 + R * 16 + l, q);
+        fwd16(E, tw, 4096 + R * 16 + l, q, nq);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) s[l * 17 + lo] = E[lo];
         __syncthreads();
@@ -562,14 +564,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         // thread (w, hi = l): lo = 0..15, stages 15..12
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) E[lo] = s[l * 17 + lo];
-        inv16(E, tw, 4096 + R * 16 + l, q);
+        inv16(E, tw, 4096 + R * 16 + l, q, nq);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) s[l * 17 + lo] = E[lo];
         __syncthreads();
         // thread (w, lo = l): hi = 0..15, stages 11..8
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) E[hi] = s[hi * 17 + l];
-        inv16(E, tw, 256 + R, q);
+        inv16(E, tw, 256 + R, q, nq);
 #pragma unroll
         for (int hi = 0; hi < 16; hi++) p[hi * 16 + l] = E[hi];
     }
