@@ -58,3 +58,39 @@ def softmax_jobs_encrypted(ctx, logits_list, M, variant="B", seed=1, k=0, exp_de
         res.append(decrypt_outputs(ctx, out[o:o + cnt], n))
         o += cnt
     return res
+
+
+def softmax_groups(runs):
+    """Softmax calls of different shapes at once (an uneven batch): `runs` is
+    a list of (context, ciphertexts, n, M, options), each context on a HIP
+    stream of its own (a context and its clones, hs_ctx_clone, share one key
+    set), each call's ciphertexts encrypted by its context.  Every call runs
+    in a host thread of its own, so the GPU overlaps the groups' launches
+    (the small launches of one group's single-ciphertext auxiliary thread
+    fill what another group leaves idle); a call with options jobs=J runs J
+    same-shape jobs in lockstep.  Every operation acts per ciphertext and per
+    context, so each call's outputs are the words it gives alone.  Returns
+    [(outputs, stats)] in order; the first error raised by a call is raised
+    here after every thread has ended."""
+    import threading
+    res = [None] * len(runs)
+    errs = [None] * len(runs)
+
+    def work(i):
+        ctx, cts, n, M, kw = runs[i]
+        try:
+            out = ctx.softmax(cts, n, M, **kw)
+            ctx.sync()
+            res[i] = (out, ctx.softmax_stats())
+        except BaseException as e:   # re-raised in the caller's thread
+            errs[i] = e
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(runs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for e in errs:
+        if e is not None:
+            raise e
+    return res

@@ -2,7 +2,9 @@
 a clone on another stream computes the same words as its parent, holds no
 copy of the parent's keys, generates keys the parent lacks into its own
 memory, refuses key generation on both sides while it lives, and keeps
-working after its parent's handle is destroyed."""
+working after its parent's handle is destroyed; an uneven batch (groups of
+different shapes run at once on a context and its clone, softmax_groups)
+gives each group the words it gives alone."""
 import numpy as np
 import pytest
 
@@ -65,4 +67,42 @@ def test_clone_shares_keys_and_computes_the_same_words():
     assert np.max(np.abs(dec - z * z[::-1])) < 1e-6
     del a, b, prod, rot, r_clone, again
     clone.close()
+    hs.stream_destroy(st)
+
+
+TOY = dict(exp_degree=7, inv_degrees=(15, 15, 31))
+
+
+def test_uneven_groups_at_once_equal_each_alone():
+    from paper_2410_11184_amd import hs
+    from paper_2410_11184_amd.softmax import encrypt_logits, softmax_groups
+    from oracle import softmax as S
+    p = synthetic.preset("toy12")
+    parent = hs.Context(p)
+    parent.keygen(SEED + 7)
+    st = hs.stream_create(0)
+    clone = parent.clone(st)
+    # group A: 3 jobs of dimension 16 (version B, 2 ciphertexts each, lockstep);
+    # group B: one job of dimension 8 (Algorithm SM, 1 ciphertext)
+    xa = [synthetic.logits_uniform(2 * p["slots"] // 16, 16, 8.0, seed=820 + j) for j in range(3)]
+    xb = synthetic.logits_uniform(p["slots"] // 8, 8, 8.0, seed=830)
+    kw_a = dict(variant=1, jobs=3, **TOY)
+    kw_b = dict(variant=0, **TOY)
+    ca = [c for j, x in enumerate(xa) for c in encrypt_logits(parent, x, 8.0, seed=840 + 10 * j)]
+    cb = encrypt_logits(clone, xb, 8.0, seed=850)
+    alone_a = [c.export() for c in parent.softmax(ca, 16, 8.0, **kw_a)]
+    alone_b = [c.export() for c in clone.softmax(cb, 8, 8.0, **kw_b)]
+    (out_a, st_a), (out_b, st_b) = softmax_groups([(parent, ca, 16, 8.0, kw_a), (clone, cb, 8, 8.0, kw_b)])
+    for got, want in ((out_a, alone_a), (out_b, alone_b)):
+        assert len(got) == len(want)
+        for g, w in zip(got, want):
+            e = g.export()
+            assert np.array_equal(e[0], w[0]) and np.array_equal(e[1], w[1])
+    ya = [S.unpack(np.stack([parent.decrypt(c).real for c in out_a[2 * j:2 * j + 2]]), 16) for j in range(3)]
+    yb = S.unpack(np.stack([clone.decrypt(c).real for c in out_b]), 8)
+    for x, y in zip(xa + [xb], ya + [yb]):
+        assert S.precision_bits(S.softmax(x), y)["worst"] >= 12.0
+    del out_a, out_b, ca, cb
+    clone.close()
+    parent.close()
     hs.stream_destroy(st)

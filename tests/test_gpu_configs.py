@@ -13,9 +13,10 @@
   twelve user levels leave at k = 6; 8 ciphertexts, 1024 Softmax);
 * a small serving mix at full size (dimensions 256, 4096 and 32768, two
   workers): each result the same alone and in the mix, the batches of the
-  two workers overlapping in time, and the precision of each dimension
-  (>= 16 bits at 256; the larger dimensions at the precision their
-  polynomials reach, reported)."""
+  two workers overlapping in time, and the precision of each dimension;
+* large dimensions (8192 and 32768, Algorithm SM on 8 ciphertexts, two
+  Newton steps per inverse square root by default): >= 16 bits, and without
+  the steps the bound their degree-255 polynomials leave."""
 import numpy as np
 import pytest
 
@@ -128,3 +129,26 @@ def test_variants_at_full_size(ctx, case):
     # Newton (first guesses of degrees 31 / 31 / 63, one step each) is a
     # trade study: reported, held to 12 bits
     assert bits["worst"] >= (12.0 if nw else 16.0), bits
+
+
+@pytest.mark.parametrize("n", [8192, 32768])
+def test_large_dimensions(ctx, n):
+    # above n = 2048 the last normalisation polynomial (degree 255, the most
+    # the levels allow) cannot resolve [~1/n, 1]; two Newton steps from it,
+    # the first guess bootstrapped when the levels run short, square its
+    # error twice (measured 19.7 and 17.7 bits)
+    from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
+    M = 256.0 if n == 32768 else 128.0
+    m = 8
+    L = m * ctx.slots // n
+    x = synthetic.logits_uniform(L, n, M, seed=6000 + n)
+    cts = encrypt_logits(ctx, x, M, seed=6100 + n)
+    print("large dimension: n=%d, %d vectors in %d ciphertexts" % (n, L, m), flush=True)
+    y = decrypt_outputs(ctx, ctx.softmax(cts, n, M, variant=0), n)
+    bits = S.precision_bits(S.softmax(x), y)
+    print("n=%d: %s, stats %s" % (n, bits, ctx.softmax_stats()))
+    assert bits["worst"] >= 16.0, bits
+    y1 = decrypt_outputs(ctx, ctx.softmax(cts, n, M, variant=0, newton_steps=-1), n)
+    b1 = S.precision_bits(S.softmax(x), y1)
+    print("n=%d without Newton's steps: %s" % (n, b1))
+    assert b1["worst"] < bits["worst"] - 4.0, (b1, bits)
