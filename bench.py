@@ -351,12 +351,15 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fgb16_smb64")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured schedule")
+    ap.add_argument("--in-flight", type=int, default=2,
+                    help="batches in flight at once, each on its own stream (a context clone sharing the keys); "
+                         "1 = one batch at a time")
     ap.add_argument("--lockstep", type=int, default=0,
                     help="also time J jobs of the metric's shape in one lockstep schedule")
     ap.add_argument("--sweep", action="store_true",
@@ -475,6 +478,64 @@ def main():
     bits = S.precision_bits(S.softmax(x), y)
     _log("batched (%s): %.2f ms/step, %.1f calls/s, precision %s" %
          ("graph" if graph else "eager", ms_step, value, bits))
+    single = {"calls_per_s": value, "ms_per_step": ms_step}
+
+    in_flight = None
+    if args.in_flight > 1:
+        # the same K steps with S batches in flight: S contexts (this one and
+        # clones sharing its keys), each on its own stream with its own copy
+        # of the batch (same words: same keys and seed) and its own captured
+        # schedule, driven by one host thread each; rounds of S concurrent
+        # steps until K steps are done
+        import threading
+        S_ = args.in_flight
+        fl_streams = [hs.stream_create(0) for _ in range(S_ - 1)]
+        fl_ctxs = [ctx] + [ctx.clone(s_) for s_ in fl_streams]
+        fl_cts = [cts] + [encrypt_logits(c_, x, M, seed=3002) for c_ in fl_ctxs[1:]]
+        from paper_2410_11184_amd.softmax import softmax_groups
+        softmax_groups([(c_, ct_, n, M, dict(variant=variant)) for c_, ct_ in zip(fl_ctxs[1:], fl_cts[1:])])
+        if graph:
+            fl_plans = [plan] + [c_.softmax_plan(ct_, n, M, variant=variant) for c_, ct_ in zip(fl_ctxs[1:], fl_cts[1:])]
+            fl_step = [lambda i=i: fl_plans[i].run(fl_cts[i]) for i in range(S_)]
+        else:
+            fl_step = [lambda i=i: fl_ctxs[i].softmax(fl_cts[i], n, M, variant=variant) for i in range(S_)]
+        outs = [None] * S_
+
+        def fl_run(i):
+            outs[i] = fl_step[i]()
+            fl_ctxs[i].sync()
+
+        def fl_round(k):
+            th = [threading.Thread(target=fl_run, args=(i,)) for i in range(k)]
+            for t_ in th:
+                t_.start()
+            for t_ in th:
+                t_.join()
+
+        fl_round(S_)                   # warm: every plan replayed once
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.steps:
+            k_ = min(S_, args.steps - done)
+            fl_round(k_)
+            done += k_
+            _log("in flight: %d steps done" % done)
+        torch.cuda.synchronize()
+        fl_elapsed = time.perf_counter() - t0
+        same = all(np.array_equal(a.export(), b.export()) for a, b in zip(outs[0][:4], out[:4]))
+        same_clone = all(np.array_equal(a.export(), b.export()) for a, b in zip(outs[-1][:4], out[:4]))
+        in_flight = {"batches": S_, "calls_per_s": L * args.steps / fl_elapsed,
+                     "ms_per_step": 1e3 * fl_elapsed / args.steps,
+                     "outputs_equal_one_at_a_time": bool(same and same_clone)}
+        _log("in flight %d: %.2f ms/step, %.1f calls/s, same words %s" %
+             (S_, in_flight["ms_per_step"], in_flight["calls_per_s"], in_flight["outputs_equal_one_at_a_time"]))
+        if graph:
+            for pl_ in fl_plans[1:]:
+                pl_.close()
+        del outs
+        value = in_flight["calls_per_s"]
+        ms_step = in_flight["ms_per_step"]
 
     # per-kernel durations: the same schedule launched eagerly with an event
     # pair around every launch (graph replays carry no per-kernel events)
@@ -675,12 +736,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": ring_desc(p) + ", m=64 ciphertexts, 8192 Softmax of dim 256, logits U[-128,0], "
                                "SM version B (last iteration as an SM step), k=%d, aux bootstraps per job=%d, "
-                               "%s schedule" %
-                               (stats["k"], stats["bootstraps"], "HIP-graph" if graph else "eager"),
+                               "%s schedule, %d batch(es) in flight on their own streams" %
+                               (stats["k"], stats["bootstraps"], "HIP-graph" if graph else "eager",
+                                in_flight["batches"] if in_flight else 1),
                    "global_batch": L, "seq_len": n, "parallelism": "single-gpu"},
         "precision_bits": bits,
+        "one_at_a_time": single,
+        "in_flight": in_flight,
         "plain": plain,
-        "speedup_vs_plain": (value / plain["calls_per_s"]) if plain else None,
+        # one batch at a time against the plain form, also one at a time
+        "speedup_vs_plain": (single["calls_per_s"] / plain["calls_per_s"]) if plain else None,
         "sm_many_ciphertext": sm_many,
         "trade_study": trade,
         "lockstep_jobs": lockstep,
