@@ -351,7 +351,7 @@ def run_serve(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fgb16_smb64")
     ap.add_argument("--no-plain", action="store_true")
@@ -485,8 +485,8 @@ def main():
         # the same K steps with S batches in flight: S contexts (this one and
         # clones sharing its keys), each on its own stream with its own copy
         # of the batch (same words: same keys and seed) and its own captured
-        # schedule, driven by one host thread each; rounds of S concurrent
-        # steps until K steps are done
+        # schedule, driven by one host thread each, which runs its share of
+        # the K steps back to back (steps i, i + S, i + 2S, ...)
         import threading
         S_ = args.in_flight
         fl_streams = [hs.stream_create(0) for _ in range(S_ - 1)]
@@ -501,28 +501,25 @@ def main():
             fl_step = [lambda i=i: fl_ctxs[i].softmax(fl_cts[i], n, M, variant=variant) for i in range(S_)]
         outs = [None] * S_
 
-        def fl_run(i):
-            outs[i] = fl_step[i]()
-            fl_ctxs[i].sync()
+        def fl_run(i, k):
+            for _ in range(k):
+                outs[i] = fl_step[i]()
+                fl_ctxs[i].sync()
 
-        def fl_round(k):
-            th = [threading.Thread(target=fl_run, args=(i,)) for i in range(k)]
+        def fl_all(shares):
+            th = [threading.Thread(target=fl_run, args=(i, k)) for i, k in enumerate(shares) if k]
             for t_ in th:
                 t_.start()
             for t_ in th:
                 t_.join()
 
-        fl_round(S_)                   # warm: every plan replayed once
+        fl_all([1] * S_)               # warm: every plan replayed once
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        done = 0
-        while done < args.steps:
-            k_ = min(S_, args.steps - done)
-            fl_round(k_)
-            done += k_
-            _log("in flight: %d steps done" % done)
+        fl_all([len(range(i, args.steps, S_)) for i in range(S_)])
         torch.cuda.synchronize()
         fl_elapsed = time.perf_counter() - t0
+        _log("in flight: %d steps done" % args.steps)
         same = all(np.array_equal(a.export(), b.export()) for a, b in zip(outs[0][:4], out[:4]))
         same_clone = all(np.array_equal(a.export(), b.export()) for a, b in zip(outs[-1][:4], out[:4]))
         in_flight = {"batches": S_, "calls_per_s": L * args.steps / fl_elapsed,
