@@ -377,12 +377,17 @@ class Context:
     def key_switch(self, d, level, key):
         """Hybrid key switching of the NTT-domain polynomial d (level+1 limbs).
         Returns (u0, u1) over q[0..level]."""
+        return self.inner_mod_down(self.mod_up(d, level), level, key)
+
+    def inner_mod_down(self, exts, level, key):
+        """The rest of key switching after ModUp: the digits' inner product
+        with the switching key over Q_level u P, then ModDown of both sums."""
         nq_l = level + 1
         p_idx = list(range(len(self.q), len(self.primes)))
         ext_idx = list(range(nq_l)) + p_idx
         acc0 = {t: np.zeros(self.N, dtype=np.uint64) for t in ext_idx}
         acc1 = {t: np.zeros(self.N, dtype=np.uint64) for t in ext_idx}
-        for j, ext in enumerate(self.mod_up(d, level)):
+        for j, ext in enumerate(exts):
             bj, aj = key[j]
             for r, t in enumerate(ext_idx):
                 acc0[t] = self.add(acc0[t], self.mul(ext[r], bj[t], t), t)
@@ -454,6 +459,27 @@ class Context:
 
     def conjugate(self, a):
         return self.apply_galois(a, 2 * self.N - 1)
+
+    def rotate_hoisted(self, a, rots):
+        """Rotations of one ciphertext by several offsets with one ModUp
+        (hoisting, Halevi-Shoup): the ModUp digits of c1 are formed once; for
+        each offset the automorphism, an NTT-domain permutation of the
+        coefficients' evaluations, is applied to every extended row of every
+        digit and to c0, followed by the inner product with that offset's key
+        and ModDown.  The approximate base conversion does not commute
+        exactly with the automorphism (a negated coefficient converts to a
+        different multiple of the digit's modulus), so the words differ from
+        rotate()'s while the values agree."""
+        level = a.level
+        exts = self.mod_up(a.c[1], level)
+        out = []
+        for r in rots:
+            g = self.galois_rot(r, self.N)
+            perm = self.automorph_perm(g)
+            u0, u1 = self.inner_mod_down([e[:, perm] for e in exts], level, self.keys[g])
+            c0 = np.stack([self.add(a.c[0][i][perm], u0[i], i) for i in range(level + 1)])
+            out.append(Ciphertext([c0, u1], level, a.scale))
+        return out
 
     def mod_raise(self, a, level):
         """Lift a level-0 ciphertext to q[0..level] with the centred residue."""

@@ -148,14 +148,16 @@ def test_rotate_batch_matches_the_oracle(pair, cts):
         _same(out, o.rotate(oc, r))
 
 
-def test_rotate_hoisted_values(pair, cts):
-    # one ModUp for all rotations: another valid lift, same values
+def test_rotate_hoisted(pair, cts):
+    # one ModUp for all rotations: the oracle's hoisted rotation word for
+    # word (another valid lift than rotate()'s, with the same values)
     from paper_2410_11184_amd import hs
     g, o = pair
-    ga, _, _, _, za, _ = cts
+    ga, _, oa, _, za, _ = cts
     rots = [1, -3, 128, 1000]
-    for out, r in zip(g.rotate_hoisted(ga, rots), rots):
+    for out, oout, r in zip(g.rotate_hoisted(ga, rots), o.rotate_hoisted(oa, rots), rots):
         assert out.level == ga.level and out.scale == ga.scale
+        _same(out, oout)
         assert np.max(np.abs(g.decrypt(out) - np.roll(za, -r))) < 2 ** -18
     with pytest.raises(hs.HSError) as e:
         g.rotate_hoisted(ga, [1, g.slots])

@@ -155,6 +155,29 @@ def test_key_switch_noise_is_small(ctx):
     assert err <= (len(ctx.p) + 1) * (1 + np.count_nonzero(ctx.s_coeff))
 
 
+def test_hoisted_rotation_is_a_rotation(ctx):
+    # one ModUp for several offsets: each result decrypts to the automorphism
+    # of the plaintext coefficients (X -> X^g) plus ModDown rounding of the
+    # same bound as an ordinary rotation, and its slots are the rotated slots
+    z = _z(ctx, 13)
+    ct = ctx.encode_encrypt(z, ctx.delta, ctx.L, 14)
+    m = ctx.decrypt_coeffs(ct)
+    N = ctx.N
+    rots = [1, -3, 128]
+    for r, h in zip(rots, ctx.rotate_hoisted(ct, rots)):
+        g = ctx.galois_rot(r, N)
+        mg = [0] * N
+        for j, v in enumerate(m):
+            e = j * g % (2 * N)
+            if e < N:
+                mg[e] += v
+            else:
+                mg[e - N] -= v
+        err = max(abs(a - b) for a, b in zip(ctx.decrypt_coeffs(h), mg))
+        assert err <= (len(ctx.p) + 1) * (1 + np.count_nonzero(ctx.s_coeff)), (r, err)
+        assert np.max(np.abs(ctx.decrypt_decode(h) - np.roll(z, -r))) < 2 ** -18
+
+
 def test_mod_down_is_rounded_division_by_P(ctx):
     # ModDown of c over Q_l u P: (c - Conv_P->Q([c]_P)) P^-1 = round(c / P) - u
     # with |u| < (alpha + 1) / 2 (the centred conversion's multiple of P),
