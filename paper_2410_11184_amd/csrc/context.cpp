@@ -376,7 +376,7 @@ Context::Context(Context& p, void* st) : prm(p.prm), device(p.device) {
     pinfo = p.pinfo;
     for (int i = 0; i < kMaxRows; i++) P_mod[i] = p.P_mod[i];
     T = p.T;
-    T.prof = prof_create();
+    T.prof = nullptr;
     tw_cos = p.tw_cos;
     tw_sin = p.tw_sin;
     cdt = p.cdt;
@@ -391,10 +391,22 @@ Context::Context(Context& p, void* st) : prm(p.prm), device(p.device) {
         keys[kv.first] = kv.second;
         borrowed_keys.push_back(kv.first);
     }
-    std::lock_guard<std::mutex> g(clone_mutex());
-    HS_REQUIRE(!p.destroy_pending, E_STATE, "clone: the parent context has been destroyed");
-    parent_ctx = &p;
-    p.live_clones++;
+    {
+        std::lock_guard<std::mutex> g(clone_mutex());
+        HS_REQUIRE(!p.destroy_pending, E_STATE, "clone: the parent context has been destroyed");
+        parent_ctx = &p;
+        p.live_clones++;
+    }
+    // last, so a clone that fails before holds no profiler; if this fails,
+    // the count on the parent is taken back
+    try {
+        T.prof = prof_create();
+    } catch (...) {
+        std::lock_guard<std::mutex> g(clone_mutex());
+        p.live_clones--;
+        parent_ctx = nullptr;
+        throw;
+    }
 }
 
 std::mutex& clone_mutex() {
@@ -962,7 +974,10 @@ static u64* make_switch_key(Context& c, int key_id, const u64* s_target) {
 
 void keygen(Context& c, u64 seed) {
     HS_REQUIRE(!c.parent_ctx, E_STATE, "keygen: a clone uses its parent's keys");
-    HS_REQUIRE(c.live_clones == 0, E_STATE, "keygen: contexts cloned from this one still use its keys");
+    {
+        std::lock_guard<std::mutex> g(clone_mutex());
+        HS_REQUIRE(c.live_clones == 0, E_STATE, "keygen: contexts cloned from this one still use its keys");
+    }
     ContextArena arena(c);
     const int nt = c.nq + c.np;
     const size_t rows_words = (size_t)nt * c.N;
