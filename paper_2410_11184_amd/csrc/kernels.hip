@@ -437,10 +437,12 @@ __device__ __forceinline__ u64 reduce4q(u64 x, u64 q) {
     return x >= q ? x - q : x;
 }
 
-// LDS tile layouts (u64 units), conflict-free for both access patterns:
-// pass 1 element (hi, lo, column c) at hi*272 + lo*16 + c,
+// Tiles of C columns (pass 1) or C chunks of 256 (pass 2) per workgroup of
+// 16 C threads, C = 16 or 8 (a tuner choice: 8 doubles the workgroups of a
+// launch); every element sees the same butterflies either way.  LDS layouts
+// (u64 units), conflict-free for both access patterns of each pass:
+// pass 1 element (hi, lo, column c) at hi*17C + lo*C + c,
 // pass 2 element (chunk w, hi, lo) at w*272 + hi*17 + lo.
-#define NTT16_LDS (16 * 272)
 
 // centred lift of x (mod q_s) to the prime of P: x if x <= (q_s - 1) / 2,
 // else x - q_s, reduced
@@ -450,17 +452,19 @@ __device__ __forceinline__ u64 lift_centred(u64 x, u64 qs, const PrimeInfo& P) {
     return mag ? P.q - mag : 0;
 }
 
-__global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
-                                                       NttSkip sk, int g0, NttLift lf) {
-    __shared__ u64 sm[NTT16_LDS];
+template <int C>
+__global__ void __launch_bounds__(16 * C) ntt16_p1_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+                                                         NttSkip sk, int g0, NttLift lf) {
+    constexpr int S1 = 17 * C;
+    __shared__ u64 sm[16 * S1];
     const int row = ntt_row(x, blockIdx.y, order, sk, g0);
     if (row < 0) return;   // whole workgroup
-    u64* p = row_ptr(x, row, 65536) + blockIdx.x * 16;
-    const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * 16;
+    u64* p = row_ptr(x, row, 65536) + blockIdx.x * C;
+    const u64* ps = row_ptr(src, row, 65536) + blockIdx.x * C;
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
     const u64 nq = T.prime[pi].nq;
-    const int t = threadIdx.x, c = t & 15, hl = t >> 4;
+    const int t = threadIdx.x, c = t % C, hl = t / C;
     u64 E[16];
     if (!inverse) {
         const ulonglong2* tw = (const ulonglong2*)T.tw2 + (size_t)pi * 65536;
@@ -468,7 +472,7 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
         if (lf.base) {
             const PrimeInfo P = T.prime[pi];
             const u64 qs = T.prime[lf.src_prime].q;
-            const u64* pl = lf.base + (size_t)(row / x.rpg) * lf.gs + blockIdx.x * 16;
+            const u64* pl = lf.base + (size_t)(row / x.rpg) * lf.gs + blockIdx.x * C;
 #pragma unroll
             for (int hi = 0; hi < 16; hi++) E[hi] = lift_centred(pl[(size_t)(hi * 16 + hl) * 256 + c], qs, P);
         } else {
@@ -477,11 +481,11 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
         }
         fwd16(E, tw, 1, q, nq);
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) sm[hi * 272 + hl * 16 + c] = E[hi];
+        for (int hi = 0; hi < 16; hi++) sm[hi * S1 + hl * C + c] = E[hi];
         __syncthreads();
         // thread (hi = hl, c): lo = 0..15, stages 4..7
 #pragma unroll
-        for (int lo = 0; lo < 16; lo++) E[lo] = sm[hl * 272 + lo * 16 + c];
+        for (int lo = 0; lo < 16; lo++) E[lo] = sm[hl * S1 + lo * C + c];
         fwd16(E, tw, 16 + hl, q, nq);
 #pragma unroll
         for (int lo = 0; lo < 16; lo++) p[(size_t)(hl * 16 + lo) * 256 + c] = E[lo];
@@ -492,11 +496,11 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
         for (int lo = 0; lo < 16; lo++) E[lo] = ps[(size_t)(hl * 16 + lo) * 256 + c];
         inv16(E, tw, 16 + hl, q, nq);
 #pragma unroll
-        for (int lo = 0; lo < 16; lo++) sm[hl * 272 + lo * 16 + c] = E[lo];
+        for (int lo = 0; lo < 16; lo++) sm[hl * S1 + lo * C + c] = E[lo];
         __syncthreads();
         // thread (lo = hl, c): hi = 0..15, stages 3..0, then N^-1
 #pragma unroll
-        for (int hi = 0; hi < 16; hi++) E[hi] = sm[hi * 272 + hl * 16 + c];
+        for (int hi = 0; hi < 16; hi++) E[hi] = sm[hi * S1 + hl * C + c];
         inv16(E, tw, 1, q, nq);
         const u64 ni = T.ninv[2 * pi], nis = T.ninv[2 * pi + 1];
 #pragma unroll
@@ -504,19 +508,19 @@ __global__ void __launch_bounds__(256) ntt16_p1_kernel(DevTables T, Rows x, Rows
     }
 }
 
-// four waves per SIMD: the LDS tile (35 KB per workgroup) allows four
-// workgroups per CU, and 128 VGPRs (no spills) lets the registers follow
-template <bool EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
+// four waves per SIMD: the LDS tile (35 KB per 256-thread workgroup) allows
+// four workgroups per CU, and 128 VGPRs (no spills) lets the registers follow
+template <bool EPI, int C>
+__global__ void __launch_bounds__(16 * C) __attribute__((amdgpu_waves_per_eu(4, 8))) ntt16_p2_kernel(DevTables T, Rows x, Rows src, int inverse, int order,
                                                        NttEpilogue Ep, NttSkip sk) {
-    __shared__ u64 sm[NTT16_LDS];
+    __shared__ u64 sm[C * 272];
     const int row = ntt_row(x, blockIdx.y, order, sk, Ep.g0);
     if (row < 0) return;   // whole workgroup
     const int pi = prime_of(x, row % x.rpg);
     const u64 q = T.prime[pi].q;
     const u64 nq = T.prime[pi].nq;
     const int t = threadIdx.x, w = t >> 4, l = t & 15;
-    const u32 R = blockIdx.x * 16 + w;             // chunk index
+    const u32 R = blockIdx.x * C + w;              // chunk index
     u64* p = row_ptr(x, row, 65536) + (size_t)R * 256;
     const u64* ps = row_ptr(src, row, 65536) + (size_t)R * 256;
     const ulonglong2* tw = (const ulonglong2*)(inverse ? T.itw2 : T.tw2) + (size_t)pi * 65536;
@@ -581,8 +585,14 @@ void k_ntt(const DevTables& T, const Rows& x, bool inverse, void* stream) { k_nt
 
 // N = 2^16 transform of x (first pass reading src) in one of the tuner's
 // variants: variant & 1 selects the row order (prime-major / storage order),
-// variant & 2 splits the launch into batches of kNttGroupBatch row groups.
+// variant & 2 splits the launch into batches of kNttGroupBatch row groups,
+// variant & 4 takes tiles of 8 columns / chunks (128-thread workgroups, twice
+// as many) instead of 16.
 constexpr int kNttGroupBatch = 8;
+static const char* const kNttVariants[] = {"prime-major",        "storage-order",
+                                           "prime-major/batched", "storage-order/batched",
+                                           "prime-major/tile8",   "storage-order/tile8",
+                                           "prime-major/batched/tile8", "storage-order/batched/tile8"};
 static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, bool inverse, int variant,
                          hipStream_t st, const NttEpilogue* epi = nullptr, const NttSkip& sk = NttSkip(),
                          const NttLift* lift = nullptr) {
@@ -602,16 +612,31 @@ static void ntt16_launch(const DevTables& T, const Rows& x, const Rows& src, boo
             lf = *lift;
             lf.base = lift->base + (size_t)g0 * lift->gs;
         }
-        const dim3 g(16, xs.ngroups * vrows);
-        if (!inverse) {
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0, lf);
-            if (epi)
-                hipLaunchKernelGGL(ntt16_p2_kernel<true>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
-            else
-                hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
+        const int rows = xs.ngroups * vrows;
+        if (!(variant & 4)) {
+            const dim3 g(16, rows);
+            if (!inverse) {
+                hipLaunchKernelGGL(ntt16_p1_kernel<16>, g, dim3(256), 0, st, T, xs, ss, 0, order, sk, g0, lf);
+                if (epi)
+                    hipLaunchKernelGGL((ntt16_p2_kernel<true, 16>), g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
+                else
+                    hipLaunchKernelGGL((ntt16_p2_kernel<false, 16>), g, dim3(256), 0, st, T, xs, xs, 0, order, e, sk);
+            } else {
+                hipLaunchKernelGGL((ntt16_p2_kernel<false, 16>), g, dim3(256), 0, st, T, xs, ss, 1, order, e, sk);
+                hipLaunchKernelGGL(ntt16_p1_kernel<16>, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
+            }
         } else {
-            hipLaunchKernelGGL(ntt16_p2_kernel<false>, g, dim3(256), 0, st, T, xs, ss, 1, order, e, sk);
-            hipLaunchKernelGGL(ntt16_p1_kernel, g, dim3(256), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
+            const dim3 g(32, rows);
+            if (!inverse) {
+                hipLaunchKernelGGL(ntt16_p1_kernel<8>, g, dim3(128), 0, st, T, xs, ss, 0, order, sk, g0, lf);
+                if (epi)
+                    hipLaunchKernelGGL((ntt16_p2_kernel<true, 8>), g, dim3(128), 0, st, T, xs, xs, 0, order, e, sk);
+                else
+                    hipLaunchKernelGGL((ntt16_p2_kernel<false, 8>), g, dim3(128), 0, st, T, xs, xs, 0, order, e, sk);
+            } else {
+                hipLaunchKernelGGL((ntt16_p2_kernel<false, 8>), g, dim3(128), 0, st, T, xs, ss, 1, order, e, sk);
+                hipLaunchKernelGGL(ntt16_p1_kernel<8>, g, dim3(128), 0, st, T, xs, xs, 1, order, sk, g0, NttLift());
+            }
         }
     }
 }
@@ -1357,8 +1382,10 @@ int tune_ntt16(const DevTables& T, const Rows& x, bool inverse, hipStream_t st, 
     const int v = tune_lookup(key);
     if (v >= 0 || !tuning_on()) return v < 0 ? 0 : v;
     const size_t words = (size_t)gq * x.rpg * T.N;
-    return tune_run(key, {"prime-major", "storage-order", "prime-major/batched", "storage-order/batched"},
-                    {true, true, gq > kNttGroupBatch, gq > kNttGroupBatch}, words, 0, true, st,
+    return tune_run(key, {kNttVariants, kNttVariants + 8},
+                    {true, true, gq > kNttGroupBatch, gq > kNttGroupBatch, true, true, gq > kNttGroupBatch,
+                     gq > kNttGroupBatch},
+                    words, 0, true, st,
                     [&](int c, const u64*, u64* buf) {
                         Rows r = x;
                         r.base = buf;
@@ -1415,7 +1442,7 @@ int tune_load(const std::string& text) {
         std::vector<std::string> names;
         if (key.rfind("conv", 0) == 0) names = {kConvVariants, kConvVariants + 4};
         else if (key.rfind("ntt", 0) == 0)
-            names = {"prime-major", "storage-order", "prime-major/batched", "storage-order/batched"};
+            names = {kNttVariants, kNttVariants + 8};
         TuneEntry E;
         E.names = names;
         E.us.assign(names.size(), -1.0);

@@ -4,8 +4,8 @@ The metric's batched Softmax job (64 ciphertexts, N = 2^16) is run with the
 default kernels, then with tuning enabled (each launch shape times its
 candidates on scratch data), then with every decision forced to a
 non-default candidate (matrix-core base conversion, conversion targets split
-over threads, other NTT row orders and batched launches): all three give the
-same output ciphertexts bit for bit."""
+over threads, other NTT row orders, batched launches and 8-column tiles): all
+three give the same output ciphertexts bit for bit."""
 import json
 
 import numpy as np
@@ -46,7 +46,8 @@ def test_tuned_and_forced_variants_match_defaults(tmp_path):
             alts = [name for name, t in r["us"].items() if t >= 0 and name not in ("valu", "prime-major")]
             forced.append({"key": r["key"], "choice": alts[i % len(alts)] if alts else r["choice"]})
         chosen = {f["choice"] for f in forced}
-        for name in ("mfma", "valu/split2", "valu/split4", "storage-order/batched"):
+        for name in ("mfma", "valu/split2", "valu/split4", "storage-order/batched", "prime-major/tile8",
+                     "storage-order/tile8"):
             assert name in chosen, name
         path = tmp_path / "forced.json"
         path.write_text("".join(json.dumps(f) + "\n" for f in forced))
