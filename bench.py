@@ -503,6 +503,7 @@ def main():
 
         def fl_run(i, k):
             for _ in range(k):
+                outs[i] = None         # the previous output's memory back before the next replay
                 outs[i] = fl_step[i]()
                 fl_ctxs[i].sync()
 
