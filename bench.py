@@ -482,20 +482,20 @@ def main():
 
     in_flight = None
     if args.in_flight > 1:
-        # the same K steps with S batches in flight: S contexts (this one and
-        # clones sharing its keys), each on its own stream with its own copy
-        # of the batch (same words: same keys and seed) and its own captured
+        # the same K steps with S batches in flight: S clones of this context
+        # (sharing its keys), each on its own stream with its own copy of the
+        # batch (same words: same keys and seed) and its own captured
         # schedule, driven by one host thread each, which runs its share of
         # the K steps back to back (steps i, i + S, i + 2S, ...)
         import threading
         S_ = args.in_flight
-        fl_streams = [hs.stream_create(0) for _ in range(S_ - 1)]
-        fl_ctxs = [ctx] + [ctx.clone(s_) for s_ in fl_streams]
-        fl_cts = [cts] + [encrypt_logits(c_, x, M, seed=3002) for c_ in fl_ctxs[1:]]
+        fl_streams = [hs.stream_create(0) for _ in range(S_)]
+        fl_ctxs = [ctx.clone(s_) for s_ in fl_streams]
+        fl_cts = [encrypt_logits(c_, x, M, seed=3002) for c_ in fl_ctxs]
         from paper_2410_11184_amd.softmax import softmax_groups
-        softmax_groups([(c_, ct_, n, M, dict(variant=variant)) for c_, ct_ in zip(fl_ctxs[1:], fl_cts[1:])])
+        softmax_groups([(c_, ct_, n, M, dict(variant=variant)) for c_, ct_ in zip(fl_ctxs, fl_cts)])
         if graph:
-            fl_plans = [plan] + [c_.softmax_plan(ct_, n, M, variant=variant) for c_, ct_ in zip(fl_ctxs[1:], fl_cts[1:])]
+            fl_plans = [c_.softmax_plan(ct_, n, M, variant=variant) for c_, ct_ in zip(fl_ctxs, fl_cts)]
             fl_step = [lambda i=i: fl_plans[i].run(fl_cts[i]) for i in range(S_)]
         else:
             fl_step = [lambda i=i: fl_ctxs[i].softmax(fl_cts[i], n, M, variant=variant) for i in range(S_)]
@@ -529,7 +529,7 @@ def main():
         _log("in flight %d: %.2f ms/step, %.1f calls/s, same words %s" %
              (S_, in_flight["ms_per_step"], in_flight["calls_per_s"], in_flight["outputs_equal_one_at_a_time"]))
         if graph:
-            for pl_ in fl_plans[1:]:
+            for pl_ in fl_plans:
                 pl_.close()
         del outs
         value = in_flight["calls_per_s"]
