@@ -226,9 +226,9 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
 
 def run_uneven(args):
     """The uneven batch (32 layer jobs of 4096 Softmax of dim 128 in lockstep,
-    and one Softmax of dim 32768, the two groups at once on a context and a
-    clone of it, each on its own stream): one JSON line with total calls/s
-    and the precision of each group."""
+    and one Softmax of dim 32768, the two groups at once on two clones of one
+    context, each on its own stream): one JSON line with total calls/s and
+    the precision of each group."""
     import torch
     import synthetic
     from paper_2410_11184_amd import hs
@@ -239,10 +239,10 @@ def run_uneven(args):
     from paper_2410_11184_amd.softmax import softmax_groups
     ctx = hs.Context(p, device=0, stream=hs.current_stream())
     ctx.keygen(2003)
-    # one context per group: the first group on ctx, the others on clones
-    # (shared keys) with streams of their own, so the groups run at once
-    streams = [hs.stream_create(0) for _ in w["groups"][1:]]
-    ctxs = [ctx] + [ctx.clone(s) for s in streams]
+    # one context per group: clones of ctx (shared keys), each with a stream
+    # of its own, so the groups run at once
+    streams = [hs.stream_create(0) for _ in w["groups"]]
+    ctxs = [ctx.clone(s) for s in streams]
     groups = []
     for gi, g in enumerate(w["groups"]):
         xs = [synthetic.group_logits(args.workload, gi, j) for j in range(g["jobs"])]
