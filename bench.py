@@ -309,7 +309,8 @@ def run_serve(args):
     p = synthetic.preset(w["preset"])
     stream = synthetic.serve_stream(w["count"], w["rate"], seed=w["seed"], M=w["M"])
     t0 = time.perf_counter()
-    srv = serve.SoftmaxServer(p, workers=2, hbm_budget_gb=120.0, variant=1, key_seed=2004, warm_dims=(256,))
+    srv = serve.SoftmaxServer(p, workers=args.serve_workers, hbm_budget_gb=120.0, variant=1, key_seed=2004,
+                              warm_dims=(256,))
     _log("server ready in %.1fs" % (time.perf_counter() - t0))
     start = time.perf_counter()
     reqs = []
@@ -340,7 +341,8 @@ def run_serve(args):
            "warmup": 0, "ms_per_step": 1e3 * elapsed, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
            "config": {"workload": "%d requests, Poisson %.1f/s, dims log-uniform 64..32768, 1-512 vectors, "
-                                  "U[-128,0], 2 workers, lockstep batching by shape" % (w["count"], w["rate"]),
+                                  "U[-128,0], %d workers, lockstep batching by shape" %
+                                  (w["count"], w["rate"], args.serve_workers),
                       "parallelism": "single-gpu"},
            "latency": serve.latency_stats(reqs), "requests": len(reqs), "errors": errors,
            "batched_requests": sum(1 for r in reqs if r.batch_jobs > 1),
@@ -357,6 +359,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of the captured schedule")
+    ap.add_argument("--serve-workers", type=int, default=2,
+                    help="serving workload: worker contexts (clones sharing one key set), one stream each")
     ap.add_argument("--in-flight", type=int, default=4,
                     help="batches in flight at once, each on its own stream (a context clone sharing the keys); "
                          "1 = one batch at a time")
