@@ -287,13 +287,14 @@ typedef struct hs_softmax_opts {
                           /* 3 or 4 with variant 0 only (HS_E_PARAM else)    */
     int debug_stop;       /* tests: >= 0 returns y after that iteration
                              (0 = after the exponential); -1 = off          */
-    int newton_steps;     /* > 0: each inverse root by that many Newton steps */
-                          /* (Appendix A, inverse square roots) from the      */
-                          /* normalisation polynomial as first guess (the     */
-                          /* guess bootstrapped first when its depth and the  */
-                          /* steps exceed the levels a bootstrap restores);   */
-                          /* 0 = by dimension: none up to n = 2048, 2 above   */
-                          /* for variant 0 with squares; -1 = none            */
+    int newton_steps;     /* > 0: each inverse square root by that many       */
+                          /* Newton steps (Appendix A) from the normalisation */
+                          /* polynomial as first guess (the guess             */
+                          /* bootstrapped first when its depth and the steps  */
+                          /* exceed the levels a bootstrap restores); version */
+                          /* B takes one in its last step only; squares only  */
+                          /* (HS_E_PARAM else); 0 = by dimension: none up to  */
+                          /* n = 2048, 2 above; -1 = none                     */
     int mask_mode;        /* 0: mask = indicator of slots [0, L); 1: the      */
                           /* averaging mask (m / n on every slot, no          */
                           /* plaintext; bootstraps of the factors unmasked)   */

@@ -165,9 +165,9 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     Returns the m output ciphertexts.  The context must hold the
     relinearisation key; the rotation keys of strides +-L 2^t are added
     here.  newton_steps > 0: each inverse square root is the polynomial's
-    first guess refined by that many Newton steps (Algorithm SM with squares
-    only); 0: by dimension, none up to n = 2048 and two above for Algorithm
-    SM with squares; -1: none.  mask_mode 1: the averaging mask, the factor divided by n2/m on
+    first guess refined by that many Newton steps (squares only; version B
+    takes an inverse square root in its last step only); 0: by dimension,
+    none up to n = 2048 and two above; -1: none.  mask_mode 1: the averaging mask, the factor divided by n2/m on
     every slot instead of the indicator of slots [0, L)."""
     N0 = ctx.slots
     m = len(xs)
@@ -175,10 +175,10 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     assert n >= 2 and n2 <= N0 and n2 % m == 0
     tp = power
     assert tp in (2, 3, 4) and (tp == 2 or variant == 0)
-    assert newton_steps <= 0 or (tp == 2 and variant == 0)
+    assert newton_steps <= 0 or tp == 2
     if newton_steps == 0:
-        newton_steps = 2 if (variant == 0 and tp == 2 and n > 2048) else 0
-    newton_steps = max(newton_steps, 0)
+        newton_steps = 2 if (tp == 2 and n > 2048) else 0
+    newton_opt = max(newton_steps, 0)
     avg = mask_mode == 1
     tl = 1 if tp == 2 else 2         # levels of y^tp
     L = m * N0 // n2
@@ -257,6 +257,8 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     for j in range(1, k + 1):
         last = j == k
         smb_step = smb and not last
+        # Newton's steps on the inverse square roots only (version B: its last step)
+        newton_steps = 0 if smb_step else newton_opt
         e = math.ldexp(1.0, -j) if smb_step else (0.5 if tp == 2 else 1.0 / tp)
         deg = inv_degrees[0] if j == 1 else (inv_degrees[2] if last else inv_degrees[1])
         if deg <= 0:

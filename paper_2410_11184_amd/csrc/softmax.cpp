@@ -323,13 +323,15 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     HS_REQUIRE(tp >= 2 && tp <= 4, E_PARAM, "power must be 2, 3 or 4");
     HS_REQUIRE(o.approx == 0 || o.approx == 1, E_PARAM, "approx must be 0 (minimax) or 1 (interpolation)");
     HS_REQUIRE(tp == 2 || !smb, E_PARAM, "version B normalizes with squares (power 2)");
-    HS_REQUIRE(o.newton_steps <= 0 || (tp == 2 && !smb), E_PARAM,
-               "Newton's iteration computes inverse square roots: Algorithm SM with squares");
-    // Newton's steps: as asked; by default none up to n = 2048 and, above,
-    // two for Algorithm SM with squares (where a degree-255 polynomial alone
-    // leaves a relative error near 2^-5 on [~1/n, 1], each step squares it)
-    const int nsteps = o.newton_steps > 0 ? o.newton_steps
-                       : (o.newton_steps == 0 && !smb && tp == 2 && n > 2048 ? 2 : 0);
+    HS_REQUIRE(o.newton_steps <= 0 || tp == 2, E_PARAM,
+               "Newton's iteration computes inverse square roots: normalisation with squares");
+    // Newton's steps on every inverse square root (Algorithm SM; version B:
+    // its last step, the only one that takes an inverse square root): as
+    // asked; by default none up to n = 2048 and, above, two (where a
+    // degree-255 polynomial alone leaves a relative error near 2^-5 on
+    // [~1/n, 1]; each step squares it)
+    const int nsteps_opt = o.newton_steps > 0 ? o.newton_steps
+                           : (o.newton_steps == 0 && tp == 2 && n > 2048 ? 2 : 0);
     const int tl = tp == 2 ? 1 : 2;         // levels of y^tp
     const int L = (int)((long long)m * N0 / np2);
     // Theorem "th:prec_softmax"'s k (M / t^k ~ ln n for the t-th power
@@ -389,6 +391,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     for (int j = 1; j <= k; j++) {
         const bool last = j == k;
         const bool smb_step = smb && !last;
+        const int nsteps = smb_step ? 0 : nsteps_opt;
         // exponent of the normalisation: 1/t (SM, and the last step of B) or 2^-j
         const double e = smb_step ? std::ldexp(1.0, -j) : (tp == 2 ? 0.5 : 1.0 / tp);
         int deg = j == 1 ? o.inv_degree_first : (last ? o.inv_degree_last : o.inv_degree_mid);

@@ -37,8 +37,9 @@ CASES = [
 # then (Newton steps, mask mode): the inverse square roots refined by one
 # Newton step from degree-7 first guesses (Appendix A), with the indicator
 # mask folded into that step or with the averaging mask (the toy ring's
-# levels allow no more: about 8 bits, 3.4 without the Newton step), and
-# version B with the averaging mask
+# levels allow no more: about 8 bits, 3.4 without the Newton step), version
+# B with the averaging mask, and version B with a Newton step in its last
+# iteration
 MORE = [
     (0, 1, 8, 4.0, 0, 7, (31, 31, 31), 14.0, 3, 0, 0),
     (1, 2, 12, 8.0, 0, 7, (15, 15, 31), 16.0, 2, 0, 0),
@@ -46,6 +47,9 @@ MORE = [
     (0, 1, 16, 8.0, 0, 7, (7, 7, 7), 8.0, 2, 1, 0),
     (0, 2, 16, 8.0, 0, 7, (7, 7, 7), 8.0, 2, 1, 1),
     (1, 2, 16, 8.0, 0, 7, (15, 15, 31), 16.0, 2, 0, 1),
+    # version B with one Newton step in its last iteration (its only inverse
+    # square root), from a degree-7 first guess
+    (1, 2, 16, 8.0, 0, 7, (15, 15, 7), 8.0, 2, 1, 0),
 ]
 
 

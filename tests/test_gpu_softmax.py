@@ -86,7 +86,7 @@ def test_bad_dimension(ctx):
         ctx.softmax(cts, 16, 8.0, power=5)
     assert e.value.name == "HS_E_PARAM"
     with pytest.raises(hs.HSError) as e:
-        ctx.softmax(cts, 16, 8.0, variant=1, newton_steps=1)
+        ctx.softmax(cts, 16, 8.0, power=3, newton_steps=1)
     assert e.value.name == "HS_E_PARAM"
     with pytest.raises(hs.HSError) as e:
         ctx.softmax(cts, 16, 8.0, approx=2)
