@@ -140,7 +140,7 @@ class SoftmaxServer:
             rm, _ = job_shape(r.V, r.n, self.slots)
             if (r.n, rm, r.M) != key:
                 continue
-            c = rm * self.bytes_per_ct * (1 if self._variant(r.n) == 1 else 3)
+            c = rm * self.bytes_per_ct * (1 if self._variant(r.n, r.M) == 1 else 3)
             if batch and (self.in_flight + cost + c > self.budget or len(batch) >= self.max_jobs):
                 break
             if not batch and self.in_flight > 0 and self.in_flight + c > self.budget:
@@ -208,10 +208,14 @@ class SoftmaxServer:
             if len(self.contexts) > 1 and self.contexts[w] is not None:
                 self.contexts[w].trim()
 
-    def _variant(self, n):
-        # version B needs k + 2 main-thread levels after the exponential; the
-        # largest dimensions take one more iteration than that budget allows
-        return self.variant if n <= 2048 else 0
+    def _variant(self, n, M):
+        # version B needs k + 2 main-thread levels after the exponential
+        # (k <= 5 with twelve user levels; k as the library takes it: the
+        # Theorem's, plus one from n = 4096); above n = 16384 its
+        # intermediate normalisations cannot hold the intervals, and
+        # Algorithm SM with Newton's steps is the more precise
+        k = max(1, math.ceil(math.log2(M) - math.log2(math.log(n)))) + (1 if n >= 4096 else 0)
+        return self.variant if (n <= 16384 and k <= 5) else 0
 
     def _run(self, ctx, batch, w):
         n, M = batch[0].n, batch[0].M
@@ -223,7 +227,7 @@ class SoftmaxServer:
             x = np.zeros((L, n))
             x[:r.V] = r.logits
             cts += encrypt_logits(ctx, x, M, seed=100003 * (r.rid + 1))
-        out = ctx.softmax(cts, n, M, variant=self._variant(n), jobs=len(batch), **self.softmax_kw)
+        out = ctx.softmax(cts, n, M, variant=self._variant(n, M), jobs=len(batch), **self.softmax_kw)
         del cts
         for i, r in enumerate(batch):
             y = decrypt_outputs(ctx, out[i * m:(i + 1) * m], n)

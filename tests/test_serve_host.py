@@ -73,3 +73,18 @@ def test_latency_stats():
         r.t_done = r.t_arrival + (i + 1) / 100.0
     st = serve.latency_stats(rs)
     assert abs(st["p50_s"] - 0.505) < 1e-9 and st["max_s"] == 1.0
+
+
+def test_variant_choice_by_dimension_and_range():
+    s = _server(budget=100, bytes_per_ct=1)
+    # version B up to n = 16384 while its k (the Theorem's, one more from
+    # n = 4096) stays within five squarings; Algorithm SM otherwise
+    assert s._variant(256, 128.0) == 1
+    assert s._variant(4096, 128.0) == 1          # k = 4 + 1
+    assert s._variant(16384, 128.0) == 1         # k = 4 + 1
+    assert s._variant(32768, 128.0) == 0         # beyond the dimension bound
+    assert s._variant(256, 256.0) == 0           # k = 6
+    assert s._variant(16384, 64.0) == 1          # k = 3 + 1
+    assert s._variant(8192, 256.0) == 0          # k = 5 + 1
+    s.variant = 0
+    assert s._variant(256, 128.0) == 0
