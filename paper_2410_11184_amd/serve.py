@@ -214,7 +214,8 @@ class SoftmaxServer:
         # Theorem's, plus one from n = 4096); above n = 16384 its
         # intermediate normalisations cannot hold the intervals, and
         # Algorithm SM with Newton's steps is the more precise
-        k = max(1, math.ceil(math.log2(M) - math.log2(math.log(n)))) + (1 if n >= 4096 else 0)
+        k = self.softmax_kw.get("k") or (max(1, math.ceil(math.log2(M) - math.log2(math.log(n))))
+                                         + (1 if n >= 4096 else 0))
         return self.variant if (n <= 16384 and k <= 5) else 0
 
     def _run(self, ctx, batch, w):

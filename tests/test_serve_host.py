@@ -29,6 +29,7 @@ def _server(budget, bytes_per_ct, max_jobs=8):
     s.in_flight = 0.0
     s.variant = 1
     s.exclusive = 0
+    s.softmax_kw = {}
     s.lock = threading.Condition()
     return s
 
@@ -86,5 +87,8 @@ def test_variant_choice_by_dimension_and_range():
     assert s._variant(256, 256.0) == 0           # k = 6
     assert s._variant(16384, 64.0) == 1          # k = 3 + 1
     assert s._variant(8192, 256.0) == 0          # k = 5 + 1
+    s.softmax_kw = {"k": 6}                     # a k given by the caller counts
+    assert s._variant(256, 128.0) == 0
+    s.softmax_kw = {}
     s.variant = 0
     assert s._variant(256, 128.0) == 0
