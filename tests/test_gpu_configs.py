@@ -155,7 +155,7 @@ def test_large_dimensions(ctx, n):
     assert b1["worst"] < bits["worst"] - 4.0, (b1, bits)
     if n <= 16384:
         # version B, the two steps in its last iteration only (measured
-        # 20.5 bits at n = 8192, M = 128)
+        # 20.7 bits at n = 8192, M = 128)
         yb = decrypt_outputs(ctx, ctx.softmax(cts, n, M, variant=1), n)
         bb = S.precision_bits(S.softmax(x), yb)
         print("n=%d version B: %s, stats %s" % (n, bb, ctx.softmax_stats()))
