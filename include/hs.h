@@ -303,6 +303,22 @@ typedef struct hs_softmax_opts {
                           /* relative error on the interval), 1 = Chebyshev   */
                           /* interpolants (larger worst case, smaller error   */
                           /* away from the interval's lower end)              */
+    int merge;            /* hs_softmax_jobs with version B: 1 = the jobs'    */
+                          /* auxiliary ciphertexts packed (Section 4.2: one   */
+                          /* auxiliary ciphertext carries the sums of many    */
+                          /* Softmax), n / m jobs per ciphertext, job         */
+                          /* g n/m + b's sums on slots [bL, (b+1)L) of the    */
+                          /* g-th, so each sum, polynomial and bootstrap of   */
+                          /* the auxiliary thread covers n / m jobs at once;  */
+                          /* each job's factor is taken back by a 0/1         */
+                          /* plaintext product (one level) before its         */
+                          /* broadcast.  Needs njobs <= n / m or a multiple   */
+                          /* of it, squares with the indicator mask and no    */
+                          /* Newton steps (HS_E_PARAM else).  A job's result  */
+                          /* then depends on the others through the shared    */
+                          /* bootstraps' noise: equal to its result alone     */
+                          /* within the precision, not word for word.         */
+                          /* 0 = separate auxiliary ciphertexts (one batch)   */
 } hs_softmax_opts;
 
 /* Softmax (Eq. "eq:smdef") of the L = m (N/2) / n vectors of dimension n

@@ -156,7 +156,8 @@ def newton_invsqrt(ctx, S, y, steps, mask=None, avg=1, tgt=None):
 
 
 def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0), bootstrap=None,
-            debug_stop=-1, stats=None, power=2, newton_steps=0, mask_mode=0, approx=0, boot_top=None):
+            debug_stop=-1, stats=None, power=2, newton_steps=0, mask_mode=0, approx=0, boot_top=None, jobs=1,
+            merge=False):
     """Softmax of the L = m N0 / n2 vectors packed in the oracle ciphertexts
     xs (m of them, one level and scale, inputs in [-M, 0]); n2 is n rounded
     up to a power of two (the packing's dimension; the extra coordinates are
@@ -168,9 +169,24 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     first guess refined by that many Newton steps (squares only; version B
     takes an inverse square root in its last step only); 0: by dimension,
     none up to n = 2048 and two above; -1: none.  mask_mode 1: the averaging mask, the factor divided by n2/m on
-    every slot instead of the indicator of slots [0, L)."""
+    every slot instead of the indicator of slots [0, L).
+
+    jobs > 1 with merge (version B only): xs holds `jobs` consecutive jobs of
+    len(xs) / jobs ciphertexts, whose auxiliary ciphertexts are packed (Section
+    4.2: one auxiliary ciphertext carries the sums of many Softmax), Jg =
+    min(jobs, n2 / m) jobs per ciphertext: after each job's rotate-and-add,
+    job g Jg + b's sums (on every block of L slots) keep block b by a 0/1
+    plaintext of that block at scale q_l, summed over the group's jobs before
+    one rescale; the polynomials and bootstraps act on the packed ciphertexts
+    (indicator of slots [0, Jg L)); a factor is taken apart the same way (job
+    g Jg + b: block b's plaintext on the g-th, one rescale) and broadcast.
+    Every y^(j) then keeps two levels (one for the packing)."""
     N0 = ctx.slots
-    m = len(xs)
+    J = jobs
+    m = len(xs) // J
+    assert J >= 1 and J * m == len(xs)
+    assert J == 1 or merge, "lockstep jobs without packing equal the jobs run one by one"
+    mg = bool(merge) and J > 1
     n2 = 1 << ilog2(n)
     assert n >= 2 and n2 <= N0 and n2 % m == 0
     tp = power
@@ -186,6 +202,8 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
     per = n2 // m
     nrot = ilog2(per)
     smb = variant == 1
+    assert not merge or (smb and mask_mode == 0 and newton_opt == 0 and (J <= per or J % per == 0))
+    Jg = min(J, per)
     log_scale = int(round(math.log2(ctx.delta)))
     Delta = math.ldexp(1.0, log_scale)
     for t in range(nrot):
@@ -247,7 +265,38 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         y0 = out
     if debug_stop == 0:
         return y0
-    mask = P.Mask(ctx, [1.0] * L + [0.0] * (N0 - L))
+    LM = Jg * L if mg else L
+    mask = P.Mask(ctx, [1.0] * LM + [0.0] * (N0 - LM))
+    blocks = [P.Mask(ctx, [0.0] * (b * L) + [1.0] * L + [0.0] * (N0 - (b + 1) * L)) for b in range(Jg)] if mg else []
+
+    def pack(Ss):
+        # job g Jg + b keeps block b of the g-th: sums of S_i times block
+        # plaintexts at q_l, one rescale
+        lvl = Ss[0].level
+        assert lvl >= 1, "no level to pack the jobs' auxiliary ciphertexts"
+        ql = float(ctx.q[lvl])
+        out = []
+        for g in range(J // Jg):
+            acc = None
+            for b in range(Jg):
+                t_ = ctx.mul_plain(Ss[g * Jg + b], blocks[b].plaintext(ql, lvl), ql)
+                acc = t_ if acc is None else ctx.add_ct(acc, t_)
+            r_ = ctx.rescale(acc)
+            r_.scale = Ss[0].scale
+            out.append(r_)
+        return out
+
+    def unpack(As):
+        # job g Jg + b's factor: A_g times block b's plaintext at q_l, one rescale
+        lvl = As[0].level
+        assert lvl >= 1, "no level to take the jobs' factors apart"
+        ql = float(ctx.q[lvl])
+        out = []
+        for i in range(J):
+            r_ = ctx.rescale(ctx.mul_plain(As[i // Jg], blocks[i % Jg].plaintext(ql, lvl), ql))
+            r_.scale = As[0].scale
+            out.append(r_)
+        return out
 
     y = list(y0)
     big = None
@@ -266,32 +315,42 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         if not smb:
             y = [ensure(c, 1 + tl if last else 1 + 2 * tl, ybound) for c in y]
         # auxiliary thread: S = sum of the t-th powers (squares: the tensors
-        # summed, one relinearisation), rotate-and-add
-        if tp == 2:
-            d = ctx.tensor(y[0], y[0])
-            for c in y[1:]:
-                d = ctx.add_ct(d, ctx.tensor(c, c))
-            S = ctx.rescale(ctx.relinearize(d))
-        else:
-            yt = [power_of(ctx, c, tp) for c in y]
-            S = yt[0]
-            for c in yt[1:]:
-                S = ctx.add_ct(S, c)
-        for t in range(nrot):
-            S = ctx.add_ct(S, ctx.rotate(S, -(L << t)))
+        # summed, one relinearisation), rotate-and-add; per job, then packed
+        Ss = []
+        for i in range(J):
+            yj = y[i * m:(i + 1) * m]
+            if tp == 2:
+                d = ctx.tensor(yj[0], yj[0])
+                for c in yj[1:]:
+                    d = ctx.add_ct(d, ctx.tensor(c, c))
+                S = ctx.rescale(ctx.relinearize(d))
+            else:
+                yt = [power_of(ctx, c, tp) for c in yj]
+                S = yt[0]
+                for c in yt[1:]:
+                    S = ctx.add_ct(S, c)
+            for t in range(nrot):
+                S = ctx.add_ct(S, ctx.rotate(S, -(L << t)))
+            Ss.append(S)
+        # the auxiliary ciphertexts: the packed ones, or the job's own
+        Sl = pack(Ss) if mg else [Ss[0]]
         # lambda lands depth (+ 1 when the affine map takes a level) + 2
         # newton_steps below S; the cube and fourth power variants and
         # Newton's steps also keep 1 + tl levels in lambda
-        keep = 2 + tl if (tp != 2 or newton_steps) else 1
+        # the last step's z = lambda y and z^2 take two of lambda's levels;
+        # packed jobs: one more for taking the factor apart
+        keep = (2 + tl if (tp != 2 or newton_steps) else (1 + tl if last else 1)) + (1 if mg and not smb_step else 0)
         # when that exceeds the level a bootstrapping restores (boot_top),
         # Newton's first guess is bootstrapped before the steps
         need_full = P.depth(deg) + 2 * newton_steps + keep
         refresh = newton_steps > 0 and bootstrap is not None and boot_top is not None and need_full > boot_top
-        S = ensure(S, max(P.depth(deg), 2 * newton_steps + keep + 1) if refresh else need_full, hi * 1.1)
+        Sl = [ensure(s_, max(P.depth(deg), 2 * newton_steps + keep + 1) if refresh else need_full, hi * 1.1)
+              for s_ in Sl]
+        S = Sl[0]
         # the polynomial's interval: [lo, lo + 2^w] (integer affine map); in the
         # last step of SM with squares exactly [lo, hi] when S has the level
         # its affine map takes on top of the polynomial and z = lambda y, z^2
-        if last and tp == 2 and not newton_steps and S.level >= P.depth(deg) + 3:
+        if last and tp == 2 and not newton_steps and S.level >= P.depth(deg) + 3 + (1 if mg else 0):
             a, b = lo, hi
         else:
             a, b = free_interval(lo, hi)
@@ -307,20 +366,21 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
         if avg:
             lam_bound /= per
         if not newton_steps:
-            lam = P.eval_cheb(ctx, S, pe, a, b, Delta, log_scale, None if avg else mask)
+            laml = [P.eval_cheb(ctx, s_, pe, a, b, Delta, log_scale, None if avg else mask) for s_ in Sl]
         else:
             g = P.eval_cheb(ctx, S, pinv, a, b, Delta, log_scale)
             if refresh:
                 g = ensure(g, 2 * newton_steps + keep, (1.0 + delta0) / math.sqrt(lo) * 1.05)
                 if g.level >= S.level:
                     g = P.drop(ctx, g, S.level - 1)
-            lam = newton_invsqrt(ctx, S, g, newton_steps, None if avg else mask, per if avg else 1, Delta)
+            laml = [newton_invsqrt(ctx, S, g, newton_steps, None if avg else mask, per if avg else 1, Delta)]
         if not smb_step:
             need_next = 1 + tl if j + 1 == k else 1 + 2 * tl
-            if not last and bootstrap is not None and lam.level < y[0].level and lam.level - 1 - tl < need_next:
-                lam = ensure(lam, y[0].level, lam_bound, 0 if avg else L)
-            lam = broadcast(lam)
-            z = [P.mult(ctx, c, lam) for c in y]
+            lv_ = laml[0].level
+            if not last and bootstrap is not None and lv_ < y[0].level and lv_ - 1 - tl < need_next:
+                laml = [ensure(l_, y[0].level, lam_bound, 0 if avg else L) for l_ in laml]
+            lams = [broadcast(l_) for l_ in (unpack(laml) if mg else laml)]
+            z = [P.mult(ctx, c, lams[i // m]) for i, c in enumerate(y)]
             y = [power_of(ctx, c, tp) for c in z]
             # sum y in [(1 - delta)^tp, (1 + delta)^tp]; by the power-mean
             # inequality sum y^tp in [(1 - delta)^(tp^2) / n^(tp-1), (1 + delta)^(tp^2)]
@@ -333,16 +393,19 @@ def softmax(ctx, xs, n, M, variant=0, k=0, exp_degree=15, inv_degrees=(0, 0, 0),
             ybound = hi * 1.05
         else:
             if avg:
-                lam = broadcast(lam)
-            big = lam if big is None else P.mult(ctx, big, lam)
-            r = 2 if j == k - 1 else 1
+                laml = [broadcast(l_) for l_ in laml]
+            big = laml if big is None else [P.mult(ctx, b_, l_) for b_, l_ in zip(big, laml)]
+            r = 2 if (j == k - 1 or mg) else 1
             want = j + 1 + r
             assert y0[0].level >= want, "version B: main-thread level budget exhausted"
-            if big.level < want:
-                big = ensure(big, want, max(64.0, lam_bound * per if avg else lam_bound, 4.0 * math.sqrt(n)),
-                             0 if avg else L)
-            bb = big if avg else broadcast(big)
-            y = [P.mult(ctx, c, bb) for c in y0]
+            want_big = want + (1 if mg else 0)
+            if big[0].level < want_big:
+                big = [ensure(b_, want_big, max(64.0, lam_bound * per if avg else lam_bound, 4.0 * math.sqrt(n)),
+                              0 if avg else LM) for b_ in big]
+            bbs = unpack(big) if mg else list(big)
+            if not avg:
+                bbs = [broadcast(b_) for b_ in bbs]
+            y = [P.mult(ctx, c, bbs[i // m]) for i, c in enumerate(y0)]
             for _ in range(j):
                 y = [P.mult(ctx, c, c) for c in y]
             ej = math.ldexp(1.0, j + 1)

@@ -834,6 +834,7 @@ static hs::SoftmaxOpts softmax_opts(const hs_softmax_opts* opts) {
         o.newton_steps = opts->newton_steps;
         o.mask_mode = opts->mask_mode;
         o.approx = opts->approx;
+        o.merge = opts->merge;
     }
     return o;
 }

@@ -39,13 +39,14 @@
 
 namespace hs {
 
-// device coefficients of the 0/1 slot vector with ones on slots [0, L)
-static const double* mask_coeffs(Context& c, int L) {
-    auto it = c.mask_coeffs.find(L);
-    if (it != c.mask_coeffs.end()) return it->second;
+// device coefficients of the 0/1 slot vector with ones on slots [lo, hi)
+static const double* mask_coeffs(Context& c, int lo, int hi) {
     const int n = c.N / 2;
+    const int key = lo * (n + 1) + hi;
+    auto it = c.mask_coeffs.find(key);
+    if (it != c.mask_coeffs.end()) return it->second;
     std::vector<double> re(n, 0.0), im(n, 0.0);
-    for (int j = 0; j < L; j++) re[j] = 1.0;
+    for (int j = lo; j < hi; j++) re[j] = 1.0;
     special_fft_inverse(c, re, im);
     std::vector<double> w(c.N);
     for (int k = 0; k < n; k++) {
@@ -53,9 +54,11 @@ static const double* mask_coeffs(Context& c, int L) {
         w[k + n] = im[k];
     }
     double* d = (double*)c.dev_table(w.data(), sizeof(double) * c.N);
-    c.mask_coeffs[L] = d;
+    c.mask_coeffs[key] = d;
     return d;
 }
+
+static const double* mask_coeffs(Context& c, int L) { return mask_coeffs(c, 0, L); }
 
 int theorem_k(int n, double M) {
     const double v = std::ceil(std::log2(M) - std::log2(std::log((double)n)));
@@ -301,6 +304,68 @@ static Ct per_job(Context& c, const Ct& a, int jobs, int m) {
     return o;
 }
 
+// Many jobs, few auxiliary ciphertexts (Section 4.2's packing of the sums
+// of many Softmax into one ciphertext, across jobs): the J jobs' sums S (one
+// ciphertext per job, each holding its L sums on every block of L slots
+// after the rotate-and-add) become G = J / Jg ciphertexts, the g-th holding
+// job g Jg + b's sums on block b (Jg = min(J, N/2 / L) jobs each), by 0/1
+// plaintexts of the blocks at scale q_l summed before one rescale (the
+// scale stays S's).
+static Ct pack_jobs(Context& c, const Ct& S, int L, int Jg) {
+    const int J = S.m, lv = S.level, G = J / Jg;
+    HS_REQUIRE(lv >= 1, E_LEVEL, "Softmax: no level to pack the jobs' auxiliary ciphertexts");
+    const double ql = (double)c.primes[lv];
+    Ct o = ct_alloc(c, G, 2, lv);
+    o.scale = S.scale * ql;
+    std::vector<u64*> own;
+    for (int g = 0; g < G; g++) {
+        std::vector<const u64*> as, ps;
+        for (int b = 0; b < Jg; b++) {
+            bool owned;
+            u64* pt = mask_plaintext(c, mask_coeffs(c, b * L, (b + 1) * L), lv, ql, &owned);
+            as.push_back(S.d + (size_t)(g * Jg + b) * S.ct_words(c.N));
+            ps.push_back(pt);
+            if (owned) own.push_back(pt);
+        }
+        c.count(OC_PTMUL, lv, (double)Jg);
+        c.count(OC_ADD, lv, (double)(Jg - 1));
+        k_mul_plain_acc(c.T, o.d + (size_t)g * o.ct_words(c.N), as.data(), ps.data(), Jg, 2, lv + 1, c.stream);
+    }
+    for (u64* p : own) c.free_words(p);
+    Ct r = op_rescale(c, o);
+    ct_free(c, o);
+    r.scale = S.scale;
+    return r;
+}
+
+// The inverse for factors computed on the packed ciphertexts a: job g Jg + b's
+// factor is a_g times the 0/1 plaintext of block b at scale q_l, one rescale
+// (the scale stays a's); J ciphertexts, job by job, each nonzero on its own
+// block only, which the broadcast (its rotate-and-add runs over every block)
+// copies to all blocks.
+static Ct unpack_jobs(Context& c, const Ct& a, int J, int L, int Jg) {
+    const int lv = a.level;
+    HS_REQUIRE(lv >= 1, E_LEVEL, "Softmax: no level to take the jobs' factors apart");
+    const double ql = (double)c.primes[lv];
+    Ct o = ct_alloc(c, J, 2, lv);
+    o.scale = a.scale * ql;
+    for (int i = 0; i < J; i++) {
+        const int g = i / Jg, b = i % Jg;
+        bool owned;
+        u64* pt = mask_plaintext(c, mask_coeffs(c, b * L, (b + 1) * L), lv, ql, &owned);
+        const Rows ra{a.d + (size_t)g * a.ct_words(c.N), 2, lv + 1, a.comp_words(c.N), lv + 1, 0, c.nq};
+        Rows ro{o.d + (size_t)i * o.ct_words(c.N), 2, lv + 1, o.comp_words(c.N), lv + 1, 0, c.nq};
+        Rows rp{pt, 2, lv + 1, 0, lv + 1, 0, c.nq};
+        c.count(OC_PTMUL, lv, 1.0);
+        k_mul(c.T, ro, ra, rp, c.stream);
+        if (owned) c.free_words(pt);
+    }
+    Ct r = op_rescale(c, o);
+    ct_free(c, o);
+    r.scale = a.scale;
+    return r;
+}
+
 Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, SoftmaxStats* stats, int jobs) {
     SoftmaxStats st;
     const int N0 = c.N / 2;
@@ -340,6 +405,13 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
     const int k = o.k > 0 ? o.k : power_k(n, M, tp) + (n >= 4096 ? 1 : 0);
     const int per = np2 / m;
     const int nrot = ilog2(per);
+    // the jobs' auxiliary ciphertexts packed into one (version B with
+    // squares and the indicator mask, no Newton steps, J L <= N/2)
+    HS_REQUIRE(o.merge == 0 || (smb && !avg && nsteps_opt == 0 && (J <= per || J % per == 0)), E_PARAM,
+               "Softmax: packed auxiliary ciphertexts for several jobs need version B, the indicator mask, no "
+               "Newton steps and jobs <= n / m or a multiple of it");
+    const bool mg = o.merge != 0 && J > 1;
+    const int Jg = std::min(J, per);          // jobs per packed auxiliary ciphertext
     const double Delta = std::ldexp(1.0, c.prm.log_scale);
     // rotation keys for the rotate-and-add loops (strides +-L 2^t)
     for (int t = 0; t < nrot; t++) {
@@ -380,7 +452,8 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         y0 = ym;
     }
     if (o.debug_stop == 0) return y0;
-    const double* mask = mask_coeffs(c, L);
+    // the factor's slots: [0, L), or [0, J L) on the packed ciphertext
+    const double* mask = mask_coeffs(c, mg ? Jg * L : L);
 
     Ct y = ct_copy(c, y0);      // y^(j-1)
     Ct big;                     // Lambda (version B), on slots [0, L) only
@@ -440,6 +513,11 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
             op_add_inplace(c, S, rr);
             ct_free(c, rr);
         }
+        if (mg) {
+            Ct Sp = pack_jobs(c, S, L, Jg);
+            ct_free(c, S);
+            S = Sp;
+        }
         // budget of the normalisation polynomial (mask folded into its leaves,
         // or into the last Newton step): lambda lands cheb_depth (+ 1 when
         // the affine map takes a level) + 2 nsteps below S; the cube and
@@ -448,7 +526,11 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // bootstrapping restores, Newton's first guess P(S) is bootstrapped
         // itself before the steps (S then needs the polynomial's depth and,
         // one level above the guess, the steps' levels)
-        const int keep = (tp != 2 || nsteps) ? 2 + tl : 1;
+        // The last step's z = lambda y and z^2 take two of lambda's levels
+        // (earlier steps of Algorithm SM bootstrap lambda when it is short;
+        // version B's Lambda product takes one); packed jobs: one more for
+        // taking the factor apart before the normalize-and-square step.
+        const int keep = ((tp != 2 || nsteps) ? 2 + tl : (last ? 1 + tl : 1)) + (mg && !smb_step ? 1 : 0);
         const int need_full = cheb_depth(deg) + 2 * nsteps + keep;
         const bool refresh = nsteps > 0 && can_bootstrap(c) && need_full > c.prm.user_top;
         {
@@ -468,7 +550,7 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
         // bits of precision at n = 256: the wider interval spends the
         // approximation on values S never takes)
         double a, b;
-        if (last && tp == 2 && !nsteps && S.level >= cheb_depth(deg) + 3) {
+        if (last && tp == 2 && !nsteps && S.level >= cheb_depth(deg) + 3 + (mg ? 1 : 0)) {
             a = lo;
             b = hi;
         } else {
@@ -529,6 +611,11 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
                     lam = l2;
                 }
             }
+            if (mg) {
+                Ct lu = unpack_jobs(c, lam, J, L, Jg);
+                ct_free(c, lam);
+                lam = lu;
+            }
             broadcast(c, lam, L, nrot);
             Ct lj = per_job(c, lam, J, m);
             ct_free(c, lam);
@@ -563,20 +650,23 @@ Ct softmax(Context& c, const Ct& x, int n, double M, const SoftmaxOpts& o, Softm
                 big = nb;
             }
             // y^(j) = (Lambda y0)^(2^j) must keep r levels: 1 for the next
-            // S, 2 before the final normalize-and-square step
-            const int r = (j == k - 1) ? 2 : 1;
+            // S, 2 before the final normalize-and-square step (packed jobs:
+            // 2 always, the next S's packing taking one); packed, Lambda
+            // keeps one more for taking the jobs' factors apart
+            const int r = (j == k - 1 || mg) ? 2 : 1;
             const int want = j + 1 + r;
             HS_REQUIRE(y0.level >= want, E_LEVEL, "Softmax version B: main-thread level budget exhausted");
-            if (big.level < want) {
+            const int want_big = want + (mg ? 1 : 0);
+            if (big.level < want_big) {
                 bool rep;
-                Ct b2 = ensure_level(c, big, want, lam_bound_big(n, avg ? lam_bound * per : lam_bound), st, rep,
-                                     "Lambda", j, avg ? 0 : L);
+                Ct b2 = ensure_level(c, big, want_big, lam_bound_big(n, avg ? lam_bound * per : lam_bound), st,
+                                     rep, "Lambda", j, avg ? 0 : (mg ? Jg * L : L));
                 if (rep) {
                     ct_free(c, big);
                     big = b2;
                 }
             }
-            Ct bb = ct_copy(c, big);
+            Ct bb = mg ? unpack_jobs(c, big, J, L, Jg) : ct_copy(c, big);
             if (!avg) broadcast(c, bb, L, nrot);
             Ct bj = per_job(c, bb, J, m);
             ct_free(c, bb);

@@ -18,6 +18,7 @@ struct SoftmaxOpts {
     int newton_steps = 0;     // > 0: inverse roots by that many Newton steps from the polynomial
     int mask_mode = 0;        // 0: indicator of slots [0, L); 1: averaging (m / n on every slot)
     int approx = 0;           // normalisation polynomials: 0 weighted minimax, 1 Chebyshev interpolants
+    int merge = 0;            // jobs > 1, version B: one auxiliary ciphertext for every job
 };
 
 struct SoftmaxStats {

@@ -53,7 +53,7 @@ class hs_softmax_opts(ctypes.Structure):
         ("inv_degree_first", ctypes.c_int), ("inv_degree_mid", ctypes.c_int),
         ("inv_degree_last", ctypes.c_int), ("alpha", ctypes.c_double),
         ("power", ctypes.c_int), ("debug_stop", ctypes.c_int), ("newton_steps", ctypes.c_int),
-        ("mask_mode", ctypes.c_int), ("approx", ctypes.c_int),
+        ("mask_mode", ctypes.c_int), ("approx", ctypes.c_int), ("merge", ctypes.c_int),
     ]
 
 
@@ -578,16 +578,17 @@ class Context:
         return self._op("hs_dbg_bootstrap_stage", a.h, stage)
 
     def softmax(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), debug_stop=-1, jobs=1,
-                power=0, newton_steps=0, mask_mode=0, approx=0):
+                power=0, newton_steps=0, mask_mode=0, approx=0, merge=0):
         """hs_softmax (jobs = 1) or hs_softmax_jobs over the packed ciphertexts
-        `cts` (jobs consecutive groups of len(cts) / jobs); returns new handles."""
+        `cts` (jobs consecutive groups of len(cts) / jobs); returns new handles.
+        merge = 1: the jobs share one auxiliary ciphertext (version B)."""
         m = len(cts)
         arr = (_vp * m)(*[c.h for c in cts])
         out = (_vp * m)()
         o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
                             inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
                             power=power, debug_stop=debug_stop, newton_steps=newton_steps, mask_mode=mask_mode,
-                            approx=approx)
+                            approx=approx, merge=merge)
         if jobs == 1:
             _check(lib().hs_softmax(self.h, arr, m, n, M, ctypes.byref(o), out))
         else:
@@ -595,7 +596,7 @@ class Context:
         return [Ciphertext(self, _vp(out[i])) for i in range(m)]
 
     def softmax_plan(self, cts, n, M, variant=0, k=0, exp_degree=0, inv_degrees=(0, 0, 0), jobs=1, power=0,
-                     newton_steps=0, mask_mode=0, approx=0):
+                     newton_steps=0, mask_mode=0, approx=0, merge=0):
         """hs_softmax_plan_create: capture the schedule of softmax(cts, ...)
         once (after one eager warm-up run on `cts`) for replays on new inputs
         of the same shape, level and scale."""
@@ -604,7 +605,7 @@ class Context:
         o = hs_softmax_opts(variant=variant, k=k, exp_degree=exp_degree, inv_degree_first=inv_degrees[0],
                             inv_degree_mid=inv_degrees[1], inv_degree_last=inv_degrees[2], alpha=0.0,
                             power=power, debug_stop=-1, newton_steps=newton_steps, mask_mode=mask_mode,
-                            approx=approx)
+                            approx=approx, merge=merge)
         h = _vp()
         _check(lib().hs_softmax_plan_create(self.h, arr, m, jobs, n, M, ctypes.byref(o), ctypes.byref(h)))
         return SoftmaxPlan(self, h, m)

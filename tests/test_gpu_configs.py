@@ -160,3 +160,36 @@ def test_large_dimensions(ctx, n):
         bb = S.precision_bits(S.softmax(x), yb)
         print("n=%d version B: %s, stats %s" % (n, bb, ctx.softmax_stats()))
         assert bb["worst"] >= 16.0, bb
+
+
+@pytest.mark.parametrize("case", [("fgb16_smb64", 256, 128.0, 16, 4), ("fgb16_uneven", 128, 64.0, 16, 8)],
+                         ids=["dim256-J4", "layer-J8"])
+def test_packed_jobs_at_full_size(ctx, case):
+    # version B with the jobs' auxiliary ciphertexts packed (merge = 1): n / m
+    # jobs' sums in one auxiliary ciphertext; every job >= 16 bits against
+    # its own FP64 Softmax, rows summing to 1, and job 0 within 2^-16 of the
+    # same batch run alone (equal to the precision: the shared bootstraps
+    # add their own noise)
+    from paper_2410_11184_amd.softmax import encrypt_logits, decrypt_outputs
+    name, n, M, m, J = case
+    L = m * ctx.slots // n
+    if name == "fgb16_uneven":
+        xs = [synthetic.group_logits(name, 0, j) for j in range(J)]      # the layer jobs' own logits
+    else:
+        xs = [synthetic.workload_logits(name, L=L, seed=9100 + j) for j in range(J)]
+    assert all(x.shape == (L, n) for x in xs)
+    cts = [c for j, x in enumerate(xs) for c in encrypt_logits(ctx, x, M, seed=9200 + j)]
+    print("packed jobs: %d x %d ciphertexts, n=%d, M=%g" % (J, m, n, M), flush=True)
+    out = ctx.softmax(cts, n, M, variant=1, jobs=J, merge=1)
+    st = ctx.softmax_stats()
+    alone = decrypt_outputs(ctx, ctx.softmax(cts[:m], n, M, variant=1), n)
+    for j in range(J):
+        y = decrypt_outputs(ctx, out[j * m:(j + 1) * m], n)
+        bits = S.precision_bits(S.softmax(xs[j]), y)
+        print("job %d: %s" % (j, bits))
+        assert bits["worst"] >= 16.0, (j, bits)
+        assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2 ** -12
+        if j == 0:
+            d = float(np.max(np.abs(y - alone)))
+            print("job 0 against alone: 2^%.2f, stats %s" % (np.log2(d + 1e-300), st))
+            assert d < 2 ** -16

@@ -157,3 +157,50 @@ def test_interpolated_normalisation_matches_oracle(pair, variant):
     _compare(g, o, gy, oy, "output")
     y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy]), n)
     assert S.precision_bits(S.softmax(x), y)["worst"] >= 16.0
+
+
+@pytest.mark.parametrize("case", [(16, 4.0, 2, 2, (31, 31, 31), 13.5), (16, 8.0, 2, 2, (7, 7, 15), 7.0),
+                                  (16, 8.0, 1, 4, (7, 7, 15), 7.0), (16, 8.0, 4, 8, (7, 7, 15), 7.0)],
+                         ids=["k1-m2-J2", "k2-m2-J2", "k2-m1-J4", "k2-m4-J8-two-packed"])
+def test_packed_jobs_match_oracle(pair, case):
+    # version B with the jobs' auxiliary ciphertexts packed (hs_softmax_jobs,
+    # merge = 1; n / m jobs per auxiliary ciphertext, so 8 jobs of m = 4 take
+    # two) against the oracle's packed schedule, word for word; k = 2 takes
+    # the packed Lambda through a version-B step (the
+    # toy ring's 23 levels hold it only with low degrees, so the precision
+    # bar is that of these degrees); each job's logits differ
+    from oracle import schedule, softmax as S
+    g, o = pair
+    n, M, m, J, dinv, want_bits = case
+    xs, gxs, oxs = [], [], []
+    for jb in range(J):
+        x, gx, ox = _inputs(g, o, n, M, m, seed=800 + 10 * jb + m)
+        xs.append(x)
+        gxs += gx
+        oxs += ox
+    kw = dict(variant=1, exp_degree=7, inv_degrees=dinv)
+    gy = g.softmax(gxs, n, M, jobs=J, merge=1, **kw)
+    oy = schedule.softmax(o, oxs, n, M, jobs=J, merge=True, **kw)
+    _compare(g, o, gy, oy, "output")
+    for jb in range(J):
+        y = S.unpack(np.stack([o.decrypt_decode(c).real for c in oy[jb * m:(jb + 1) * m]]), n)
+        bits = S.precision_bits(S.softmax(xs[jb]), y)
+        print(case, jb, bits)
+        assert bits["worst"] >= want_bits, (jb, bits)
+
+
+def test_packed_jobs_refusals(pair):
+    from paper_2410_11184_amd import hs
+    g, o = pair
+    n, M, m = 16, 8.0, 2
+    _, gx, _ = _inputs(g, o, n, M, m, seed=890)
+    for kw in (dict(variant=0), dict(variant=1, mask_mode=1), dict(variant=1, newton_steps=1)):
+        with pytest.raises(hs.HSError) as e:
+            g.softmax(gx, n, M, jobs=2, merge=1, exp_degree=7, inv_degrees=(7, 7, 15), **kw)
+        assert e.value.name == "HS_E_PARAM", kw
+    # more jobs than blocks of L slots and not a multiple of them: n / m = 8
+    # blocks, 12 jobs of m = 2
+    cts = [gx[i % m] for i in range(24)]
+    with pytest.raises(hs.HSError) as e:
+        g.softmax(cts, n, M, jobs=12, merge=1, variant=1, exp_degree=7, inv_degrees=(7, 7, 15))
+    assert e.value.name == "HS_E_PARAM"

@@ -291,3 +291,38 @@ def test_weighted_minimax_equioscillates_and_beats_interpolation():
         ci = P.cheb_interp(lambda x: x ** -e, a, b, d)
         ei = np.max(np.abs(P.cheb_eval(ci, g, a, b) * g ** e - 1))
         assert emax < ei, (d, e, emax, ei)
+
+
+def test_packed_jobs_schedule_on_toy_ring():
+    # Version B with the jobs' auxiliary ciphertexts packed into one (Section
+    # 4.2's single auxiliary ciphertext, across two jobs): each job's
+    # decrypted output is the FP64 Softmax of its own logits to the bits its
+    # degree-31 polynomial reaches at k = 1 (the toy ring has no bootstrap,
+    # and the packing takes two levels per iteration), rows summing to 1, and
+    # agrees with the job run alone (its own auxiliary ciphertext) far below
+    # that; the jobs' logits differ, so a packing that mixed them up would
+    # fail both checks
+    import synthetic
+    from oracle import ckks, schedule
+    p = synthetic.preset("toy12")
+    o = ckks.Context(**p)
+    o.keygen(97)
+    n, M, m, J = 16, 4.0, 2, 2
+    L = m * o.slots // n
+    xs, cts = [], []
+    for jb in range(J):
+        x = synthetic.logits_uniform(L, n, M, seed=140 + jb)
+        xs.append(x)
+        packed = S.pack(x, m, o.slots)
+        cts += [o.encode_encrypt(packed[i], o.delta * 2.0 / M, p["user_top"], 60 + jb * m + i) for i in range(m)]
+    kw = dict(variant=1, exp_degree=7, inv_degrees=(31, 31, 31))
+    ys = schedule.softmax(o, cts, n, M, jobs=J, merge=True, **kw)
+    assert len(ys) == J * m
+    for jb in range(J):
+        y = S.unpack(np.stack([o.decrypt_decode(c).real for c in ys[jb * m:(jb + 1) * m]]), n)
+        bits = S.precision_bits(S.softmax(xs[jb]), y)
+        assert bits["worst"] >= 14.0, (jb, bits)
+        assert np.max(np.abs(y.sum(axis=1) - 1.0)) < 2.0 ** -12
+        alone = schedule.softmax(o, cts[jb * m:(jb + 1) * m], n, M, **kw)
+        ya = S.unpack(np.stack([o.decrypt_decode(c).real for c in alone]), n)
+        assert np.max(np.abs(y - ya)) < 2.0 ** -22, jb
