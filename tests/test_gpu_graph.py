@@ -79,6 +79,14 @@ def test_bootstrapping_plan_replays_match_eager(boot, variant):
     print("boot10u variant", variant, "nodes", nodes)
 
 
+def test_packed_jobs_plan_replays_match_eager(boot):
+    # two version-B jobs with their auxiliary ciphertexts packed into one,
+    # bootstrapped inside the captured schedule
+    _, _, nodes = _replays(boot, 16, 8.0, 2, 2, 1, dict(merge=1), [940, 941, 942])
+    assert boot.softmax_stats()["bootstraps"] > 0
+    print("boot10u packed jobs, nodes", nodes)
+
+
 def test_plan_rejects_other_shapes(toy):
     from paper_2410_11184_amd import hs
     from paper_2410_11184_amd.softmax import encrypt_logits
