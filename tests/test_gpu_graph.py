@@ -81,8 +81,10 @@ def test_bootstrapping_plan_replays_match_eager(boot, variant):
 
 def test_packed_jobs_plan_replays_match_eager(boot):
     # two version-B jobs with their auxiliary ciphertexts packed into one,
-    # bootstrapped inside the captured schedule
-    _, _, nodes = _replays(boot, 16, 8.0, 2, 2, 1, dict(merge=1), [940, 941, 942])
+    # bootstrapped inside the captured schedule (degrees 15 / 15 / 31: the
+    # packing's extra level in the last step leaves the default degree-127
+    # polynomial more levels than the ring's 10 user levels)
+    _, _, nodes = _replays(boot, 16, 8.0, 2, 2, 1, dict(merge=1, **TOY), [940, 941, 942])
     assert boot.softmax_stats()["bootstraps"] > 0
     print("boot10u packed jobs, nodes", nodes)
 
